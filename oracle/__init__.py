@@ -1,0 +1,322 @@
+"""CPU FP64 oracle of the IREBM step -- TEST INFRASTRUCTURE ONLY.
+
+This package is the plain, slow, obviously correct statement of what the
+GPU path computes: the implicit regularized enthalpy lattice Boltzmann
+step of Luddens, Lothode and Danaila (arXiv 2505.13097), Algorithm 3
+(Section 4.1), with the boundary closures of Section 4.2, the Neumann
+similarity solution of Section 2 and a reverse mode of the step.
+
+Only the tests, the smoke check and the CPU-baseline leg of the bench may
+import it.  It shares no code with the GPU library: the C sources in this
+directory are compiled with gcc into ``liboracle.so`` and called through
+ctypes below.  The state is the distribution functions f[i][y][x].
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCES = ("irebm.c", "irebm_cs.c")
+
+DIRICHLET, BOUNCEBACK, PERIODIC = 0, 1, 2
+SAFEGUARDED, PLAIN = 0, 1
+FRONT_INTEGRAL, FRONT_CROSSING = 0, 1
+_BC = {"dirichlet": DIRICHLET, "bounceback": BOUNCEBACK, "periodic": PERIODIC}
+_NEWTON = {"safeguarded": SAFEGUARDED, "plain": PLAIN}
+
+
+def build():
+    """Compile liboracle.so with gcc (plain -O2, single thread)."""
+    srcs = [os.path.join(_HERE, s) for s in SOURCES]
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o",
+           LIB_PATH + ".tmp"] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("q", ctypes.c_int),
+        ("nx", ctypes.c_long), ("ny", ctypes.c_long),
+        ("tau", ctypes.c_double), ("ste", ctypes.c_double),
+        ("tm", ctypes.c_double), ("delta", ctypes.c_double),
+        ("bc", ctypes.c_int * 4), ("wall_T", ctypes.c_double * 4),
+        ("wall_profile", ctypes.POINTER(ctypes.c_double) * 4),
+        ("tol", ctypes.c_double), ("max_it", ctypes.c_int),
+        ("newton_mode", ctypes.c_int), ("dx", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("max_it", ctypes.c_int), ("nonconverged", ctypes.c_long),
+        ("bisections", ctypes.c_long), ("max_residual", ctypes.c_double),
+        ("flux_in", ctypes.c_double), ("flux_out", ctypes.c_double),
+        ("it_hist", ctypes.c_long * 33),
+    ]
+
+    def as_dict(self):
+        return {
+            "max_it": self.max_it, "nonconverged": self.nonconverged,
+            "bisections": self.bisections, "max_residual": self.max_residual,
+            "flux_in": self.flux_in, "flux_out": self.flux_out,
+            "it_hist": list(self.it_hist),
+        }
+
+
+_lib_handle = None
+
+
+def lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        P = ctypes.POINTER(Params)
+        S = ctypes.POINTER(Stats)
+        sig = {
+            "orc_lattice": [ctypes.c_int, ctypes.c_int, ip, ip, dp, ip],
+            "orc_newton": [ctypes.c_double] * 6 + [ctypes.c_int, ctypes.c_int,
+                                                   dp, ip, ip],
+            "orc_init": [P, dp, dp],
+            "orc_step": [P, dp, dp, S],
+            "orc_run": [P, dp, ctypes.c_long, S, dp, dp],
+            "orc_temperature": [P, dp, dp],
+            "orc_energy": [P, dp, dp],
+            "orc_front": [P, dp, ctypes.c_int, dp],
+            "orc_stefan_lambda": [ctypes.c_double, ctypes.c_double, dp],
+            "orc_front_loss": [P, dp, ctypes.c_long, dp, dp],
+            "orc_front_loss_grad": [P, dp, ctypes.c_long, dp, dp, dp, dp, dp],
+            "orc_adjoint_step": [P, dp, dp, dp, dp, dp, dp],
+            "orc_cs_step": [P, dp, dp, ctypes.c_double, ctypes.c_double, dp,
+                            dp, dp],
+            "orc_cs_front_loss": [P, dp, ctypes.c_long, dp, ctypes.c_double,
+                                  ctypes.c_double, dp, dp, dp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        for name in ("orc_phi", "orc_dphi"):
+            fn = getattr(L, name)
+            fn.argtypes = [ctypes.c_double] * 3
+            fn.restype = ctypes.c_double
+        L.orc_neumann_T.argtypes = [ctypes.c_double] * 4
+        L.orc_neumann_T.restype = ctypes.c_double
+        _lib_handle = L
+    return _lib_handle
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Setup:
+    """orc_params built from a problem description (synth.Problem or any
+    object with the same attributes); keeps wall profiles alive."""
+
+    def __init__(self, prob):
+        p = Params()
+        p.dim, p.q = prob.dim, prob.q
+        p.nx, p.ny = prob.nx, prob.ny
+        p.tau, p.ste, p.tm, p.delta = prob.tau, prob.ste, prob.tm, prob.delta
+        self._keep = []
+        for k in range(4):
+            b = prob.bc[k]
+            p.bc[k] = _BC[b] if isinstance(b, str) else int(b)
+            p.wall_T[k] = prob.wall_T[k]
+            prof = prob.wall_profile[k] if prob.wall_profile else None
+            if prof is not None:
+                arr = _f64(prof)
+                self._keep.append(arr)
+                p.wall_profile[k] = _dp(arr)
+        p.tol, p.max_it = prob.tol, prob.max_it
+        nm = prob.newton_mode
+        p.newton_mode = _NEWTON[nm] if isinstance(nm, str) else int(nm)
+        p.dx = prob.dx
+        self.p = p
+        self.q, self.nx, self.ny = prob.q, prob.nx, prob.ny
+
+    @property
+    def shape(self):
+        return (self.q, self.ny, self.nx)
+
+    def ref(self):
+        return ctypes.byref(self.p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle: {what} rejected its arguments (rc={rc})")
+
+
+def lattice(dim, q):
+    ex = (ctypes.c_int * q)()
+    ey = (ctypes.c_int * q)()
+    w = (ctypes.c_double * q)()
+    opp = (ctypes.c_int * q)()
+    _check(lib().orc_lattice(dim, q, ex, ey, w, opp), "orc_lattice")
+    return (np.array(ex[:]), np.array(ey[:]), np.array(w[:]),
+            np.array(opp[:]))
+
+
+def phi(theta, tm, delta):
+    return lib().orc_phi(theta, tm, delta)
+
+
+def dphi(theta, tm, delta):
+    return lib().orc_dphi(theta, tm, delta)
+
+
+def newton(m0, theta, ste, tm, delta, tol=1e-12, max_it=20,
+           mode=SAFEGUARDED):
+    out = ctypes.c_double()
+    it = ctypes.c_int()
+    conv = ctypes.c_int()
+    _check(lib().orc_newton(m0, theta, ste, tm, delta, tol, max_it, mode,
+                            ctypes.byref(out), ctypes.byref(it),
+                            ctypes.byref(conv)), "orc_newton")
+    return out.value, it.value, bool(conv.value)
+
+
+def init(prob, T0=None):
+    s = Setup(prob)
+    f = np.zeros(s.shape)
+    T0a = None if T0 is None else _f64(np.broadcast_to(T0, (s.ny, s.nx)))
+    _check(lib().orc_init(s.ref(), _dp(T0a), _dp(f)), "orc_init")
+    return f
+
+
+def step(prob, f):
+    s = Setup(prob)
+    f = _f64(f)
+    out = np.empty_like(f)
+    st = Stats()
+    _check(lib().orc_step(s.ref(), _dp(f), _dp(out), ctypes.byref(st)),
+           "orc_step")
+    return out, st.as_dict()
+
+
+def run(prob, f, nsteps, trace=False):
+    """Advance nsteps; returns (f, stats[, energy_trace, flux_trace])."""
+    s = Setup(prob)
+    f = np.array(f, dtype=np.float64, copy=True, order="C")
+    st = Stats()
+    et = np.empty(nsteps + 1) if trace else None
+    ft = np.empty((nsteps, 2)) if trace else None
+    _check(lib().orc_run(s.ref(), _dp(f), nsteps, ctypes.byref(st), _dp(et),
+                         _dp(ft)), "orc_run")
+    if trace:
+        return f, st.as_dict(), et, ft
+    return f, st.as_dict()
+
+
+def temperature(prob, f):
+    s = Setup(prob)
+    T = np.empty((s.ny, s.nx))
+    _check(lib().orc_temperature(s.ref(), _dp(_f64(f)), _dp(T)),
+           "orc_temperature")
+    return T
+
+
+def energy(prob, f):
+    s = Setup(prob)
+    E = ctypes.c_double()
+    _check(lib().orc_energy(s.ref(), _dp(_f64(f)), ctypes.byref(E)),
+           "orc_energy")
+    return E.value
+
+
+def front(prob, f, mode=FRONT_INTEGRAL):
+    s = Setup(prob)
+    xf = np.empty(s.ny)
+    _check(lib().orc_front(s.ref(), _dp(_f64(f)), mode, _dp(xf)), "orc_front")
+    return xf
+
+
+def stefan_lambda(ste, theta0):
+    lam = ctypes.c_double()
+    _check(lib().orc_stefan_lambda(ste, theta0, ctypes.byref(lam)),
+           "orc_stefan_lambda")
+    return lam.value
+
+
+def neumann_T(x, t, lam, theta0):
+    x = np.asarray(x, dtype=np.float64)
+    fn = lib().orc_neumann_T
+    return np.vectorize(lambda xx: fn(float(xx), t, lam, theta0))(x)
+
+
+def front_loss(prob, T0, nsteps, target):
+    s = Setup(prob)
+    T0a = None if T0 is None else _f64(np.broadcast_to(T0, (s.ny, s.nx)))
+    L = ctypes.c_double()
+    _check(lib().orc_front_loss(s.ref(), _dp(T0a), nsteps,
+                                _dp(_f64(target)), ctypes.byref(L)),
+           "orc_front_loss")
+    return L.value
+
+
+def front_loss_grad(prob, T0, nsteps, target):
+    """Returns (loss, dL/dT_wall (x- wall, per row), dL/dSte, dL/ddelta)."""
+    s = Setup(prob)
+    T0a = None if T0 is None else _f64(np.broadcast_to(T0, (s.ny, s.nx)))
+    L = ctypes.c_double()
+    gw = np.zeros(s.ny)
+    gs = ctypes.c_double()
+    gd = ctypes.c_double()
+    _check(lib().orc_front_loss_grad(s.ref(), _dp(T0a), nsteps,
+                                     _dp(_f64(target)), ctypes.byref(L),
+                                     _dp(gw), ctypes.byref(gs),
+                                     ctypes.byref(gd)), "orc_front_loss_grad")
+    return L.value, gw, gs.value, gd.value
+
+
+def adjoint_step(prob, f, gbar):
+    """Returns (fbar, dL/dT_wall contribution, dSte, ddelta) of one step."""
+    s = Setup(prob)
+    fb = np.empty(s.shape)
+    gw = np.zeros(s.ny)
+    gs = ctypes.c_double(0.0)
+    gd = ctypes.c_double(0.0)
+    _check(lib().orc_adjoint_step(s.ref(), _dp(_f64(f)), _dp(_f64(gbar)),
+                                  _dp(fb), _dp(gw), ctypes.byref(gs),
+                                  ctypes.byref(gd)), "orc_adjoint_step")
+    return fb, gw, gs.value, gd.value
+
+
+def cs_step(prob, f, f_im=None, ste_im=0.0, delta_im=0.0, wall_im=None):
+    s = Setup(prob)
+    ore = np.empty(s.shape)
+    oim = np.empty(s.shape)
+    _check(lib().orc_cs_step(s.ref(), _dp(_f64(f)),
+                             _dp(None if f_im is None else _f64(f_im)),
+                             ste_im, delta_im,
+                             _dp(None if wall_im is None else _f64(wall_im)),
+                             _dp(ore), _dp(oim)), "orc_cs_step")
+    return ore, oim
+
+
+def cs_front_loss(prob, T0, nsteps, target, ste_im=0.0, delta_im=0.0,
+                  wall_im=None):
+    s = Setup(prob)
+    T0a = None if T0 is None else _f64(np.broadcast_to(T0, (s.ny, s.nx)))
+    lr = ctypes.c_double()
+    li = ctypes.c_double()
+    _check(lib().orc_cs_front_loss(
+        s.ref(), _dp(T0a), nsteps, _dp(_f64(target)), ste_im, delta_im,
+        _dp(None if wall_im is None else _f64(wall_im)), ctypes.byref(lr),
+        ctypes.byref(li)), "orc_cs_front_loss")
+    return lr.value, li.value

@@ -1,0 +1,114 @@
+/*
+ * oracle.h -- CPU FP64 oracle for the implicit regularized enthalpy
+ * lattice Boltzmann method (IREBM) of Luddens, Lothode and Danaila,
+ * "An implicit regularized enthalpy Lattice Boltzmann Method for the
+ * Stefan problem" (arXiv 2505.13097).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct statement of what the GPU path computes.  It shares no code,
+ * header, table or helper with the GPU library, and it is only called by
+ * the tests, by the smoke check and by the CPU-baseline leg of the bench.
+ *
+ * State layout: distribution functions f[i][y][x] (plane i of q planes,
+ * row-major, nx fastest), double precision.  1D lattices use ny = 1.
+ *
+ * Every function returns 0 on success and -1 on an invalid argument.
+ */
+#ifndef IREBM_ORACLE_H
+#define IREBM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_DIRICHLET = 0, ORC_BOUNCEBACK = 1, ORC_PERIODIC = 2 };
+enum { ORC_SAFEGUARDED = 0, ORC_PLAIN = 1 };
+enum { ORC_FRONT_INTEGRAL = 0, ORC_FRONT_CROSSING = 1 };
+
+typedef struct {
+  int dim;              /* 1 or 2 */
+  int q;                /* 3 (D1Q3), 5 (D2Q5) or 9 (D2Q9) */
+  long nx, ny;          /* node counts; ny = 1 in 1D */
+  double tau;           /* BGK relaxation time */
+  double ste;           /* Stefan number */
+  double tm;            /* melting temperature (0 in the scaled problem) */
+  double delta;         /* regularization width, temperature units */
+  int bc[4];            /* walls x-, x+, y-, y+ */
+  double wall_T[4];     /* Dirichlet temperature per wall */
+  const double *wall_profile[4]; /* optional per-node wall temperatures
+                                    (length ny for x walls, nx for y walls) */
+  double tol;           /* Newton stopping tolerance on |theta_{k+1}-theta_k| */
+  int max_it;           /* Newton iteration cap */
+  int newton_mode;      /* ORC_SAFEGUARDED or ORC_PLAIN */
+  double dx;            /* lattice spacing, used by the front position */
+} orc_params;
+
+typedef struct {
+  int max_it;           /* largest Newton iteration count seen */
+  long nonconverged;    /* node-steps that reached the cap */
+  long bisections;      /* safeguard bisections taken */
+  double max_residual;  /* largest |F(theta_new)| */
+  double flux_in;       /* sum of populations set by boundary closures */
+  double flux_out;      /* sum of post-collision populations leaving */
+  long it_hist[33];     /* iteration histogram, last bin counts >= 32 */
+} orc_stats;
+
+/* lattice tables: velocities, weights, opposite directions */
+int orc_lattice(int dim, int q, int *ex, int *ey, double *w, int *opp);
+
+/* regularized liquid fraction and its derivative */
+double orc_phi(double theta, double tm, double delta);
+double orc_dphi(double theta, double tm, double delta);
+
+/* the local scalar problem of one node: returns the new temperature */
+int orc_newton(double m0, double theta, double ste, double tm, double delta,
+               double tol, int max_it, int mode, double *theta_new,
+               int *iters, int *converged);
+
+int orc_init(const orc_params *p, const double *T0, double *f);
+int orc_step(const orc_params *p, const double *f, double *fout,
+             orc_stats *st);
+int orc_run(const orc_params *p, double *f, long nsteps, orc_stats *st,
+            double *energy_trace, double *flux_trace);
+int orc_temperature(const orc_params *p, const double *f, double *T);
+int orc_energy(const orc_params *p, const double *f, double *E);
+int orc_front(const orc_params *p, const double *f, int mode, double *xf);
+
+/* Neumann similarity solution of the two-phase Stefan problem */
+int orc_stefan_lambda(double ste, double theta0, double *lambda);
+double orc_neumann_T(double x, double t, double lambda, double theta0);
+
+/* front misfit loss L = 1/2 sum_y (xf(y) - target(y))^2 after nsteps,
+   starting from the equilibrium state of T0 */
+int orc_front_loss(const orc_params *p, const double *T0, long nsteps,
+                   const double *target, double *loss);
+
+/* reverse mode of orc_front_loss: gradients with respect to the x- wall
+   temperature profile (length ny), Ste and delta */
+int orc_front_loss_grad(const orc_params *p, const double *T0, long nsteps,
+                        const double *target, double *loss,
+                        double *g_wall, double *g_ste, double *g_delta);
+
+/* reverse mode of one step at state f: fbar = (df'/df)^T gbar, and the
+   matching additions to the parameter gradients */
+int orc_adjoint_step(const orc_params *p, const double *f,
+                     const double *gbar, double *fbar, double *g_wall,
+                     double *g_ste, double *g_delta);
+
+/* complex-step evaluation of one step at f + i f_im with perturbed
+   parameters (tangent of the step: Im(out)/h) */
+int orc_cs_step(const orc_params *p, const double *f_re, const double *f_im,
+                double ste_im, double delta_im, const double *wall_im,
+                double *out_re, double *out_im);
+
+/* complex-step evaluation of orc_front_loss: perturbs Ste, delta and the
+   x- wall profile by i*(imaginary parts) and returns Re and Im of L */
+int orc_cs_front_loss(const orc_params *p, const double *T0, long nsteps,
+                      const double *target, double ste_im, double delta_im,
+                      const double *wall_im, double *loss_re,
+                      double *loss_im);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
