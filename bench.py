@@ -1,0 +1,180 @@
+"""Benchmark of the IREBM step on one MI355X.
+
+A step is one IREBM time step (collision, pull streaming, boundary
+closures, local Newton solve, source and update, per-tile Newton and flux
+statistics) over the whole lattice: one kernel launch.  Inputs are
+resident in HBM before the timed region.
+
+Default workload: the 8192 x 8192 D2Q9 cavity (FP32 populations, FP64
+per-node arithmetic), heated at x = 0, adiabatic y walls, Ste drawn from
+the seed, delta = 1.5 cells, tau = 0.6, Newton tol 1e-12.
+
+Prints one JSON line.  Roofline: algorithmic bytes per launch
+(2 q sizeof(population) per node: each population read once and written
+once) over the average launch time measured with HIP events on the stream
+the kernels run on.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "MLUPS and HBM GB/s (% roofline), plain vs batched vs adjoint, fixed tol"
+
+
+def workload(name):
+    import synth
+    if name == "cavity":
+        return synth.cavity_2d()
+    if name == "planar":
+        return synth.planar_2d()
+    if name == "stefan1d":
+        return synth.stefan_1d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def bytes_per_node(prob):
+    s = 8 if prob.storage == "f64" else 4
+    return 2 * prob.q * s
+
+
+def time_plain(prob, steps, warmup, variant=-1):
+    import torch
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob, variant=variant)
+    stream = torch.cuda.current_stream()
+    g.step(warmup)
+    g.reset_stats()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    g.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gpu_ms = ev0.elapsed_time(ev1)
+    st = g.stats()
+    front = g.front("integral")
+    g.close()
+    return {"wall_s": t1 - t0, "gpu_ms": gpu_ms, "stats": st,
+            "front_mean": float(front.mean())}
+
+
+def cpu_baseline(prob, steps=1):
+    """The oracle, as it stands, on `steps` steps of the same lattice from
+    the same initial state (single thread)."""
+    import oracle as O
+    f = O.init(prob, prob.T0)
+    t0 = time.perf_counter()
+    O.run(prob, f, steps)
+    dt = time.perf_counter() - t0
+    return {"value": prob.nodes * steps / dt / 1e6, "unit": "MLUPS",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{steps} step(s) of the full {prob.nx}x{prob.ny} "
+                      f"{prob.name} lattice from its initial state, "
+                      f"single-threaded C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cavity",
+                    choices=["cavity", "planar", "stefan1d"])
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "--gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth  # noqa: F401
+    from paper_2505_13097_amd import variant_names
+    torch.cuda.set_device(0)
+
+    prob = workload(args.workload)
+    print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D2Q{prob.q} "
+          f"steps {args.steps} warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+    r = time_plain(prob, args.steps, args.warmup, args.variant)
+    print(f"[bench] timed region done: {r['gpu_ms']:.1f} ms", file=sys.stderr,
+          flush=True)
+    ms_per_step = r["wall_s"] * 1e3 / args.steps
+    mlups = prob.nodes * args.steps / r["wall_s"] / 1e6
+    launch_ms = r["gpu_ms"] / args.steps
+    bpn = bytes_per_node(prob)
+    achieved = prob.nodes * bpn / (launch_ms * 1e-3) / 1e9
+    from paper_2505_13097_amd.stefan import make_params  # noqa: F401
+    vname = variant_names(prob.q, prob.storage)[
+        args.variant if args.variant >= 0 else (0 if prob.q == 3 else 3)]
+
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": prob.name,
+            "lattice": f"D{prob.dim}Q{prob.q}",
+            "nx": prob.nx, "ny": prob.ny,
+            "storage": prob.storage,
+            "tau": prob.tau, "ste": round(prob.ste, 6),
+            "delta_cells": round(prob.delta / prob.dx, 4),
+            "newton_tol": prob.tol, "newton_max_it": prob.max_it,
+            "bc": list(prob.bc),
+            "kernel_variant": vname,
+        },
+        "hbm_gbps_algorithmic": round(achieved, 1),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": None,
+            "kernel": "step_kernel",
+            "bytes_per_node": bpn,
+            "avg_launch_us": round(launch_ms * 1e3, 2),
+        },
+        "newton": {
+            "max_it": r["stats"]["max_newton_it"],
+            "nonconverged": r["stats"]["nonconverged"],
+            "max_residual": r["stats"]["max_residual"],
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, 1 if prob.nodes > 1e6 else 200)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * lbm_stefan.h -- C ABI of the MI355X (gfx950) implementation of the
+ * implicit regularized enthalpy lattice Boltzmann method (IREBM) for the
+ * two-phase Stefan problem (Luddens, Lothode, Danaila, arXiv 2505.13097).
+ *
+ * One time step is Algorithm 3 of Section 4.1: BGK collision of the
+ * thermal populations with equilibrium w_i T, pull streaming, the zeroth
+ * moment, a local Newton solve of
+ *     T~ = M0(q) + (phi(T) - phi(T~)) / Ste,
+ *     phi(T) = (1 + tanh((T - T_m)/delta)) / 2        (Section 4.1)
+ * for the new temperature, the source term (w_i/Ste)(phi(T) - phi(T~))
+ * and the update, with the boundary closures on the pulled populations of
+ * Section 4.2 (Dirichlet, bounce-back) or periodic axes.
+ *
+ * Conventions
+ *   - All entry points return LBM_STEFAN_OK (0) or a negative error code;
+ *     the text of the last error of a handle is lbm_stefan_last_error(h)
+ *     (lbm_stefan_last_error(NULL) for errors raised before a handle
+ *     exists).  No entry point aborts the process.
+ *   - "host" pointers are ordinary CPU memory and are only read or written
+ *     during the call.  "device" pointers are GPU memory of the device that
+ *     was current when the handle was created.
+ *   - Lattices: D1Q3 (dim 1), D2Q5 and D2Q9 (dim 2).  Velocity order: rest,
+ *     +x, +y, -x, -y, then (+1,+1), (-1,+1), (-1,-1), (+1,-1); weights
+ *     D1Q3 (2/3, 1/6, 1/6), D2Q5 (1/3, 1/6 x4), D2Q9 (4/9, 1/9 x4,
+ *     1/36 x4): the "standard weights" of Section 3.2, whose second moment
+ *     is T/3 times the identity as the Chapman-Enskog analysis requires.
+ *   - The state is the set of post-collision populations
+ *     Omega_i = (1 - 1/tau) f_i + (w_i/tau) T  (eq. def_qi_omegai) at the
+ *     current time, stored as q planes [q][ny][nx] (x fastest) in the
+ *     storage type (double or float).  T = sum_i Omega_i = sum_i f_i.
+ *     Per-node arithmetic is always double precision.
+ *   - nx nodes span x in [0, 1] unless dx says otherwise; wall nodes are
+ *     lattice nodes ("wet" walls).
+ *   - A handle enqueues all GPU work on the stream it was created with and
+ *     is not thread-safe; use one handle per stream.  Calls that overlap on
+ *     one handle race.
+ */
+#ifndef LBM_STEFAN_H
+#define LBM_STEFAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define LBM_STEFAN_OK 0
+#define LBM_STEFAN_EINVAL (-1)   /* invalid argument (see each call) */
+#define LBM_STEFAN_EDEVICE (-2)  /* a HIP runtime error; text in last_error */
+#define LBM_STEFAN_ENOTCONV (-3) /* strict mode: a Newton solve hit the cap */
+#define LBM_STEFAN_ENAN (-4)     /* a reduction found NaN or Inf */
+
+/* boundary kind of a wall (Section 4.2) */
+#define LBM_BC_DIRICHLET 0   /* eq. Dir_on_q: fixes the wall temperature */
+#define LBM_BC_BOUNCEBACK 1  /* q_i = q_opp(i): homogeneous Neumann */
+#define LBM_BC_PERIODIC 2    /* both walls of the axis must be periodic */
+
+/* population storage */
+#define LBM_STORE_F64 0
+#define LBM_STORE_F32 1
+
+/* Newton variant */
+#define LBM_NEWTON_SAFEGUARDED 0 /* Newton step kept inside a bisection
+                                    safeguard (rtsafe rule), default */
+#define LBM_NEWTON_PLAIN 1       /* the update of Algorithm 3 as printed */
+
+/* front position of each row y (Section 6: "position of the interface") */
+#define LBM_FRONT_LIQUID_INTEGRAL 0 /* dx * trapezoid sum_x phi(T(x, y)) */
+#define LBM_FRONT_ZERO_CROSSING 1   /* first x where T - T_m goes from > 0
+                                       to <= 0, linearly interpolated */
+
+/* fields for lbm_stefan_get_field */
+#define LBM_FIELD_T 0     /* temperature, double [ny][nx] */
+#define LBM_FIELD_STATE 1 /* the state planes, storage type [q][ny][nx] */
+
+typedef struct lbm_stefan_params {
+  int32_t dim;           /* 1 or 2 */
+  int32_t q;             /* 3 (dim 1), 5 or 9 (dim 2) */
+  int64_t nx, ny;        /* node counts; ny = 1 when dim = 1 */
+  int32_t storage;       /* LBM_STORE_F64 or LBM_STORE_F32 */
+  int32_t newton_mode;   /* LBM_NEWTON_* */
+  double tau;            /* BGK relaxation time (eq. std_lbm_collide_stream),
+                            > 1/2; diffusivity (tau - 1/2)/3 in lattice
+                            units (Section 5) */
+  double ste;            /* Stefan number (Section 2), > 0 */
+  double t_m;            /* melting temperature (0 in scaled units) */
+  double delta;          /* width of the regularized liquid fraction, in
+                            temperature units, > 0 (Section 4.1) */
+  int32_t bc[4];         /* walls x-, x+, y-, y+: LBM_BC_*; y walls are
+                            ignored when dim = 1 */
+  double wall_T[4];      /* Dirichlet temperature of each wall */
+  const double *wall_profile[4]; /* host, nullable: per-node Dirichlet
+                            temperatures (length ny for x walls, nx for y
+                            walls); copied during init */
+  double dx;             /* lattice spacing used by the front position;
+                            0 means 1/(nx - 1) */
+  double newton_tol;     /* stop when |T^(k+1) - T^(k)| <= tol, > 0 */
+  int32_t newton_max_it; /* iteration cap, 1..1000 */
+  int32_t strict;        /* nonzero: lbm_stefan_step returns
+                            LBM_STEFAN_ENOTCONV if a solve hit the cap */
+  int32_t variant;       /* kernel variant (lbm_stefan_variant_name); -1
+                            picks the library default for the lattice */
+  int32_t flags;         /* LBM_FLAG_* */
+} lbm_stefan_params;
+
+#define LBM_FLAG_ADJOINT 1 /* reserve workspace for the reverse mode */
+
+typedef struct lbm_stefan_stats {
+  int64_t steps;         /* steps taken since init */
+  int32_t max_newton_it; /* largest Newton iteration count since the last
+                            lbm_stefan_reset_stats (or init) */
+  int32_t reserved;
+  int64_t nonconverged;  /* node-steps that reached the cap, same window */
+  double max_residual;   /* largest |T~ + phi(T~)/Ste - M0(q) - phi(T)/Ste| */
+  double energy;         /* E = sum_x [T + phi(T)/Ste] of the current state
+                            (eq. eq-H), FP64 in a fixed summation order */
+  double flux_in;        /* sum of populations set by boundary closures */
+  double flux_out;       /* sum of post-collision populations leaving the
+                            lattice; E(n) - E(0) = flux_in - flux_out up to
+                            Newton residuals (same window) */
+} lbm_stefan_stats;
+
+typedef struct lbm_stefan lbm_stefan_t;
+
+/* Library version string (static storage). */
+const char *lbm_stefan_version(void);
+
+/* Text of the last error of h, or of the calling thread's last failed
+   lbm_stefan_init / *_workspace_bytes when h is NULL.  Static or
+   handle-owned storage; never NULL. */
+const char *lbm_stefan_last_error(const lbm_stefan_t *h);
+
+/*
+ * Device workspace needed by a handle for params p (the two population
+ * buffers, wall profiles, per-tile statistics and reduction scratch).
+ * Errors: EINVAL for invalid params (same checks as init).
+ */
+int lbm_stefan_workspace_bytes(const lbm_stefan_params *p, size_t *bytes);
+
+/*
+ * Create a handle and its initial state: Omega_i = w_i T0 (the
+ * equilibrium state, f_i = w_i T0), with nodes on Dirichlet walls at their
+ * wall temperature (where two Dirichlet walls meet, the first of x-, x+,
+ * y-, y+ gives it).
+ *   T0         host, nullable: initial temperature [ny][nx] (NULL: 0).
+ *   workspace  device, >= lbm_stefan_workspace_bytes(p), 256-byte
+ *              aligned; owned by the caller, must outlive the handle.
+ *   stream     hipStream_t to enqueue on (NULL: the null stream).
+ *   out        receives the handle (host memory owned by the library).
+ * Blocks until the state is built.  Errors: EINVAL (invalid params:
+ * tau <= 1/2, Ste <= 0, delta <= 0, tol <= 0, max_it outside 1..1000,
+ * nx < 3, ny < 3 in 2D or != 1 in 1D, lattice/dim mismatch, a periodic
+ * axis with one non-periodic wall, workspace too small or misaligned,
+ * unknown variant), EDEVICE.
+ */
+int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
+                    void *workspace, size_t bytes, void *stream,
+                    lbm_stefan_t **out);
+
+/*
+ * Advance nsteps >= 0 time steps (one kernel launch per step on the
+ * handle's stream).  Asynchronous when stats is NULL and strict is off;
+ * otherwise waits for the stream and fills *stats (the energy is
+ * recomputed from the final state).  Errors: EINVAL (nsteps < 0),
+ * ENOTCONV (strict), ENAN (the energy is not finite), EDEVICE.
+ */
+int lbm_stefan_step(lbm_stefan_t *h, int64_t nsteps, lbm_stefan_stats *stats);
+
+/* Zero the Newton and flux accumulators (asynchronous). */
+int lbm_stefan_reset_stats(lbm_stefan_t *h);
+
+/*
+ * Front position of every row of the current state (mode LBM_FRONT_*),
+ * written to front (host, ny doubles, may be NULL), and the energy E
+ * (host, may be NULL).  Both reductions are FP64 in a fixed order.
+ * Waits for the stream.  Errors: EINVAL (bad mode), ENAN, EDEVICE.
+ */
+int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
+                           double *energy);
+
+/*
+ * Copy a field of the current state to host memory: LBM_FIELD_T (ny*nx
+ * doubles) or LBM_FIELD_STATE (q*ny*nx values of the storage type).
+ * Waits for the stream.  Errors: EINVAL, EDEVICE.
+ */
+int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host);
+
+/*
+ * Replace the current state by q planes of the storage type (layout as
+ * above), read from device memory (on_device != 0) or host memory.
+ * Enqueued on the stream; a host source is copied before return.
+ */
+int lbm_stefan_set_state(lbm_stefan_t *h, const void *state,
+                         int32_t on_device);
+
+/* Device pointer of the current state planes (valid until the next
+   step, set_state or destroy). */
+int lbm_stefan_state_ptr(lbm_stefan_t *h, void **dev_state);
+
+/* Number of compiled kernel variants for a lattice/storage pair, and the
+   name of one ("<tile_x>x<tile_y>/npt<k>"); used by autotuners. */
+int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count);
+const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
+                                    int32_t variant);
+
+/* Select the kernel variant of an existing handle. */
+int lbm_stefan_set_variant(lbm_stefan_t *h, int32_t variant);
+
+/* Free the handle (host memory only; the workspace stays the caller's).
+   Waits for the stream. */
+int lbm_stefan_destroy(lbm_stefan_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_STEFAN_H */

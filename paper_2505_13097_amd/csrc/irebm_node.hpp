@@ -1,0 +1,385 @@
+// irebm_node.hpp -- device-side pieces of the IREBM step for gfx950:
+// lattice constants, the regularized liquid fraction, the local Newton
+// solve and the per-node update on the post-collision state.
+//
+// Method: Luddens, Lothode, Danaila, arXiv 2505.13097, Algorithm 3
+// (Section 4.1) with the boundary closures of Section 4.2.
+//
+// State: Omega_i(x) = (1 - 1/tau) f_i(x) + (w_i/tau) T(x) (eq.
+// def_qi_omegai), stored as q planes.  One step for node x reads
+//   T(x)   = sum_j Omega_j(x)            (collision conserves M0),
+//   q_i(x) = Omega_i(x - e_i)            (pull streaming),
+// solves the local equation for the new temperature T~, forms
+//   f~_i = q_i + (w_i/Ste)(phi(T) - phi(T~))   (source and update),
+// and writes the next state Omega'_i = (1 - 1/tau) f~_i + (w_i/tau) M0(f~).
+// Storing Omega instead of f makes the pull read one direction per
+// neighbour, so a step moves the minimum 2 q s bytes per node.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace irebm {
+
+// ---- lattices (Section 3.2): rest, +x, +y, -x, -y, (1,1), (-1,1),
+// (-1,-1), (1,-1); D1Q3 is rest, +x, -x.
+template <int Q>
+__host__ __device__ constexpr int cx(int i) {
+  return Q == 3 ? (i == 1 ? 1 : (i == 2 ? -1 : 0))
+                : ((i == 1 || i == 5 || i == 8) ? 1
+                   : (i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+template <int Q>
+__host__ __device__ constexpr int cy(int i) {
+  return Q == 3 ? 0
+                : ((i == 2 || i == 5 || i == 6) ? 1
+                   : (i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+template <int Q>
+__host__ __device__ constexpr double wt(int i) {
+  return Q == 3 ? (i == 0 ? 2.0 / 3.0 : 1.0 / 6.0)
+       : Q == 5 ? (i == 0 ? 1.0 / 3.0 : 1.0 / 6.0)
+                : (i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0));
+}
+template <int Q>
+__host__ __device__ constexpr int opp(int i) {
+  return Q == 3 ? (i == 0 ? 0 : 3 - i)
+       : i == 0 ? 0
+       : i < 5  ? (i + 1) % 4 + 1
+                : (i - 3) % 4 + 5;
+}
+
+enum { BC_DIRICHLET = 0, BC_BOUNCEBACK = 1, BC_PERIODIC = 2 };
+
+// Per-tile statistics slot, accumulated across steps by the one block
+// that owns the tile (no atomics; deterministic).
+struct StatSlot {
+  int32_t max_it;
+  int32_t nonconv;
+  double max_res;
+  double flux_in;
+  double flux_out;
+};
+
+// Everything one step of one lattice needs; passed by value.
+struct StepArgs {
+  const void *src;      // current state planes
+  void *dst;            // next state planes
+  int32_t nx, ny;
+  int64_t plane;        // nx * ny
+  int32_t tiles_x, ntiles, per_xcd;
+  int32_t periodic_x, periodic_y;
+  double a;             // 1 - 1/tau
+  double wtau[9];       // w_i / tau
+  double wste[9];       // w_i / Ste
+  double inv_ste, tm, inv_delta, tol;
+  int32_t max_it;
+  int32_t bc[4];
+  double wall_T[4];
+  const double *prof[4];
+  StatSlot *slots;
+};
+
+// ---- regularized liquid fraction (Section 4.1)
+// phi(T) = (1 + tanh(u))/2 = 1/(1 + exp(-2u)), u = (T - T_m)/delta, and
+// phi'(T) = (1 - tanh^2 u)/(2 delta) = 2 e/(1 + e)^2 / delta with
+// e = exp(-2u).  Past |u| > 20, tanh(u) rounds to +-1 in double, so
+// phi is exactly 0 or 1 there and phi' is 0.
+__device__ inline void phi_dphi(double t, double tm, double inv_delta,
+                                double &ph, double &dph) {
+  const double u = (t - tm) * inv_delta;
+  if (u > 20.0) {
+    ph = 1.0;
+    dph = 0.0;
+  } else if (u < -20.0) {
+    ph = 0.0;
+    dph = 0.0;
+  } else {
+    const double e = exp(-2.0 * u);
+    const double r = 1.0 / (1.0 + e);
+    ph = r;
+    dph = 2.0 * inv_delta * e * r * r;
+  }
+}
+
+__device__ inline double phi_only(double t, double tm, double inv_delta) {
+  const double u = (t - tm) * inv_delta;
+  if (u > 20.0) return 1.0;
+  if (u < -20.0) return 0.0;
+  return 1.0 / (1.0 + exp(-2.0 * u));
+}
+
+// ---- local Newton solve of eq. rhs_fl_2:
+//   F(t) = t + phi(t)/Ste - c = 0,  c = m0 + phi(T)/Ste,
+// started from t = T (Algorithm 3).  PLAIN takes the printed update.
+// The safeguarded form keeps the same step inside the rtsafe rule
+// (Press et al., Numerical Recipes, sec. 9.4): bracket [c - 1/Ste, c]
+// (F' >= 1 and 0 <= phi <= 1 make it valid), bisect when the step leaves
+// the bracket or fails to halve the step before the last.  Stops when
+// |t_{k+1} - t_k| <= tol; returns the last candidate.
+template <bool PLAIN>
+__device__ inline double newton(double m0, double th, double pth,
+                                const StepArgs &A, int &iters, bool &conv) {
+  const double s = A.inv_ste;
+  const double c = m0 + pth * s;
+  double lo = c - s, hi = c;
+  double dx = hi - lo, dxold = dx;
+  double cur = th, cand = th;
+  int k = 0;
+  conv = false;
+  while (k < A.max_it) {
+    double ph, dph;
+    phi_dphi(cur, A.tm, A.inv_delta, ph, dph);
+    if (PLAIN) {
+      cand = (m0 + pth * s + dph * cur * s - ph * s) / (1.0 + dph * s);
+    } else {
+      const double F = cur + ph * s - c;
+      if (F < 0.0) lo = cur;
+      else if (F > 0.0) hi = cur;
+      const double stp = (dph == 0.0) ? F : F / (1.0 + dph * s);
+      cand = cur - stp;
+      if (cand < lo || cand > hi || 2.0 * fabs(stp) > fabs(dxold)) {
+        cand = 0.5 * (lo + hi);
+        dxold = dx;
+        dx = 0.5 * (hi - lo);
+      } else {
+        dxold = dx;
+        dx = stp;
+      }
+    }
+    ++k;
+    if (fabs(cand - cur) <= A.tol) {
+      conv = true;
+      break;
+    }
+    cur = cand;
+  }
+  iters = k;
+  return cand;
+}
+
+struct NodeStats {
+  int max_it = 0;
+  int nonconv = 0;
+  double max_res = 0.0;
+  double flux_in = 0.0;
+  double flux_out = 0.0;
+};
+
+template <typename S>
+__device__ inline double ld(const S *p) {
+  return (double)*p;
+}
+
+// Raw loads of one node: own populations (for T) and pulled ones.
+template <int Q, typename S>
+struct NodeLoad {
+  S own[Q];
+  S pull[Q];
+  uint32_t known;   // bit i: pull source of direction i is a lattice node
+  uint32_t out;     // bit i: destination x + e_i leaves the lattice
+};
+
+// FAST: every pull source and destination of the node lies inside the
+// lattice without wrapping (interior tile); no checks are compiled.
+template <int Q, typename S, bool FAST>
+__device__ inline void load_node(const StepArgs &A, int x, int y,
+                                 NodeLoad<Q, S> &L) {
+  const S *__restrict__ src = (const S *)A.src;
+  const int64_t P = A.plane;
+  const int nx = A.nx;
+  int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+  bool vxm = true, vxp = true, vym = true, vyp = true;
+  if (!FAST) {
+    if (xm < 0) {
+      if (A.periodic_x) xm += nx; else vxm = false;
+    }
+    if (xp >= nx) {
+      if (A.periodic_x) xp -= nx; else vxp = false;
+    }
+    if (Q > 3) {
+      if (ym < 0) {
+        if (A.periodic_y) ym += A.ny; else vym = false;
+      }
+      if (yp >= A.ny) {
+        if (A.periodic_y) yp -= A.ny; else vyp = false;
+      }
+    }
+  }
+  const int64_t row = (int64_t)y * nx;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) L.own[j] = src[j * P + row + x];
+  L.known = 1u;
+  L.out = 0u;
+  L.pull[0] = L.own[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int ex = cx<Q>(i), ey = cy<Q>(i);
+    const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
+    const int sy = ey == 1 ? ym : (ey == -1 ? yp : y);
+    const bool ok = (ex == 1 ? vxm : (ex == -1 ? vxp : true)) &&
+                    (ey == 1 ? vym : (ey == -1 ? vyp : true));
+    const bool leaves = (ex == 1 ? !vxp : (ex == -1 ? !vxm : false)) ||
+                        (ey == 1 ? !vyp : (ey == -1 ? !vym : false));
+    if (FAST || ok) {
+      L.pull[i] = src[i * P + (int64_t)sy * nx + sx];
+      L.known |= 1u << i;
+    } else {
+      L.pull[i] = (S)0;
+    }
+    if (!FAST && leaves) L.out |= 1u << i;
+  }
+}
+
+// Does the unknown direction i of node (x, y) leave the lattice only
+// through bounce-back walls?
+template <int Q>
+__device__ inline bool leaves_by_bounceback(const StepArgs &A, int x, int y,
+                                            int i) {
+  const int sx = x - cx<Q>(i), sy = y - cy<Q>(i);
+  if (sx < 0 && A.bc[0] != BC_BOUNCEBACK) return false;
+  if (sx >= A.nx && A.bc[1] != BC_BOUNCEBACK) return false;
+  if (Q > 3 && sy < 0 && A.bc[2] != BC_BOUNCEBACK) return false;
+  if (Q > 3 && sy >= A.ny && A.bc[3] != BC_BOUNCEBACK) return false;
+  return true;
+}
+
+template <int Q>
+__device__ inline int dirichlet_wall(const StepArgs &A, int x, int y) {
+  if (x == 0 && A.bc[0] == BC_DIRICHLET) return 0;
+  if (x == A.nx - 1 && A.bc[1] == BC_DIRICHLET) return 1;
+  if (Q > 3 && y == 0 && A.bc[2] == BC_DIRICHLET) return 2;
+  if (Q > 3 && y == A.ny - 1 && A.bc[3] == BC_DIRICHLET) return 3;
+  return -1;
+}
+
+__device__ inline double wall_value(const StepArgs &A, int wall, int x,
+                                    int y) {
+  const double *p = A.prof[wall];
+  return p ? p[wall < 2 ? y : x] : A.wall_T[wall];
+}
+
+// Closure of the unknown pulled populations (Section 4.2):
+// 1. bounce-back q_i = q_opp(i) for unknowns beyond bounce-back walls
+//    only, when the opposite is known;
+// 2. on a Dirichlet node, the zeroth moment is fixed to
+//    T_D + (phi(T_D) - phi(T))/Ste (eq. Dir_on_q), so that the new
+//    temperature is T_D; the deficit is shared by weight among the
+//    remaining unknowns;
+// 3. anything left (corner of two bounce-back walls): own Omega_opp(i).
+template <int Q>
+__device__ inline double close_node(const StepArgs &A, int x, int y,
+                                    double th, const double *om, double *q,
+                                    uint32_t known) {
+  uint32_t set = known;
+  double fill = 0.0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int o = opp<Q>(i);
+    if (!(known >> i & 1u) && (known >> o & 1u) &&
+        leaves_by_bounceback<Q>(A, x, y, i)) {
+      q[i] = q[o];
+      set |= 1u << i;
+      fill += q[i];
+    }
+  }
+  const int wall = dirichlet_wall<Q>(A, x, y);
+  if (wall >= 0) {
+    const double TD = wall_value(A, wall, x, y);
+    double D = TD + (phi_only(TD, A.tm, A.inv_delta) -
+                     phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
+    double wu = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (set >> i & 1u) D -= q[i];
+      else wu += wt<Q>(i);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (!(set >> i & 1u)) {
+        q[i] = D * (wt<Q>(i) / wu);
+        fill += q[i];
+      }
+    set = (1u << Q) - 1u;
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if (!(set >> i & 1u)) {
+      q[i] = om[opp<Q>(i)];
+      fill += q[i];
+    }
+  return fill;
+}
+
+// The update of one node from its loads; writes the next state.
+template <int Q, typename S, bool PLAIN, bool FAST>
+__device__ inline void update_node(const StepArgs &A, int x, int y,
+                                   const NodeLoad<Q, S> &L, NodeStats &st) {
+  double om[Q], q[Q];
+  double th = 0.0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    om[j] = (double)L.own[j];
+    th += om[j];
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
+  if (!FAST) {
+    if (L.known != (1u << Q) - 1u)
+      st.flux_in += close_node<Q>(A, x, y, th, om, q, L.known);
+    if (L.out) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (L.out >> i & 1u) st.flux_out += om[i];
+    }
+  }
+  double m0 = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) m0 += q[i];
+  const double pth = phi_only(th, A.tm, A.inv_delta);
+  int it;
+  bool conv;
+  const double tn = newton<PLAIN>(m0, th, pth, A, it, conv);
+  const double pnew = phi_only(tn, A.tm, A.inv_delta);
+  const double dphi_s = pth - pnew;
+  double f[Q];
+  double tsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    f[i] = q[i] + A.wste[i] * dphi_s;
+    tsum += f[i];
+  }
+  S *__restrict__ dst = (S *)A.dst;
+  const int64_t base = (int64_t)y * A.nx + x;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    dst[i * A.plane + base] = (S)(A.a * f[i] + A.wtau[i] * tsum);
+  const double res = fabs(tn + pnew * A.inv_ste - (m0 + pth * A.inv_ste));
+  st.max_it = it > st.max_it ? it : st.max_it;
+  st.nonconv += conv ? 0 : 1;
+  st.max_res = res > st.max_res ? res : st.max_res;
+}
+
+// ---- wave and block reductions (wave64)
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace irebm

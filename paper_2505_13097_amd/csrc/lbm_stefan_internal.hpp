@@ -1,0 +1,63 @@
+// lbm_stefan_internal.hpp -- the handle and helpers shared by the
+// translation units of the library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "irebm_node.hpp"
+#include "lbm_stefan.h"
+
+namespace irebm {
+
+// offsets into the caller's workspace
+struct Layout {
+  size_t buf_bytes = 0;
+  size_t off_buf[2] = {0, 0};
+  size_t off_prof[4] = {0, 0, 0, 0};
+  size_t off_slots = 0, off_partials = 0, off_small = 0, off_adj = 0;
+  size_t total = 0;
+  int64_t max_tiles = 0, n_partials = 0;
+  bool adjoint = false;
+};
+
+// the small device result area: stats [0..5), energy, then the front
+constexpr int kSmallEnergy = 8;
+constexpr int kSmallCount = 9;
+constexpr int kSmallFront = 16;
+
+}  // namespace irebm
+
+struct lbm_stefan {
+  lbm_stefan_params p;
+  irebm::Layout layout;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  double *prof[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool has_prof[4] = {false, false, false, false};
+  irebm::StatSlot *slots = nullptr;
+  int64_t max_tiles = 0;
+  double *partials = nullptr;
+  double *small = nullptr;
+  char *adj = nullptr;
+  int variant = 0;
+  int64_t steps = 0;
+  std::string err;
+};
+
+namespace irebm {
+
+std::string validate_params(const lbm_stefan_params *p);
+Layout layout_for(const lbm_stefan_params *p);
+size_t adjoint_bytes(const lbm_stefan_params *p, int64_t max_tiles);
+int fail(lbm_stefan_t *h, int code, const std::string &msg);
+void fill_step_args(const lbm_stefan_t *h, StepArgs *A);
+hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst);
+hipError_t zero_stats_async(lbm_stefan_t *h);
+int read_stats(lbm_stefan_t *h, lbm_stefan_stats *st);
+
+}  // namespace irebm

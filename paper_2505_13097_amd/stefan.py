@@ -1,0 +1,176 @@
+"""Python face of the C ABI: one lattice (``Stefan``) on one device.
+
+Argument marshalling only: every step of the method runs in the gfx950
+kernels of liblbm_stefan.so.  PyTorch provides the device memory (the
+workspace is a uint8 tensor) and the stream (torch's current stream).
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+_BC = {"dirichlet": C.BC_DIRICHLET, "bounceback": C.BC_BOUNCEBACK,
+       "periodic": C.BC_PERIODIC}
+_STORE = {"f64": C.STORE_F64, "f32": C.STORE_F32}
+_NEWTON = {"safeguarded": C.NEWTON_SAFEGUARDED, "plain": C.NEWTON_PLAIN}
+_FRONT = {"integral": C.FRONT_LIQUID_INTEGRAL,
+          "crossing": C.FRONT_ZERO_CROSSING}
+
+
+def make_params(prob, variant=-1, flags=0, strict=False):
+    """lbm_stefan_params from a problem description (synth.Problem or an
+    object with the same attributes).  Returns (params, keepalive)."""
+    p = C.Params()
+    p.dim, p.q = prob.dim, prob.q
+    p.nx, p.ny = prob.nx, prob.ny
+    p.storage = _STORE[prob.storage] if isinstance(prob.storage, str) else prob.storage
+    nm = prob.newton_mode
+    p.newton_mode = _NEWTON[nm] if isinstance(nm, str) else nm
+    p.tau, p.ste, p.t_m, p.delta = prob.tau, prob.ste, prob.tm, prob.delta
+    keep = []
+    for k in range(4):
+        b = prob.bc[k]
+        p.bc[k] = _BC[b] if isinstance(b, str) else int(b)
+        p.wall_T[k] = prob.wall_T[k]
+        prof = prob.wall_profile[k] if prob.wall_profile else None
+        if prof is not None:
+            arr = np.ascontiguousarray(prof, dtype=np.float64)
+            keep.append(arr)
+            p.wall_profile[k] = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.dx = prob.dx or 0.0
+    p.newton_tol = prob.tol
+    p.newton_max_it = prob.max_it
+    p.strict = 1 if strict else 0
+    p.variant = variant
+    p.flags = flags
+    return p, keep
+
+
+def workspace_bytes(prob, variant=-1, flags=0):
+    p, _ = make_params(prob, variant, flags)
+    n = ctypes.c_size_t()
+    C.check(C.lib().lbm_stefan_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def variant_names(q, storage="f32"):
+    L = C.lib()
+    s = _STORE[storage]
+    n = ctypes.c_int32()
+    C.check(L.lbm_stefan_variant_count(q, s, ctypes.byref(n)))
+    return [L.lbm_stefan_variant_name(q, s, v).decode() for v in range(n.value)]
+
+
+class Stefan:
+    """One IREBM lattice on the current CUDA (HIP) device.
+
+    prob      synth.Problem-like description (lattice, sizes, tau, Ste,
+              delta, walls, Newton settings, storage, initial T0).
+    variant   kernel variant (-1: library default).
+    """
+
+    def __init__(self, prob, variant=-1, flags=0, strict=False,
+                 device=None, stream=None):
+        self.prob = prob
+        self._lib = C.lib()
+        self.device = torch.device("cuda", torch.cuda.current_device()
+                                   if device is None else device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            p, keep = make_params(prob, variant, flags, strict)
+            self._params = p
+            n = ctypes.c_size_t()
+            C.check(self._lib.lbm_stefan_workspace_bytes(ctypes.byref(p),
+                                                         ctypes.byref(n)))
+            self.workspace = torch.empty(n.value, dtype=torch.uint8,
+                                         device=self.device)
+            T0 = None
+            T0p = None
+            if prob.T0 is not None:
+                T0 = np.ascontiguousarray(
+                    np.broadcast_to(prob.T0, (prob.ny, prob.nx)), dtype=np.float64)
+                T0p = T0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            h = ctypes.c_void_p()
+            C.check(self._lib.lbm_stefan_init(
+                ctypes.byref(p), T0p, ctypes.c_void_p(self.workspace.data_ptr()),
+                n.value, ctypes.c_void_p(self.stream.cuda_stream),
+                ctypes.byref(h)))
+            del keep, T0
+        self.h = h
+        self.state_dtype = np.float64 if prob.storage == "f64" else np.float32
+
+    # -- time stepping -------------------------------------------------
+    def step(self, nsteps, stats=False):
+        """Advance nsteps.  With stats=True waits and returns a dict
+        (Newton counters, energy, boundary fluxes)."""
+        st = C.Stats() if stats else None
+        rc = self._lib.lbm_stefan_step(self.h, int(nsteps),
+                                       ctypes.byref(st) if st is not None else None)
+        C.check(rc, self.h)
+        return st.as_dict() if st is not None else None
+
+    def stats(self):
+        return self.step(0, stats=True)
+
+    def reset_stats(self):
+        C.check(self._lib.lbm_stefan_reset_stats(self.h), self.h)
+
+    # -- queries -------------------------------------------------------
+    def front(self, mode="integral"):
+        out = np.empty(self.prob.ny)
+        C.check(self._lib.lbm_stefan_query_front(
+            self.h, _FRONT[mode], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            None), self.h)
+        return out
+
+    def energy(self):
+        e = ctypes.c_double()
+        C.check(self._lib.lbm_stefan_query_front(
+            self.h, C.FRONT_LIQUID_INTEGRAL, None, ctypes.byref(e)), self.h)
+        return e.value
+
+    def temperature(self):
+        T = np.empty((self.prob.ny, self.prob.nx))
+        C.check(self._lib.lbm_stefan_get_field(
+            self.h, C.FIELD_T, ctypes.c_void_p(T.ctypes.data)), self.h)
+        return T
+
+    def state(self):
+        s = np.empty((self.prob.q, self.prob.ny, self.prob.nx),
+                     dtype=self.state_dtype)
+        C.check(self._lib.lbm_stefan_get_field(
+            self.h, C.FIELD_STATE, ctypes.c_void_p(s.ctypes.data)), self.h)
+        return s
+
+    def state_ptr(self):
+        p = ctypes.c_void_p()
+        C.check(self._lib.lbm_stefan_state_ptr(self.h, ctypes.byref(p)), self.h)
+        return p.value
+
+    def set_state(self, state):
+        """state: host numpy array or device tensor of shape (q, ny, nx)
+        and the storage dtype."""
+        if isinstance(state, torch.Tensor):
+            t = state.contiguous()
+            C.check(self._lib.lbm_stefan_set_state(
+                self.h, ctypes.c_void_p(t.data_ptr()), 1), self.h)
+        else:
+            a = np.ascontiguousarray(state, dtype=self.state_dtype)
+            C.check(self._lib.lbm_stefan_set_state(
+                self.h, ctypes.c_void_p(a.ctypes.data), 0), self.h)
+
+    def set_variant(self, v):
+        C.check(self._lib.lbm_stefan_set_variant(self.h, int(v)), self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            C.check(self._lib.lbm_stefan_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

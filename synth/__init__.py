@@ -47,7 +47,7 @@ class Problem:
     max_it: int = 20
     newton_mode: str = "safeguarded"
     storage: str = "f64"  # population storage: "f64" or "f32"
-    T0: np.ndarray = None  # initial temperature, shape (ny, nx)
+    T0: object = None     # initial temperature: (ny, nx) array or scalar
     nsteps: int = 0
     name: str = ""
     dx: float = field(default=None)
@@ -122,7 +122,7 @@ def cavity_2d(n=8192, ny=None, nsteps=2000, seed=DEFAULT_SEED,
                    delta=1.5 / (n - 1),
                    bc=("dirichlet", "dirichlet", "bounceback", "bounceback"),
                    wall_T=(1.0, -0.5, 0.0, 0.0), tol=1e-12, max_it=32,
-                   storage=storage, T0=None, nsteps=nsteps,
+                   storage=storage, T0=-0.5, nsteps=nsteps,
                    name=f"cavity2d_d2q9_{storage}_{n}x{ny}")
 
 

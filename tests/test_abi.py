@@ -1,0 +1,121 @@
+"""The C ABI library loads, exports every symbol include/lbm_stefan.h
+declares, and its host-side argument checks work (no GPU needed: these
+paths return before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_stefan.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2505_13097_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2505_13097_amd import build
+        build.build(verbose=False)
+    return _lib
+
+
+def declared_functions(path):
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_stefan_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported(L):
+    names = declared_functions(HEADER)
+    assert "lbm_stefan_init" in names and "lbm_stefan_step" in names
+    lib = L.lib()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares the same set
+    assert set(L.SIGNATURES) <= set(names)
+
+
+def test_version_string(L):
+    v = L.lib().lbm_stefan_version().decode()
+    assert "gfx950" in v
+
+
+def _params(L, prob, **over):
+    from paper_2505_13097_amd.stefan import make_params
+    p, keep = make_params(prob)
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p, keep
+
+
+def _ws(L, p):
+    n = ctypes.c_size_t()
+    rc = L.lib().lbm_stefan_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    return rc, n.value
+
+
+@pytest.mark.parametrize("field,value", [
+    ("tau", 0.5), ("tau", 0.3), ("ste", 0.0), ("ste", -1.0), ("delta", 0.0),
+    ("newton_tol", 0.0), ("newton_max_it", 0), ("newton_max_it", 1001),
+    ("nx", 2), ("ny", 2), ("q", 4), ("dim", 3), ("storage", 7),
+    ("newton_mode", 5), ("variant", 99), ("tau", float("nan")),
+])
+def test_invalid_params_rejected(L, field, value):
+    p, keep = _params(L, synth.planar_2d(n=32, ny=16))
+    setattr(p, field, value)
+    rc, _ = _ws(L, p)
+    assert rc == L.EINVAL
+    msg = L.lib().lbm_stefan_last_error(None).decode()
+    assert msg and msg != "no error"
+
+
+def test_lattice_dimension_mismatch(L):
+    p, _ = _params(L, synth.stefan_1d(nx=32))
+    p.ny = 4
+    assert _ws(L, p)[0] == L.EINVAL
+    p, _ = _params(L, synth.planar_2d(n=32, ny=16))
+    p.bc[2] = L.BC_DIRICHLET       # y- not periodic, y+ periodic
+    assert _ws(L, p)[0] == L.EINVAL
+
+
+@pytest.mark.parametrize("maker,q,s", [
+    (lambda: synth.stefan_1d(nx=256), 3, 8),
+    (lambda: synth.planar_2d(n=128, ny=96), 5, 4),
+    (lambda: synth.cavity_2d(n=200, ny=130), 9, 4),
+])
+def test_workspace_holds_two_state_buffers(L, maker, q, s):
+    prob = maker()
+    p, _ = _params(L, prob)
+    rc, n = _ws(L, p)
+    assert rc == L.OK
+    assert n >= 2 * q * prob.nodes * s
+    assert n < 2 * q * prob.nodes * s + 64 * prob.nodes + (1 << 20)
+    p.flags = L.FLAG_ADJOINT
+    rc, n2 = _ws(L, p)
+    assert rc == L.OK and n2 >= n
+
+
+def test_init_rejects_small_or_misaligned_workspace(L):
+    p, _ = _params(L, synth.planar_2d(n=32, ny=16))
+    rc, n = _ws(L, p)
+    h = ctypes.c_void_p()
+    lib = L.lib()
+    assert lib.lbm_stefan_init(ctypes.byref(p), None, None, n, None,
+                               ctypes.byref(h)) == L.EINVAL
+    assert lib.lbm_stefan_init(ctypes.byref(p), None, ctypes.c_void_p(256),
+                               n - 1, None, ctypes.byref(h)) == L.EINVAL
+    assert lib.lbm_stefan_init(ctypes.byref(p), None, ctypes.c_void_p(4096 + 8),
+                               n, None, ctypes.byref(h)) == L.EINVAL
+    assert not h.value
+
+
+def test_variants_listed(L):
+    from paper_2505_13097_amd import variant_names
+    for q in (3, 5, 9):
+        names = variant_names(q)
+        assert len(names) >= 3
+        assert all(re.fullmatch(r"\d+x\d+/npt\d", n) for n in names)
+    assert L.lib().lbm_stefan_variant_name(5, 1, 999) == b""

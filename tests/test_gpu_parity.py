@@ -1,0 +1,259 @@
+"""GPU parity: the gfx950 IREBM step, called through the C ABI, against
+the CPU FP64 oracle on the same seeded inputs.
+
+Bars: FP64 storage, ||T_gpu - T_orc||_inf <= 1e-12 max(||T_orc||_inf, 1)
+and fronts to 1e-12 relative; FP32 storage (per-node math in FP64),
+||dT||_inf <= 1e-5 and the zero-crossing front within one cell; the
+energy is an FP64 sum in both precisions.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _gpu_run(prob, nsteps, variant=-1):
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob, variant=variant)
+    st = g.step(nsteps, stats=True)
+    out = {
+        "T": g.temperature(),
+        "front": g.front("integral"),
+        "cross": g.front("crossing"),
+        "energy": g.energy(),
+        "stats": st,
+    }
+    g.close()
+    return out
+
+
+def _oracle_run(prob, nsteps):
+    f = O.init(prob, prob.T0)
+    E0 = O.energy(prob, f)
+    f, st = O.run(prob, f, nsteps)
+    return {
+        "T": O.temperature(prob, f),
+        "front": O.front(prob, f, O.FRONT_INTEGRAL),
+        "cross": O.front(prob, f, O.FRONT_CROSSING),
+        "energy": O.energy(prob, f),
+        "E0": E0,
+        "stats": st,
+    }
+
+
+def _compare(prob, g, o, tol):
+    scale = max(1.0, np.max(np.abs(o["T"])))
+    err = np.max(np.abs(g["T"] - o["T"]))
+    print(f"{prob.name}: max|dT| = {err:.3e} (scale {scale:.3g})", flush=True)
+    assert err <= tol * scale
+    assert g["stats"]["nonconverged"] == 0 and o["stats"]["nonconverged"] == 0
+    if prob.storage == "f64":
+        fr = np.abs(g["front"] - o["front"])
+        assert np.all(fr <= 1e-12 * np.maximum(np.abs(o["front"]), prob.dx))
+        cr = np.abs(g["cross"] - o["cross"])
+        assert np.all(cr <= 1e-10 * np.maximum(np.abs(o["cross"]), prob.dx))
+        assert abs(g["energy"] - o["energy"]) <= 1e-12 * max(1.0, abs(o["energy"])) * 10
+        for k in ("flux_in", "flux_out"):
+            a, b = g["stats"][k], o["stats"][k]
+            assert abs(a - b) <= 1e-11 * max(1.0, abs(b)), (k, a, b)
+        assert g["stats"]["max_residual"] < 1e-10
+    else:
+        cr = np.abs(g["cross"] - o["cross"])
+        assert np.all(cr <= prob.dx), cr.max()
+        assert abs(g["energy"] - o["energy"]) <= 1e-5 * prob.nodes
+
+
+def _mushy(prob, shift=0.45):
+    """Same problem started near the melting temperature, so that Newton
+    works at most nodes."""
+    return prob.with_(T0=(prob.T0 if prob.T0 is not None
+                          else np.full((prob.ny, prob.nx), -0.5)) + shift)
+
+
+def test_stefan_1d_full_run_fp64():
+    """The 1D workload at full length: D1Q3, N = 256, 20k steps, FP64."""
+    prob = synth.stefan_1d()
+    g = _gpu_run(prob, prob.nsteps)
+    o = _oracle_run(prob, prob.nsteps)
+    _compare(prob, g, o, TOL64)
+    # energy balance through the boundaries, in both implementations
+    dE = g["energy"] - o["E0"]
+    assert abs(dE - (g["stats"]["flux_in"] - g["stats"]["flux_out"])) < 1e-9
+
+
+CASES = [
+    # (name, problem builder, steps)
+    ("d2q5_periodic_ragged", lambda s: _mushy(synth.planar_2d(
+        n=131, ny=67, storage=s)), 150),
+    ("d2q9_cavity_ragged", lambda s: _mushy(synth.cavity_2d(
+        n=150, ny=77, storage=s), 0.4), 150),
+    ("d2q9_all_bounceback", lambda s: _mushy(synth.cavity_2d(
+        n=97, ny=70, storage=s)).with_(
+            bc=("bounceback",) * 4), 120),
+    ("d2q5_all_periodic", lambda s: _mushy(synth.planar_2d(
+        n=70, ny=45, storage=s)).with_(bc=("periodic",) * 4), 120),
+    ("d2q9_mixed_profile", lambda s: _mushy(synth.cavity_2d(
+        n=90, ny=66, storage=s)).with_(
+            bc=("dirichlet", "bounceback", "dirichlet", "bounceback"),
+            wall_T=(1.0, 0.0, 0.2, 0.0),
+            wall_profile=(np.linspace(0.5, 1.5, 66), None,
+                          np.linspace(-0.3, 0.3, 90), None)), 120),
+    ("d2q5_tiny_3x3", lambda s: synth.planar_2d(n=3, ny=3, storage=s), 40),
+    ("d1q3_plain_newton", lambda s: synth.stefan_1d(nx=333).with_(
+        newton_mode="plain", storage=s), 500),
+]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_small_lattices_against_oracle(case, storage):
+    name, make, steps = CASES[case]
+    prob = make(storage).with_(name=f"{name}_{storage}")
+    g = _gpu_run(prob, steps)
+    o = _oracle_run(prob, steps)
+    _compare(prob, g, o, TOL64 if storage == "f64" else TOL32)
+
+
+def test_variants_bitwise_identical():
+    """The per-node arithmetic does not depend on the tile shape."""
+    from paper_2505_13097_amd import variant_names
+    prob = _mushy(synth.cavity_2d(n=300, ny=131, storage="f64"), 0.4)
+    ref = None
+    for v in range(len(variant_names(9, "f64"))):
+        T = _gpu_run(prob, 40, variant=v)["T"]
+        if ref is None:
+            ref = T
+        assert np.array_equal(T, ref), v
+
+
+def test_zero_steps_and_state_roundtrip():
+    from paper_2505_13097_amd import Stefan
+    prob = synth.planar_2d(n=64, ny=32, storage="f64")
+    g = Stefan(prob)
+    T0 = g.temperature()
+    expect = prob.T0.copy()
+    expect[:, 0] = 1.0
+    expect[:, -1] = -0.5
+    assert np.max(np.abs(T0 - expect)) < 1e-15
+    s = g.state()
+    g.step(5)
+    g.set_state(s)
+    assert np.array_equal(g.temperature(), T0)
+    st = g.step(0, stats=True)
+    assert st["steps"] == 5
+    g.close()
+
+
+def _window_problem(prob, x0, y0, w, h):
+    """Window [x0, x0+w) x [y0, y0+h) of prob as a lattice of its own.
+    Sides on the real boundary keep its closure; artificial sides get
+    bounce-back (which leaves the initial state alone)."""
+    bc = (prob.bc[0] if x0 == 0 else "bounceback",
+          prob.bc[1] if x0 + w == prob.nx else "bounceback",
+          prob.bc[2] if y0 == 0 else "bounceback",
+          prob.bc[3] if y0 + h == prob.ny else "bounceback")
+    assert "periodic" not in bc
+    prof = tuple(None if a is None else
+                 (a[y0:y0 + h] if k < 2 else a[x0:x0 + w])
+                 for k, a in enumerate(prob.wall_profile))
+    T0 = np.broadcast_to(0.0 if prob.T0 is None else prob.T0,
+                         (prob.ny, prob.nx))[y0:y0 + h, x0:x0 + w]
+    return prob.with_(nx=w, ny=h, bc=bc, wall_profile=prof, T0=T0,
+                      dx=prob.dx), bc
+
+
+def _check_windows(prob, steps, windows, tol):
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob)
+    st = g.step(steps, stats=True)
+    T = g.temperature()
+    g.close()
+    assert st["nonconverged"] == 0
+    worst = 0.0
+    for (x0, y0, w, h) in windows:
+        sub, bc = _window_problem(prob, x0, y0, w, h)
+        f = O.init(sub, sub.T0)
+        f, _ = O.run(sub, f, steps)
+        To = O.temperature(sub, f)
+        # nodes within `steps` cells of an artificial side are not exact
+        xa = 0 if x0 == 0 else steps
+        xb = w if x0 + w == prob.nx else w - steps
+        ya = 0 if y0 == 0 else steps
+        yb = h if y0 + h == prob.ny else h - steps
+        d = np.abs(T[y0 + ya:y0 + yb, x0 + xa:x0 + xb] - To[ya:yb, xa:xb])
+        worst = max(worst, d.max())
+    print(f"{prob.name}: {len(windows)} windows, max|dT| = {worst:.3e}",
+          flush=True)
+    assert worst <= tol * max(1.0, np.abs(T).max())
+
+
+def _windows(nx, ny, w, h, seed, count, avoid_y_edges=False):
+    """Corners, wall midpoints and seeded interior windows."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ylo = h if avoid_y_edges else 0
+    yhi = ny - 2 * h if avoid_y_edges else ny - h
+    out = [(0, ylo, w, h), (nx - w, yhi, w, h),
+           (0, (ylo + yhi) // 2, w, h), (nx - w, (ylo + yhi) // 2, w, h)]
+    if not avoid_y_edges:
+        out += [(0, 0, w, h), (nx - w, ny - h, w, h), (nx // 2, 0, w, h),
+                (nx // 3, ny - h, w, h)]
+    for _ in range(count):
+        out.append((int(rng.integers(0, nx - w)), int(rng.integers(ylo, yhi)),
+                    w, h))
+    return out
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_full_size_cavity_sampled_windows(storage, tol):
+    """The 8192 x 8192 D2Q9 cavity lattice in the launch configuration the
+    bench times, from a seeded field around the melting temperature (most
+    nodes run a non-trivial Newton solve); after 6 steps, 16 windows
+    (walls, corners, interior) against the oracle."""
+    prob = synth.cavity_2d(storage=storage)
+    T0 = synth.node_noise(7, prob.nodes, 0.004).reshape(prob.ny, prob.nx)
+    prob = prob.with_(T0=T0, name=f"cavity8192_{storage}")
+    _check_windows(prob, 6, _windows(prob.nx, prob.ny, 72, 40, 3, 8), tol)
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_full_size_planar_sampled_windows(storage, tol):
+    """The 2048 x 2048 D2Q5 planar lattice (periodic y) from its seeded
+    noisy initial field shifted into the mushy zone; 12 windows after 10
+    steps."""
+    prob = synth.planar_2d(storage=storage)
+    prob = prob.with_(T0=prob.T0 + 0.5, name=f"planar2048_{storage}")
+    _check_windows(prob, 10, _windows(prob.nx, prob.ny, 80, 48, 4, 8,
+                                      avoid_y_edges=True), tol)
+
+
+def test_full_size_planar_properties():
+    """The 2048 x 2048 D2Q5 planar workload at full length (10k steps):
+    energy balance through the walls, bounded temperatures, Newton within
+    its cap, and a y-uniform front (the initial noise has diffused)."""
+    prob = synth.planar_2d()
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob)
+    E0 = g.energy()
+    st = g.step(prob.nsteps, stats=True)
+    T = g.temperature()
+    assert st["nonconverged"] == 0
+    assert T.min() >= -0.5 - 1e-3 - 1e-6 and T.max() <= 1.0 + 1e-6
+    dE = st["energy"] - E0
+    assert abs(dE - (st["flux_in"] - st["flux_out"])) < 1e-3 * abs(dE)
+    cross = g.front("crossing")
+    assert cross.max() - cross.min() < 2 * prob.dx
+    g.close()
