@@ -44,11 +44,16 @@ def bytes_per_node(prob):
     return 2 * prob.q * s
 
 
-def time_plain(prob, steps, warmup, variant=-1):
+def time_plain(prob, steps, warmup, variant=-1, autotune=True):
     import torch
     from paper_2505_13097_amd import Stefan
     g = Stefan(prob, variant=variant)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if autotune and variant < 0:
+        v, ms = g.autotune(steps=10)
+        tuned = {"variant": v, "ms_per_step": round(ms, 4)}
+        variant = v
     g.step(warmup)
     g.reset_stats()
     torch.cuda.synchronize()
@@ -65,7 +70,8 @@ def time_plain(prob, steps, warmup, variant=-1):
     front = g.front("integral")
     g.close()
     return {"wall_s": t1 - t0, "gpu_ms": gpu_ms, "stats": st,
-            "front_mean": float(front.mean())}
+            "front_mean": float(front.mean()), "variant": variant,
+            "tuned": tuned}
 
 
 def cpu_baseline(prob, steps=1):
@@ -92,6 +98,7 @@ def main():
                     choices=["cavity", "planar", "stefan1d"])
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
@@ -109,7 +116,8 @@ def main():
     print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D2Q{prob.q} "
           f"steps {args.steps} warmup {args.warmup}", file=sys.stderr,
           flush=True)
-    r = time_plain(prob, args.steps, args.warmup, args.variant)
+    r = time_plain(prob, args.steps, args.warmup, args.variant,
+                   autotune=not args.no_autotune)
     print(f"[bench] timed region done: {r['gpu_ms']:.1f} ms", file=sys.stderr,
           flush=True)
     ms_per_step = r["wall_s"] * 1e3 / args.steps
@@ -117,9 +125,8 @@ def main():
     launch_ms = r["gpu_ms"] / args.steps
     bpn = bytes_per_node(prob)
     achieved = prob.nodes * bpn / (launch_ms * 1e-3) / 1e9
-    from paper_2505_13097_amd.stefan import make_params  # noqa: F401
-    vname = variant_names(prob.q, prob.storage)[
-        args.variant if args.variant >= 0 else (0 if prob.q == 3 else 3)]
+    v = r["variant"] if r["variant"] >= 0 else (0 if prob.q == 3 else 3)
+    vname = variant_names(prob.q, prob.storage)[v]
 
     if args.copy_probe:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -151,6 +158,8 @@ def main():
             "newton_tol": prob.tol, "newton_max_it": prob.max_it,
             "bc": list(prob.bc),
             "kernel_variant": vname,
+            "kernel_variant_id": v,
+            "autotuned": r["tuned"] is not None,
         },
         "hbm_gbps_algorithmic": round(achieved, 1),
         "roofline": {

@@ -206,8 +206,21 @@ int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count);
 const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
                                     int32_t variant);
 
-/* Select the kernel variant of an existing handle. */
+/* Select the kernel variant of an existing handle (resets statistics). */
 int lbm_stefan_set_variant(lbm_stefan_t *h, int32_t variant);
+
+/*
+ * Autotuner: time every compiled variant for `steps` steps (1..10000) with
+ * HIP events on the handle's stream, keep the fastest.  The state is saved
+ * to `scratch` (device, >= q*nx*ny*sizeof(storage) bytes, caller-owned)
+ * before the trials and restored after each one, so the handle's state
+ * and step count are unchanged; statistics are reset.  Writes the chosen
+ * variant and its time per step (ms); either output may be NULL.  Waits
+ * for the stream.  Errors: EINVAL, EDEVICE.
+ */
+int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
+                        int32_t steps, int32_t *best_variant,
+                        double *best_ms_per_step);
 
 /* Free the handle (host memory only; the workspace stays the caller's).
    Waits for the stream. */

@@ -53,8 +53,8 @@ static R RN(dphi_)(R th, R tm, R delta) {
  * brackets it.  In the quadratic phase every Newton step is kept, so the
  * iterates are those of the plain method.
  *
- * Stops when |theta^(k+1) - theta^(k)| <= tol and returns the last
- * candidate; *iters counts the candidates computed.
+ * Stops when |theta^(k+1) - theta^(k)| <= tol, then takes one more
+ * Newton step (below); *iters counts the candidates before it.
  */
 static R RN(newton_)(R m0, R th, R ste, R tm, R delta, double tol,
                      int max_it, int mode, int *iters, int *conv,
@@ -97,15 +97,16 @@ static R RN(newton_)(R m0, R th, R ste, R tm, R delta, double tol,
     cur = cand;
   }
   *iters = k;
-#if CS
-  /* complex step: one more Newton step from the converged iterate makes
-     the imaginary part the implicit-function derivative to O(tol). */
-  {
+  /* A solve that stops on a bisection step is only within tol of the
+     root.  One more Newton step from the converged iterate returns the
+     root itself to rounding (error ~ tol^2 F''/F'), so the result does
+     not depend on the path the safeguard took; in the complex-step build
+     it also makes the imaginary part the implicit-function derivative. */
+  if (*conv) {
     R ph = RN(phi_)(cand, tm, delta);
     R dph = RN(dphi_)(cand, tm, delta);
     cand = cand - (cand + ph / ste - c) / (1.0 + dph / ste);
   }
-#endif
   return cand;
 }
 

@@ -72,6 +72,9 @@ SIGNATURES = {
     "lbm_stefan_variant_name": (ctypes.c_char_p, [ctypes.c_int32, ctypes.c_int32,
                                                   ctypes.c_int32]),
     "lbm_stefan_set_variant": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_stefan_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           _c_double_p]),
     "lbm_stefan_destroy": (ctypes.c_int, [_vp]),
 }
 

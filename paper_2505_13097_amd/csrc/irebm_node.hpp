@@ -116,7 +116,7 @@ __device__ inline double phi_only(double t, double tm, double inv_delta) {
 // (Press et al., Numerical Recipes, sec. 9.4): bracket [c - 1/Ste, c]
 // (F' >= 1 and 0 <= phi <= 1 make it valid), bisect when the step leaves
 // the bracket or fails to halve the step before the last.  Stops when
-// |t_{k+1} - t_k| <= tol; returns the last candidate.
+// |t_{k+1} - t_k| <= tol, then takes one more Newton step (below).
 template <bool PLAIN>
 __device__ inline double newton(double m0, double th, double pth,
                                 const StepArgs &A, int &iters, bool &conv) {
@@ -155,6 +155,15 @@ __device__ inline double newton(double m0, double th, double pth,
     cur = cand;
   }
   iters = k;
+  // one more Newton step from the converged iterate: a solve that stopped
+  // on a bisection step is then the root to rounding, not any point within
+  // tol of it, so the result does not depend on the safeguard's path
+  if (conv) {
+    double ph, dph;
+    phi_dphi(cand, A.tm, A.inv_delta, ph, dph);
+    const double F = cand + ph * s - c;
+    cand -= (dph == 0.0) ? F : F / (1.0 + dph * s);
+  }
   return cand;
 }
 
@@ -165,11 +174,6 @@ struct NodeStats {
   double flux_in = 0.0;
   double flux_out = 0.0;
 };
-
-template <typename S>
-__device__ inline double ld(const S *p) {
-  return (double)*p;
-}
 
 // Raw loads of one node: own populations (for T) and pulled ones.
 template <int Q, typename S>

@@ -833,6 +833,69 @@ int lbm_stefan_set_variant(lbm_stefan_t *h, int32_t variant) {
   return LBM_STEFAN_OK;
 }
 
+int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
+                        int32_t steps, int32_t *best_variant,
+                        double *best_ms_per_step) {
+  if (!h) return fail(nullptr, LBM_STEFAN_EINVAL, "handle is NULL");
+  const lbm_stefan_params &p = h->p;
+  const size_t sb = p.storage == LBM_STORE_F64 ? 8 : 4;
+  const size_t bytes = (size_t)p.q * p.nx * p.ny * sb;
+  if (!scratch || scratch_bytes < bytes)
+    return fail(h, LBM_STEFAN_EINVAL, "scratch smaller than the state");
+  if (steps < 1 || steps > 10000)
+    return fail(h, LBM_STEFAN_EINVAL, "steps must be in 1..10000");
+  DeviceGuard g(h->device);
+  int nv;
+  variants(p.q, &nv);
+  const int cur0 = h->cur;
+  HIPCHK(h, hipMemcpyAsync(scratch, h->buf[cur0], bytes,
+                           hipMemcpyDeviceToDevice, h->stream));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(h, LBM_STEFAN_EDEVICE, "hipEventCreate failed");
+  }
+  int best = h->variant;
+  float best_ms = 0.0f;
+  hipError_t err = hipSuccess;
+  for (int v = 0; v < nv && err == hipSuccess; ++v) {
+    h->variant = v;
+    // two untimed steps, then the timed trial
+    for (int s = 0; s < steps + 2 && err == hipSuccess; ++s) {
+      if (s == 2) err = hipEventRecord(e0, h->stream);
+      if (err == hipSuccess)
+        err = launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]);
+      h->cur ^= 1;
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, h->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && (v == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = v;
+    }
+    // restore the saved state for the next trial
+    h->cur = cur0;
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(h->buf[cur0], scratch, bytes,
+                           hipMemcpyDeviceToDevice, h->stream);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->cur = cur0;
+  h->variant = best;
+  if (err != hipSuccess)
+    return fail(h, LBM_STEFAN_EDEVICE,
+                std::string("autotune: ") + hipGetErrorString(err));
+  HIPCHK(h, zero_stats_async(h));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (best_variant) *best_variant = best;
+  if (best_ms_per_step) *best_ms_per_step = best_ms / steps;
+  return LBM_STEFAN_OK;
+}
+
 int lbm_stefan_destroy(lbm_stefan_t *h) {
   if (!h) return LBM_STEFAN_OK;
   DeviceGuard g(h->device);

@@ -164,6 +164,19 @@ class Stefan:
     def set_variant(self, v):
         C.check(self._lib.lbm_stefan_set_variant(self.h, int(v)), self.h)
 
+    def autotune(self, steps=10):
+        """Time every kernel variant on this lattice and keep the fastest;
+        the state is saved and restored.  Returns (variant, ms per step)."""
+        nbytes = self.prob.q * self.prob.nodes * (8 if self.prob.storage == "f64" else 4)
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        v = ctypes.c_int32()
+        ms = ctypes.c_double()
+        C.check(self._lib.lbm_stefan_autotune(
+            self.h, ctypes.c_void_p(scratch.data_ptr()), nbytes, int(steps),
+            ctypes.byref(v), ctypes.byref(ms)), self.h)
+        del scratch
+        return v.value, ms.value
+
     def close(self):
         if getattr(self, "h", None):
             C.check(self._lib.lbm_stefan_destroy(self.h))
