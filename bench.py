@@ -74,6 +74,50 @@ def time_plain(prob, steps, warmup, variant=-1, autotune=True):
             "tuned": tuned}
 
 
+def time_batched(probs, steps, warmup, autotune=True, graph_steps=100):
+    """The batched form: all instances advanced by one persistent launch
+    per step, replayed from a captured hipGraph of graph_steps launches."""
+    import torch
+    from paper_2505_13097_amd import StefanBatch, variant_names
+    b = StefanBatch(probs)
+    tuned = None
+    v, bpc = -1, 4
+    if autotune:
+        v, bpc, ms = b.autotune(steps=3)
+        tuned = {"variant": variant_names(probs[0].q, probs[0].storage)[v],
+                 "blocks_per_cu": bpc, "ms_per_step": round(ms, 4)}
+    b.set_schedule(v, bpc, graph_steps)
+    b.step(warmup)
+    b.reset_stats()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    b.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = b.stats()
+    b.close()
+    nodes = sum(p.nodes for p in probs)
+    bpn = bytes_per_node(probs[0])
+    gpu_ms = ev0.elapsed_time(ev1)
+    return {
+        "workload": f"batch{len(probs)}_d2q5_{probs[0].storage}",
+        "instances": len(probs), "nodes": nodes, "steps": steps,
+        "value": round(nodes * steps / (t1 - t0) / 1e6, 1), "unit": "MLUPS",
+        "hbm_gbps_algorithmic": round(nodes * bpn * steps / (gpu_ms * 1e-3) / 1e9, 1),
+        "frac_of_peak": round(nodes * bpn * steps / (gpu_ms * 1e-3) / 1e9 /
+                              HBM_PEAK_GBPS, 4),
+        "ms_per_step": round(gpu_ms / steps, 4),
+        "graph_steps": graph_steps, "autotune": tuned,
+        "nonconverged": int(sum(s["nonconverged"] for s in st)),
+        "max_newton_it": int(max(s["max_newton_it"] for s in st)),
+    }
+
+
 def cpu_baseline(prob, steps=1):
     """The oracle, as it stands, on `steps` steps of the same lattice from
     the same initial state (single thread)."""
@@ -99,6 +143,10 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--forms", default="plain,batched",
+                    help="comma list of extra forms to time: batched, adjoint")
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
@@ -179,6 +227,16 @@ def main():
             "max_residual": r["stats"]["max_residual"],
         },
     }
+    forms = {}
+    if "batched" in args.forms.split(","):
+        import synth as S
+        print(f"[bench] batched form: {args.batch_count} instances, "
+              f"{args.batch_steps} steps", file=sys.stderr, flush=True)
+        probs = S.batch_table(count=args.batch_count, nsteps=args.batch_steps)
+        forms["batched"] = time_batched(probs, args.batch_steps, 10)
+        print("[bench] batched done", file=sys.stderr, flush=True)
+    if forms:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, 1 if prob.nodes > 1e6 else 200)

@@ -226,6 +226,86 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
    Waits for the stream. */
 int lbm_stefan_destroy(lbm_stefan_t *h);
 
+/* ---------------------------------------------------------------------
+ * Batched form: many independent lattices with their own sizes and
+ * parameters, advanced together by one persistent kernel launch per time
+ * step (optionally replayed from a captured hipGraph).  Every instance is
+ * stepped by exactly the arithmetic of the single-lattice step (Algorithm
+ * 3, Section 4.1; closures of Section 4.2): a batch member evolves
+ * bit-identically to the same lattice run alone.  Instances must share
+ * q, storage and newton_mode; everything else may differ.  The variant
+ * field of the params is ignored (the batch has one schedule).
+ * --------------------------------------------------------------------- */
+typedef struct lbm_stefan_batch lbm_stefan_batch_t;
+
+/* Workspace for `count` instances (params array of length count).
+   Errors: EINVAL (an invalid instance, mixed q/storage/newton_mode). */
+int lbm_stefan_batch_workspace_bytes(const lbm_stefan_params *params,
+                                     int32_t count, size_t *bytes);
+
+/*
+ * Create a batch: equilibrium initial state of every instance, as in
+ * lbm_stefan_init.  T0: host, nullable array of `count` nullable host
+ * arrays [ny_k][nx_k].  workspace: device, 256-byte aligned, >= the size
+ * above, owned by the caller.  Default schedule: the library's default
+ * variant, 4 blocks per compute unit, no graph.  Blocks until built.
+ */
+int lbm_stefan_batch_init(const lbm_stefan_params *params, int32_t count,
+                          const double *const *T0, void *workspace,
+                          size_t bytes, void *stream,
+                          lbm_stefan_batch_t **out);
+
+/*
+ * Schedule: kernel variant (-1: default), persistent grid of
+ * blocks_per_cu x compute units (1..32), and graph_steps (even, 0..1e5):
+ * when > 0, lbm_stefan_batch_step replays a captured hipGraph of that many
+ * launches (captured on first use) and launches any remainder directly.
+ * Changing the variant resets statistics.
+ */
+int lbm_stefan_batch_set_schedule(lbm_stefan_batch_t *b, int32_t variant,
+                                  int32_t blocks_per_cu, int32_t graph_steps);
+
+/* Advance every instance nsteps (asynchronous on the batch's stream). */
+int lbm_stefan_batch_step(lbm_stefan_batch_t *b, int64_t nsteps);
+
+/* Per-instance statistics (out: host, count entries), as for a single
+   lattice.  Waits for the stream.  Errors: ENAN, EDEVICE. */
+int lbm_stefan_batch_stats(lbm_stefan_batch_t *b, lbm_stefan_stats *out);
+
+/* Zero every instance's Newton and flux accumulators. */
+int lbm_stefan_batch_reset_stats(lbm_stefan_batch_t *b);
+
+/* Front (host, ny_k doubles, nullable) and energy (host, nullable) of one
+   instance; as lbm_stefan_query_front. */
+int lbm_stefan_batch_query_front(lbm_stefan_batch_t *b, int32_t inst,
+                                 int32_t mode, double *front, double *energy);
+
+/* One instance's field, as lbm_stefan_get_field. */
+int lbm_stefan_batch_get_field(lbm_stefan_batch_t *b, int32_t inst,
+                               int32_t what, void *host);
+
+/* Bytes of all instances' current states together (autotune scratch). */
+int lbm_stefan_batch_state_bytes(const lbm_stefan_batch_t *b, size_t *bytes);
+
+/*
+ * Autotuner of the batched kernel: times every (variant, blocks per CU in
+ * {1, 2, 4, 8}) pair for `steps` steps with HIP events, saving the states
+ * to `scratch` (device, >= lbm_stefan_batch_state_bytes) and restoring
+ * them after each trial; keeps the fastest pair (the graph length is
+ * kept).  Outputs are nullable.  Resets statistics.  Waits for the stream.
+ */
+int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
+                              size_t scratch_bytes, int32_t steps,
+                              int32_t *best_variant,
+                              int32_t *best_blocks_per_cu,
+                              double *best_ms_per_step);
+
+/* Text of the batch's last error (NULL: as lbm_stefan_last_error(NULL)). */
+const char *lbm_stefan_batch_last_error(const lbm_stefan_batch_t *b);
+
+/* Free the batch (host memory and its graphs).  Waits for the stream. */
+int lbm_stefan_batch_destroy(lbm_stefan_batch_t *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,30 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int32),
                                            _c_double_p]),
     "lbm_stefan_destroy": (ctypes.c_int, [_vp]),
+    "lbm_stefan_batch_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int32,
+                                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_stefan_batch_init": (ctypes.c_int, [_P, ctypes.c_int32,
+                                             ctypes.POINTER(_c_double_p), _vp,
+                                             ctypes.c_size_t, _vp,
+                                             ctypes.POINTER(_vp)]),
+    "lbm_stefan_batch_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                                     ctypes.c_int32, ctypes.c_int32]),
+    "lbm_stefan_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "lbm_stefan_batch_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+    "lbm_stefan_batch_reset_stats": (ctypes.c_int, [_vp]),
+    "lbm_stefan_batch_query_front": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                                    ctypes.c_int32, _c_double_p,
+                                                    _c_double_p]),
+    "lbm_stefan_batch_get_field": (ctypes.c_int, [_vp, ctypes.c_int32,
+                                                  ctypes.c_int32, _vp]),
+    "lbm_stefan_batch_state_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_stefan_batch_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t,
+                                                 ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 _c_double_p]),
+    "lbm_stefan_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "lbm_stefan_batch_destroy": (ctypes.c_int, [_vp]),
 }
 
 _lib = None
@@ -112,4 +136,10 @@ class LbmError(RuntimeError):
 def check(rc, handle=None):
     if rc != OK:
         msg = lib().lbm_stefan_last_error(handle)
+        raise LbmError(rc, msg.decode() if msg else "")
+
+
+def check_batch(rc, batch=None):
+    if rc != OK:
+        msg = lib().lbm_stefan_batch_last_error(batch)
         raise LbmError(rc, msg.decode() if msg else "")

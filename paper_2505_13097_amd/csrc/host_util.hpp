@@ -1,0 +1,157 @@
+// host_util.hpp -- host-side helpers shared by the translation units of
+// the library: kernel variant table, type dispatch, error macro, device
+// guard and small launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "lbm_stefan.h"
+
+namespace irebm {
+
+// A kernel variant: block of bx x by threads, each thread updating npt
+// nodes bx apart along x; the tile is (bx * npt) x by nodes.
+struct Variant {
+  int bx, by, npt;
+};
+
+inline const Variant *variants(int q, int *n) {
+  static const Variant v1[] = {{256, 1, 1}, {128, 1, 1}, {64, 1, 1},
+                               {256, 1, 2}};
+  static const Variant v2[] = {{64, 4, 1},  {256, 1, 1}, {128, 2, 1},
+                               {64, 4, 2},  {128, 2, 2}, {256, 1, 2},
+                               {64, 2, 2},  {64, 4, 4}};
+  if (q == 3) {
+    *n = (int)(sizeof(v1) / sizeof(Variant));
+    return v1;
+  }
+  *n = (int)(sizeof(v2) / sizeof(Variant));
+  return v2;
+}
+constexpr int kDefaultVariant1D = 0;
+constexpr int kDefaultVariant2D = 3;
+
+inline int64_t tiles_x_for(const Variant &v, int64_t nx) {
+  const int64_t tw = (int64_t)v.bx * v.npt;
+  return (nx + tw - 1) / tw;
+}
+inline int64_t tiles_for(const Variant &v, int64_t nx, int64_t ny) {
+  return tiles_x_for(v, nx) * ((ny + v.by - 1) / v.by);
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline unsigned blocks_for(int64_t n, int t) {
+  return (unsigned)((n + t - 1) / t);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess || prev == dev ||
+        hipSetDevice(dev) != hipSuccess)
+      prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <int Q>
+using QT = std::integral_constant<int, Q>;
+template <typename T>
+struct TT {
+  using type = T;
+};
+
+// calls f(QT<Q>{}, TT<S>{}) for a lattice and a storage type
+template <typename F>
+hipError_t dispatch_qs(int q, int storage, F &&f) {
+  const bool f32 = storage == LBM_STORE_F32;
+  switch (q) {
+    case 3:
+      return f32 ? f(QT<3>{}, TT<float>{}) : f(QT<3>{}, TT<double>{});
+    case 5:
+      return f32 ? f(QT<5>{}, TT<float>{}) : f(QT<5>{}, TT<double>{});
+    default:
+      return f32 ? f(QT<9>{}, TT<float>{}) : f(QT<9>{}, TT<double>{});
+  }
+}
+
+#define QS_TYPES(qt, tt)                  \
+  constexpr int Q = decltype(qt)::value; \
+  using S = typename decltype(tt)::type
+
+inline hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 8);
+  if (n <= 0) return hipSuccess;
+  zero_kernel<<<blocks_for(n, 256), 256, 0, s>>>((uint64_t *)p, n);
+  return hipGetLastError();
+}
+
+// E = sum [T + phi(T)/Ste] of n nodes of state `src` into *out (device),
+// using `partials` (>= ceil(n / kEnergyChunk) doubles) as scratch
+inline hipError_t energy_async(int q, int storage, const void *src, int64_t n,
+                               double tm, double delta, double ste,
+                               double *partials, double *out,
+                               hipStream_t stream) {
+  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    const int64_t parts = (n + kEnergyChunk - 1) / kEnergyChunk;
+    energy_partial_kernel<Q, S><<<(unsigned)parts, 256, 0, stream>>>(
+        (const S *)src, n, tm, 1.0 / delta, 1.0 / ste, partials);
+    sum_kernel<<<1, 256, 0, stream>>>(partials, parts, out);
+    return hipGetLastError();
+  });
+}
+
+// per-row front of an nx x ny state into out[0..ny) (device)
+inline hipError_t front_async(int q, int storage, const void *src, int64_t nx,
+                              int64_t ny, int mode, double tm, double delta,
+                              double dx, double *out, hipStream_t stream) {
+  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    if (mode == LBM_FRONT_LIQUID_INTEGRAL)
+      front_integral_kernel<Q, S><<<(unsigned)ny, 256, 0, stream>>>(
+          (const S *)src, nx * ny, (int)nx, tm, 1.0 / delta, dx, out);
+    else
+      front_crossing_kernel<Q, S><<<(unsigned)ny, 256, 0, stream>>>(
+          (const S *)src, nx * ny, (int)nx, tm, dx, out);
+    return hipGetLastError();
+  });
+}
+
+// T = sum_i Omega_i of n nodes into T (device doubles)
+inline hipError_t temperature_async(int q, int storage, const void *src,
+                                    int64_t n, double *T, hipStream_t stream) {
+  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    temp_kernel<Q, S><<<blocks_for(n, 256), 256, 0, stream>>>(
+        (const S *)src, n, T);
+    return hipGetLastError();
+  });
+}
+
+// equilibrium initial state of the lattice described by A (A.dst)
+inline hipError_t init_async(int q, int storage, const StepArgs &A,
+                             const double *T0, hipStream_t stream) {
+  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    init_kernel<Q, S><<<blocks_for(A.plane, 256), 256, 0, stream>>>(A, T0);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace irebm
+
+#define HIPCHK(h, expr)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return irebm::fail((h), LBM_STEFAN_EDEVICE,                         \
+                         std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)

@@ -1,0 +1,294 @@
+// kernels.hpp -- gfx950 kernels of the IREBM step and its reductions.
+// Included by each translation unit of the library; the kernels sit in an
+// anonymous namespace so every unit registers its own copies.
+//
+//   step_kernel      one time step, one launch; each block owns one tile of
+//                    the lattice (tile_x = bx * npt columns, tile_y = by
+//                    rows).  Blocks are remapped so that each of the eight
+//                    XCDs sweeps one contiguous band of tile rows: the rows
+//                    a tile pulls from its neighbours then sit in that
+//                    XCD's L2.  Interior tiles take a path with no bounds
+//                    checks.  Per-tile Newton and flux statistics are
+//                    accumulated by the owning block (no atomics).
+//   init_kernel      equilibrium state from a temperature field.
+//   temp_kernel      T = sum_i Omega_i.
+//   energy_*         E = sum [T + phi(T)/Ste], two fixed-order passes.
+//   front_*          per-row front position.
+//   stats_kernel     fixed-order reduction of per-tile slots.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "irebm_node.hpp"
+
+namespace irebm {
+
+constexpr int kEnergyChunk = 2048;  // nodes per energy partial
+
+// Statistics of one block (already reduced over the node loop of each
+// thread), combined across the block and added to the tile's slot by
+// thread 0.
+__device__ inline void block_stats_to_slot(const NodeStats &st, bool fast,
+                                           StatSlot *sl) {
+  __shared__ int s_it[4], s_nc[4];
+  __shared__ double s_res[4], s_fin[4], s_fout[4];
+  const int lin = (int)(threadIdx.x + threadIdx.y * blockDim.x);
+  const int wid = lin >> 6, nw = (int)(blockDim.x * blockDim.y) >> 6;
+  const int it = wave_max_i(st.max_it);
+  const int nc = wave_sum_i(st.nonconv);
+  const double res = wave_max(st.max_res);
+  double fin = 0.0, fout = 0.0;
+  if (!fast) {
+    fin = wave_sum(st.flux_in);
+    fout = wave_sum(st.flux_out);
+  }
+  if ((lin & 63) == 0) {
+    s_it[wid] = it;
+    s_nc[wid] = nc;
+    s_res[wid] = res;
+    s_fin[wid] = fin;
+    s_fout[wid] = fout;
+  }
+  __syncthreads();
+  if (lin == 0) {
+    int bit = s_it[0], bnc = s_nc[0];
+    double bres = s_res[0], bfin = s_fin[0], bfout = s_fout[0];
+    for (int w = 1; w < nw; ++w) {
+      bit = max(bit, s_it[w]);
+      bnc += s_nc[w];
+      bres = fmax(bres, s_res[w]);
+      bfin += s_fin[w];
+      bfout += s_fout[w];
+    }
+    sl->max_it = max(sl->max_it, bit);
+    sl->nonconv += bnc;
+    sl->max_res = fmax(sl->max_res, bres);
+    if (!fast) {
+      sl->flux_in += bfin;
+      sl->flux_out += bfout;
+    }
+  }
+  __syncthreads();
+}
+
+// One tile (tx, ty) of the lattice described by A: load, update, stats.
+template <int Q, typename S, int NPT, bool PLAIN>
+__device__ inline void step_tile(const StepArgs &A, int tx, int ty,
+                                 StatSlot *slot) {
+  const int bx = blockDim.x, by = blockDim.y;
+  const int TW = bx * NPT;
+  const int x0 = tx * TW, y0 = ty * by;
+  const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
+                    (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
+  const int y = y0 + (int)threadIdx.y;
+  NodeStats st;
+  if (fast) {
+    NodeLoad<Q, S> L[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      load_node<Q, S, true>(A, x0 + (int)threadIdx.x + k * bx, y, L[k]);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      update_node<Q, S, PLAIN, true>(A, x0 + (int)threadIdx.x + k * bx, y,
+                                     L[k], st);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int x = x0 + (int)threadIdx.x + k * bx;
+      if (x < A.nx && y < A.ny) {
+        NodeLoad<Q, S> L;
+        load_node<Q, S, false>(A, x, y, L);
+        update_node<Q, S, PLAIN, false>(A, x, y, L, st);
+      }
+    }
+  }
+  block_stats_to_slot(st, fast, slot);
+}
+
+namespace {
+
+
+// one time step of one lattice; block b works on tile
+// (b mod 8) * per_xcd + b div 8 (XCD-aware order)
+template <int Q, typename S, int NPT, bool PLAIN>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
+  const int b = blockIdx.x;
+  const int t = (b & 7) * A.per_xcd + (b >> 3);
+  if (t >= A.ntiles) return;
+  step_tile<Q, S, NPT, PLAIN>(A, t % A.tiles_x, t / A.tiles_x, A.slots + t);
+}
+
+// ---------------------------------------------------------------------
+// init, temperature, zero fill
+
+template <int Q, typename S>
+__global__ void init_kernel(StepArgs A, const double *T0) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= A.plane) return;
+  const int x = (int)(k % A.nx), y = (int)(k / A.nx);
+  const int wall = dirichlet_wall<Q>(A, x, y);
+  const double T = wall >= 0 ? wall_value(A, wall, x, y) : (T0 ? T0[k] : 0.0);
+  S *dst = (S *)A.dst;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dst[i * A.plane + k] = (S)(wt<Q>(i) * T);
+}
+
+template <int Q, typename S>
+__global__ void temp_kernel(const S *src, int64_t plane, double *T) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= plane) return;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) s += (double)src[j * plane + k];
+  T[k] = s;
+}
+
+__global__ void zero_kernel(uint64_t *p, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
+// ---------------------------------------------------------------------
+// fixed-order reductions
+
+__device__ inline double block_sum_256(double v) {
+  __shared__ double s[4];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s[w] = v;
+  __syncthreads();
+  double r = s[0] + s[1] + s[2] + s[3];
+  __syncthreads();
+  return r;
+}
+
+// partial[b] = sum over nodes [b*chunk, (b+1)*chunk) of T + phi(T)/Ste
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void energy_partial_kernel(
+    const S *src, int64_t plane, double tm, double inv_delta, double inv_ste,
+    double *partial) {
+  const int64_t base = (int64_t)blockIdx.x * kEnergyChunk;
+  double acc = 0.0;
+  for (int j = 0; j < kEnergyChunk / 256; ++j) {
+    const int64_t k = base + j * 256 + threadIdx.x;
+    if (k < plane) {
+      double T = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
+      acc += T + phi_only(T, tm, inv_delta) * inv_ste;
+    }
+  }
+  const double s = block_sum_256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_kernel(const double *partial,
+                                                  int64_t n, double *out) {
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) acc += partial[k];
+  const double s = block_sum_256(acc);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// out: max_it, nonconv, max_res, flux_in, flux_out (as doubles)
+__global__ __launch_bounds__(256) void stats_kernel(const StatSlot *slots,
+                                                    int64_t n, double *out) {
+  int it = 0;
+  double nc = 0.0, res = 0.0, fin = 0.0, fout = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) {
+    const StatSlot s = slots[k];
+    it = max(it, s.max_it);
+    nc += (double)s.nonconv;
+    res = fmax(res, s.max_res);
+    fin += s.flux_in;
+    fout += s.flux_out;
+  }
+  __shared__ int s_it[4];
+  __shared__ double s_res[4];
+  it = wave_max_i(it);
+  res = wave_max(res);
+  if ((threadIdx.x & 63) == 0) {
+    s_it[threadIdx.x >> 6] = it;
+    s_res[threadIdx.x >> 6] = res;
+  }
+  const double snc = block_sum_256(nc);
+  const double sfin = block_sum_256(fin);
+  const double sfout = block_sum_256(fout);
+  if (threadIdx.x == 0) {
+    out[0] = (double)max(max(s_it[0], s_it[1]), max(s_it[2], s_it[3]));
+    out[1] = snc;
+    out[2] = fmax(fmax(s_res[0], s_res[1]), fmax(s_res[2], s_res[3]));
+    out[3] = sfin;
+    out[4] = sfout;
+  }
+}
+
+// front of row blockIdx.x: dx * trapezoid sum of phi(T)
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void front_integral_kernel(
+    const S *src, int64_t plane, int nx, double tm, double inv_delta,
+    double dx, double *out) {
+  const int64_t row = (int64_t)blockIdx.x * nx;
+  double acc = 0.0;
+  for (int x = threadIdx.x; x < nx; x += 256) {
+    double T = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) T += (double)src[i * plane + row + x];
+    const double ph = phi_only(T, tm, inv_delta);
+    acc += (x == 0 || x == nx - 1) ? 0.5 * ph : ph;
+  }
+  const double s = block_sum_256(acc);
+  if (threadIdx.x == 0) out[blockIdx.x] = dx * s;
+}
+
+template <int Q, typename S>
+__device__ inline double temp_at(const S *src, int64_t plane, int64_t k) {
+  double T = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
+  return T;
+}
+
+// first x (from x = 0) with T(x) - tm > 0 >= T(x+1) - tm, interpolated
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void front_crossing_kernel(
+    const S *src, int64_t plane, int nx, double tm, double dx, double *out) {
+  const int64_t row = (int64_t)blockIdx.x * nx;
+  const int chunk = (nx + 255) / 256;
+  const int xa = threadIdx.x * chunk;
+  int first = INT32_MAX;
+  for (int x = xa; x < xa + chunk && x + 1 < nx; ++x) {
+    const double t0 = temp_at<Q, S>(src, plane, row + x) - tm;
+    const double t1 = temp_at<Q, S>(src, plane, row + x + 1) - tm;
+    if (t0 > 0.0 && t1 <= 0.0) {
+      first = x;
+      break;
+    }
+  }
+  __shared__ int s_min[4];
+  int m = first;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+    const double T0 = temp_at<Q, S>(src, plane, row) - tm;
+    double pos;
+    if (T0 <= 0.0) {
+      pos = 0.0;
+    } else if (m == INT32_MAX) {
+      pos = (nx - 1) * dx;
+    } else {
+      const double t0 = temp_at<Q, S>(src, plane, row + m) - tm;
+      const double t1 = temp_at<Q, S>(src, plane, row + m + 1) - tm;
+      pos = dx * (m + t0 / (t0 - t1));
+    }
+    out[blockIdx.x] = pos;
+  }
+}
+
+}  // namespace
+}  // namespace irebm

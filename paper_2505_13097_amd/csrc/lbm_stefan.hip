@@ -2,20 +2,8 @@
 // (Luddens, Lothode, Danaila, arXiv 2505.13097, Algorithm 3 with the
 // boundary closures of Section 4.2).  See include/lbm_stefan.h.
 //
-// Kernels
-//   step_kernel      one time step, one launch; each block owns one tile of
-//                    the lattice (tile_x = bx * npt columns, tile_y = by
-//                    rows).  Blocks are remapped so that each of the eight
-//                    XCDs sweeps one contiguous band of tile rows: the rows
-//                    a tile pulls from its neighbours then sit in that
-//                    XCD's L2.  Interior tiles take a path with no bounds
-//                    checks.  Per-tile Newton and flux statistics are
-//                    accumulated by the owning block (no atomics).
-//   init_kernel      equilibrium state from a temperature field.
-//   temp_kernel      T = sum_i Omega_i.
-//   energy_*         E = sum [T + phi(T)/Ste], two fixed-order passes.
-//   front_*          per-row front position.
-//   stats_kernel     fixed-order reduction of the per-tile slots.
+// The kernels are in kernels.hpp; this unit holds the host side of the
+// single-lattice handle.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,266 +14,13 @@
 #include <string>
 #include <type_traits>
 
-#include "irebm_node.hpp"
+#include "host_util.hpp"
+#include "kernels.hpp"
 #include "lbm_stefan.h"
 #include "lbm_stefan_internal.hpp"
 
 using namespace irebm;
 
-namespace irebm {
-
-constexpr int kEnergyChunk = 2048;  // nodes per energy partial
-
-// ---------------------------------------------------------------------
-// step
-
-template <int Q, typename S, int NPT, bool PLAIN>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
-  const int b = blockIdx.x;
-  const int t = (b & 7) * A.per_xcd + (b >> 3);
-  if (t >= A.ntiles) return;
-  const int bx = blockDim.x, by = blockDim.y;
-  const int TW = bx * NPT;
-  const int tx = t % A.tiles_x, ty = t / A.tiles_x;
-  const int x0 = tx * TW, y0 = ty * by;
-  const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
-                    (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
-  const int y = y0 + (int)threadIdx.y;
-  NodeStats st;
-  if (fast) {
-    NodeLoad<Q, S> L[NPT];
-#pragma unroll
-    for (int k = 0; k < NPT; ++k)
-      load_node<Q, S, true>(A, x0 + (int)threadIdx.x + k * bx, y, L[k]);
-#pragma unroll
-    for (int k = 0; k < NPT; ++k)
-      update_node<Q, S, PLAIN, true>(A, x0 + (int)threadIdx.x + k * bx, y,
-                                     L[k], st);
-  } else {
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int x = x0 + (int)threadIdx.x + k * bx;
-      if (x < A.nx && y < A.ny) {
-        NodeLoad<Q, S> L;
-        load_node<Q, S, false>(A, x, y, L);
-        update_node<Q, S, PLAIN, false>(A, x, y, L, st);
-      }
-    }
-  }
-  // block reduction of the statistics, then one read-modify-write of the
-  // tile's slot by thread 0
-  __shared__ int s_it[4], s_nc[4];
-  __shared__ double s_res[4], s_fin[4], s_fout[4];
-  const int lin = (int)(threadIdx.x + threadIdx.y * blockDim.x);
-  const int wid = lin >> 6, nw = (bx * by) >> 6;
-  const int it = wave_max_i(st.max_it);
-  const int nc = wave_sum_i(st.nonconv);
-  const double res = wave_max(st.max_res);
-  double fin = 0.0, fout = 0.0;
-  if (!fast) {
-    fin = wave_sum(st.flux_in);
-    fout = wave_sum(st.flux_out);
-  }
-  if ((lin & 63) == 0) {
-    s_it[wid] = it;
-    s_nc[wid] = nc;
-    s_res[wid] = res;
-    s_fin[wid] = fin;
-    s_fout[wid] = fout;
-  }
-  __syncthreads();
-  if (lin == 0) {
-    int bit = s_it[0], bnc = s_nc[0];
-    double bres = s_res[0], bfin = s_fin[0], bfout = s_fout[0];
-    for (int w = 1; w < nw; ++w) {
-      bit = max(bit, s_it[w]);
-      bnc += s_nc[w];
-      bres = fmax(bres, s_res[w]);
-      bfin += s_fin[w];
-      bfout += s_fout[w];
-    }
-    StatSlot *sl = A.slots + t;
-    sl->max_it = max(sl->max_it, bit);
-    sl->nonconv += bnc;
-    sl->max_res = fmax(sl->max_res, bres);
-    if (!fast) {
-      sl->flux_in += bfin;
-      sl->flux_out += bfout;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------
-// init, temperature, zero fill
-
-template <int Q, typename S>
-__global__ void init_kernel(StepArgs A, const double *T0) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= A.plane) return;
-  const int x = (int)(k % A.nx), y = (int)(k / A.nx);
-  const int wall = dirichlet_wall<Q>(A, x, y);
-  const double T = wall >= 0 ? wall_value(A, wall, x, y) : (T0 ? T0[k] : 0.0);
-  S *dst = (S *)A.dst;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) dst[i * A.plane + k] = (S)(wt<Q>(i) * T);
-}
-
-template <int Q, typename S>
-__global__ void temp_kernel(const S *src, int64_t plane, double *T) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= plane) return;
-  double s = 0.0;
-#pragma unroll
-  for (int j = 0; j < Q; ++j) s += (double)src[j * plane + k];
-  T[k] = s;
-}
-
-__global__ void zero_kernel(uint64_t *p, int64_t n) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = 0;
-}
-
-// ---------------------------------------------------------------------
-// fixed-order reductions
-
-__device__ inline double block_sum_256(double v) {
-  __shared__ double s[4];
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) s[w] = v;
-  __syncthreads();
-  double r = s[0] + s[1] + s[2] + s[3];
-  __syncthreads();
-  return r;
-}
-
-// partial[b] = sum over nodes [b*chunk, (b+1)*chunk) of T + phi(T)/Ste
-template <int Q, typename S>
-__global__ __launch_bounds__(256) void energy_partial_kernel(
-    const S *src, int64_t plane, double tm, double inv_delta, double inv_ste,
-    double *partial) {
-  const int64_t base = (int64_t)blockIdx.x * kEnergyChunk;
-  double acc = 0.0;
-  for (int j = 0; j < kEnergyChunk / 256; ++j) {
-    const int64_t k = base + j * 256 + threadIdx.x;
-    if (k < plane) {
-      double T = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
-      acc += T + phi_only(T, tm, inv_delta) * inv_ste;
-    }
-  }
-  const double s = block_sum_256(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-__global__ __launch_bounds__(256) void sum_kernel(const double *partial,
-                                                  int64_t n, double *out) {
-  double acc = 0.0;
-  for (int64_t k = threadIdx.x; k < n; k += 256) acc += partial[k];
-  const double s = block_sum_256(acc);
-  if (threadIdx.x == 0) *out = s;
-}
-
-// out: max_it, nonconv, max_res, flux_in, flux_out (as doubles)
-__global__ __launch_bounds__(256) void stats_kernel(const StatSlot *slots,
-                                                    int64_t n, double *out) {
-  int it = 0;
-  double nc = 0.0, res = 0.0, fin = 0.0, fout = 0.0;
-  for (int64_t k = threadIdx.x; k < n; k += 256) {
-    const StatSlot s = slots[k];
-    it = max(it, s.max_it);
-    nc += (double)s.nonconv;
-    res = fmax(res, s.max_res);
-    fin += s.flux_in;
-    fout += s.flux_out;
-  }
-  __shared__ int s_it[4];
-  __shared__ double s_res[4];
-  it = wave_max_i(it);
-  res = wave_max(res);
-  if ((threadIdx.x & 63) == 0) {
-    s_it[threadIdx.x >> 6] = it;
-    s_res[threadIdx.x >> 6] = res;
-  }
-  const double snc = block_sum_256(nc);
-  const double sfin = block_sum_256(fin);
-  const double sfout = block_sum_256(fout);
-  if (threadIdx.x == 0) {
-    out[0] = (double)max(max(s_it[0], s_it[1]), max(s_it[2], s_it[3]));
-    out[1] = snc;
-    out[2] = fmax(fmax(s_res[0], s_res[1]), fmax(s_res[2], s_res[3]));
-    out[3] = sfin;
-    out[4] = sfout;
-  }
-}
-
-// front of row blockIdx.x: dx * trapezoid sum of phi(T)
-template <int Q, typename S>
-__global__ __launch_bounds__(256) void front_integral_kernel(
-    const S *src, int64_t plane, int nx, double tm, double inv_delta,
-    double dx, double *out) {
-  const int64_t row = (int64_t)blockIdx.x * nx;
-  double acc = 0.0;
-  for (int x = threadIdx.x; x < nx; x += 256) {
-    double T = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) T += (double)src[i * plane + row + x];
-    const double ph = phi_only(T, tm, inv_delta);
-    acc += (x == 0 || x == nx - 1) ? 0.5 * ph : ph;
-  }
-  const double s = block_sum_256(acc);
-  if (threadIdx.x == 0) out[blockIdx.x] = dx * s;
-}
-
-template <int Q, typename S>
-__device__ inline double temp_at(const S *src, int64_t plane, int64_t k) {
-  double T = 0.0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
-  return T;
-}
-
-// first x (from x = 0) with T(x) - tm > 0 >= T(x+1) - tm, interpolated
-template <int Q, typename S>
-__global__ __launch_bounds__(256) void front_crossing_kernel(
-    const S *src, int64_t plane, int nx, double tm, double dx, double *out) {
-  const int64_t row = (int64_t)blockIdx.x * nx;
-  const int chunk = (nx + 255) / 256;
-  const int xa = threadIdx.x * chunk;
-  int first = INT32_MAX;
-  for (int x = xa; x < xa + chunk && x + 1 < nx; ++x) {
-    const double t0 = temp_at<Q, S>(src, plane, row + x) - tm;
-    const double t1 = temp_at<Q, S>(src, plane, row + x + 1) - tm;
-    if (t0 > 0.0 && t1 <= 0.0) {
-      first = x;
-      break;
-    }
-  }
-  __shared__ int s_min[4];
-  int m = first;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    m = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
-    const double T0 = temp_at<Q, S>(src, plane, row) - tm;
-    double pos;
-    if (T0 <= 0.0) {
-      pos = 0.0;
-    } else if (m == INT32_MAX) {
-      pos = (nx - 1) * dx;
-    } else {
-      const double t0 = temp_at<Q, S>(src, plane, row + m) - tm;
-      const double t1 = temp_at<Q, S>(src, plane, row + m + 1) - tm;
-      pos = dx * (m + t0 / (t0 - t1));
-    }
-    out[blockIdx.x] = pos;
-  }
-}
-
-}  // namespace irebm
 
 // =====================================================================
 // host side
@@ -294,34 +29,6 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
-struct Variant {
-  int bx, by, npt;
-};
-const Variant kVariants1D[] = {{256, 1, 1}, {128, 1, 1}, {64, 1, 1},
-                               {256, 1, 2}};
-const Variant kVariants2D[] = {{64, 4, 1},  {256, 1, 1}, {128, 2, 1},
-                               {64, 4, 2},  {128, 2, 2}, {256, 1, 2},
-                               {64, 2, 2},  {64, 4, 4}};
-constexpr int kNumV1 = sizeof(kVariants1D) / sizeof(Variant);
-constexpr int kNumV2 = sizeof(kVariants2D) / sizeof(Variant);
-constexpr int kDefaultV1 = 0;
-constexpr int kDefaultV2 = 3;
-
-const Variant *variants(int q, int *n) {
-  if (q == 3) {
-    *n = kNumV1;
-    return kVariants1D;
-  }
-  *n = kNumV2;
-  return kVariants2D;
-}
-
-int64_t tiles_for(const Variant &v, int64_t nx, int64_t ny) {
-  const int64_t tw = (int64_t)v.bx * v.npt, th = v.by;
-  return ((nx + tw - 1) / tw) * ((ny + th - 1) / th);
-}
-
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -407,16 +114,11 @@ int irebm::fail(lbm_stefan_t *h, int code, const std::string &msg) {
   return code;
 }
 
-#define HIPCHK(h, expr)                                                   \
-  do {                                                                    \
-    hipError_t e_ = (expr);                                               \
-    if (e_ != hipSuccess)                                                 \
-      return irebm::fail((h), LBM_STEFAN_EDEVICE,                         \
-                         std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+void irebm::set_global_error(const std::string &msg) { g_err = msg; }
 
-void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
-  const lbm_stefan_params &p = h->p;
+
+void irebm::fill_args(const lbm_stefan_params &p, double *const prof[4],
+                      StepArgs *A) {
   std::memset(A, 0, sizeof(*A));
   A->nx = (int32_t)p.nx;
   A->ny = (int32_t)p.ny;
@@ -437,24 +139,18 @@ void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
   for (int k = 0; k < 4; ++k) {
     A->bc[k] = (p.dim == 1 && k >= 2) ? BC_PERIODIC : p.bc[k];
     A->wall_T[k] = p.wall_T[k];
-    A->prof[k] = h->has_prof[k] ? h->prof[k] : nullptr;
+    A->prof[k] = prof ? prof[k] : nullptr;
   }
+}
+
+void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
+  double *prof[4];
+  for (int k = 0; k < 4; ++k) prof[k] = h->has_prof[k] ? h->prof[k] : nullptr;
+  fill_args(h->p, prof, A);
   A->slots = h->slots;
 }
 
 namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess || prev == dev ||
-        hipSetDevice(dev) != hipSuccess)
-      prev = -1;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
 
 template <int Q, typename S>
 hipError_t launch_step_t(const lbm_stefan_t *h, const StepArgs &A,
@@ -462,7 +158,7 @@ hipError_t launch_step_t(const lbm_stefan_t *h, const StepArgs &A,
   const int64_t ntiles = tiles_for(v, h->p.nx, h->p.ny);
   const int per_xcd = (int)((ntiles + 7) / 8);
   StepArgs B = A;
-  B.tiles_x = (int32_t)((h->p.nx + v.bx * v.npt - 1) / (v.bx * v.npt));
+  B.tiles_x = (int32_t)tiles_x_for(v, h->p.nx);
   B.ntiles = (int32_t)ntiles;
   B.per_xcd = per_xcd;
   dim3 grid(8 * per_xcd), block(v.bx, v.by);
@@ -508,65 +204,23 @@ hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
 
 namespace {
 
-template <int Q>
-using QT = std::integral_constant<int, Q>;
-template <typename T>
-struct TT {
-  using type = T;
-};
-
-// calls f(QT<Q>{}, TT<S>{}) for the lattice and storage of a handle
-template <typename F>
-hipError_t dispatch_qs(int q, int storage, F &&f) {
-  const bool f32 = storage == LBM_STORE_F32;
-  switch (q) {
-    case 3:
-      return f32 ? f(QT<3>{}, TT<float>{}) : f(QT<3>{}, TT<double>{});
-    case 5:
-      return f32 ? f(QT<5>{}, TT<float>{}) : f(QT<5>{}, TT<double>{});
-    default:
-      return f32 ? f(QT<9>{}, TT<float>{}) : f(QT<9>{}, TT<double>{});
-  }
-}
-
-#define QS_TYPES(qt, tt)                  \
-  constexpr int Q = decltype(qt)::value; \
-  using S = typename decltype(tt)::type
-
-unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
-
-hipError_t zero_async(uint64_t *p, int64_t n_words, hipStream_t s) {
-  if (n_words <= 0) return hipSuccess;
-  zero_kernel<<<blocks_for(n_words, 256), 256, 0, s>>>(p, n_words);
-  return hipGetLastError();
-}
-
 // energy of the state `src` into h->small[kSmallEnergy] (device)
-hipError_t energy_async(const lbm_stefan_t *h, const void *src) {
-  return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
-    QS_TYPES(qt, tt);
-    const int64_t n = h->p.nx * h->p.ny;
-    const int64_t parts = (n + kEnergyChunk - 1) / kEnergyChunk;
-    energy_partial_kernel<Q, S><<<(unsigned)parts, 256, 0, h->stream>>>(
-        (const S *)src, n, h->p.t_m, 1.0 / h->p.delta, 1.0 / h->p.ste,
-        h->partials);
-    sum_kernel<<<1, 256, 0, h->stream>>>(h->partials, parts,
-                                         h->small + kSmallEnergy);
-    return hipGetLastError();
-  });
+hipError_t handle_energy_async(const lbm_stefan_t *h, const void *src) {
+  return irebm::energy_async(h->p.q, h->p.storage, src, h->p.nx * h->p.ny,
+                             h->p.t_m, h->p.delta, h->p.ste, h->partials,
+                             h->small + kSmallEnergy, h->stream);
 }
 
 }  // namespace
 
 hipError_t irebm::zero_stats_async(lbm_stefan_t *h) {
-  return zero_async((uint64_t *)h->slots,
-                    (int64_t)(h->max_tiles * sizeof(StatSlot) / 8), h->stream);
+  return zero_async(h->slots, h->max_tiles * sizeof(StatSlot), h->stream);
 }
 
 int irebm::read_stats(lbm_stefan_t *h, lbm_stefan_stats *st) {
   stats_kernel<<<1, 256, 0, h->stream>>>(h->slots, h->max_tiles, h->small);
   HIPCHK(h, hipGetLastError());
-  HIPCHK(h, energy_async(h, h->buf[h->cur]));
+  HIPCHK(h, handle_energy_async(h, h->buf[h->cur]));
   double hs[kSmallCount];
   HIPCHK(h, hipMemcpyAsync(hs, h->small, sizeof(hs), hipMemcpyDeviceToHost,
                            h->stream));
@@ -624,7 +278,7 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   if (p->dim == 1) h->p.bc[2] = h->p.bc[3] = LBM_BC_PERIODIC;
   int nv;
   variants(p->q, &nv);
-  h->variant = p->variant >= 0 ? p->variant : (p->q == 3 ? kDefaultV1 : kDefaultV2);
+  h->variant = p->variant >= 0 ? p->variant : (p->q == 3 ? kDefaultVariant1D : kDefaultVariant2D);
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
@@ -735,7 +389,7 @@ int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
   }
   double e = 0.0;
   if (energy) {
-    HIPCHK(h, energy_async(h, h->buf[h->cur]));
+    HIPCHK(h, handle_energy_async(h, h->buf[h->cur]));
     HIPCHK(h, hipMemcpyAsync(&e, h->small + kSmallEnergy, 8,
                              hipMemcpyDeviceToHost, h->stream));
   }

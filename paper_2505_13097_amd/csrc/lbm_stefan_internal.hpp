@@ -55,6 +55,11 @@ std::string validate_params(const lbm_stefan_params *p);
 Layout layout_for(const lbm_stefan_params *p);
 size_t adjoint_bytes(const lbm_stefan_params *p, int64_t max_tiles);
 int fail(lbm_stefan_t *h, int code, const std::string &msg);
+void set_global_error(const std::string &msg);
+// StepArgs of a lattice from its params (prof: device wall profiles or
+// NULL); src, dst, slots and the tile fields are left zero
+void fill_args(const lbm_stefan_params &p, double *const prof[4],
+               StepArgs *A);
 void fill_step_args(const lbm_stefan_t *h, StepArgs *A);
 hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst);
 hipError_t zero_stats_async(lbm_stefan_t *h);

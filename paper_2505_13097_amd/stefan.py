@@ -187,3 +187,104 @@ class Stefan:
             self.close()
         except Exception:
             pass
+
+
+class StefanBatch:
+    """Many independent IREBM lattices (uneven sizes and parameters, one
+    lattice type and storage) advanced by one persistent kernel launch per
+    step, optionally replayed from a captured hipGraph."""
+
+    def __init__(self, probs, stream=None):
+        self.probs = list(probs)
+        self._lib = C.lib()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        n = len(self.probs)
+        arr = (C.Params * n)()
+        keep = []
+        for k, pr in enumerate(self.probs):
+            p, kk = make_params(pr)
+            arr[k] = p
+            keep.append(kk)
+        self._params = arr
+        nb = ctypes.c_size_t()
+        C.check_batch(self._lib.lbm_stefan_batch_workspace_bytes(arr, n, ctypes.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        T0s = []
+        T0p = (C._c_double_p * n)()
+        for k, pr in enumerate(self.probs):
+            if pr.T0 is not None:
+                a = np.ascontiguousarray(np.broadcast_to(pr.T0, (pr.ny, pr.nx)),
+                                         dtype=np.float64)
+                T0s.append(a)
+                T0p[k] = a.ctypes.data_as(C._c_double_p)
+        h = ctypes.c_void_p()
+        C.check_batch(self._lib.lbm_stefan_batch_init(
+            arr, n, T0p, ctypes.c_void_p(self.workspace.data_ptr()), nb.value,
+            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        del keep, T0s
+        self.h = h
+
+    def __len__(self):
+        return len(self.probs)
+
+    def set_schedule(self, variant=-1, blocks_per_cu=4, graph_steps=0):
+        C.check_batch(self._lib.lbm_stefan_batch_set_schedule(
+            self.h, int(variant), int(blocks_per_cu), int(graph_steps)), self.h)
+
+    def step(self, nsteps):
+        C.check_batch(self._lib.lbm_stefan_batch_step(self.h, int(nsteps)), self.h)
+
+    def stats(self):
+        out = (C.Stats * len(self.probs))()
+        C.check_batch(self._lib.lbm_stefan_batch_stats(self.h, out), self.h)
+        return [s.as_dict() for s in out]
+
+    def reset_stats(self):
+        C.check_batch(self._lib.lbm_stefan_batch_reset_stats(self.h), self.h)
+
+    def front(self, k, mode="integral"):
+        out = np.empty(self.probs[k].ny)
+        C.check_batch(self._lib.lbm_stefan_batch_query_front(
+            self.h, int(k), _FRONT[mode],
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None), self.h)
+        return out
+
+    def energy(self, k):
+        e = ctypes.c_double()
+        C.check_batch(self._lib.lbm_stefan_batch_query_front(
+            self.h, int(k), C.FRONT_LIQUID_INTEGRAL, None, ctypes.byref(e)), self.h)
+        return e.value
+
+    def temperature(self, k):
+        pr = self.probs[k]
+        T = np.empty((pr.ny, pr.nx))
+        C.check_batch(self._lib.lbm_stefan_batch_get_field(
+            self.h, int(k), C.FIELD_T, ctypes.c_void_p(T.ctypes.data)), self.h)
+        return T
+
+    def autotune(self, steps=10):
+        """Time every (variant, blocks per CU) pair and keep the fastest;
+        states are saved and restored.  Returns (variant, bpc, ms/step)."""
+        nb = ctypes.c_size_t()
+        C.check_batch(self._lib.lbm_stefan_batch_state_bytes(self.h, ctypes.byref(nb)))
+        scratch = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        v = ctypes.c_int32()
+        bpc = ctypes.c_int32()
+        ms = ctypes.c_double()
+        C.check_batch(self._lib.lbm_stefan_batch_autotune(
+            self.h, ctypes.c_void_p(scratch.data_ptr()), nb.value, int(steps),
+            ctypes.byref(v), ctypes.byref(bpc), ctypes.byref(ms)), self.h)
+        del scratch
+        return v.value, bpc.value, ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            C.check_batch(self._lib.lbm_stefan_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

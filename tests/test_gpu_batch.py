@@ -1,0 +1,159 @@
+"""GPU tests of the batched form: many uneven lattices in one persistent
+launch per step must evolve exactly as each lattice stepped alone (same
+per-node arithmetic), match the CPU oracle, survive hipGraph replays and
+autotuning without any change of state."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _mixed(storage, count=7, seed=11):
+    probs = synth.batch_table(count=count, seed=seed, sizes=[64, 128, 192],
+                              storage=storage, nsteps=300)
+    # uneven: one non-square, one with a wall profile, one plain Newton
+    probs[1] = probs[1].with_(ny=96, T0=probs[1].T0[:96])
+    probs[2] = probs[2].with_(wall_profile=(
+        0.8 + 0.4 * np.sin(np.arange(probs[2].ny) / 7.0), None, None, None))
+    probs[3] = probs[3].with_(newton_mode="plain")
+    return probs
+
+
+def _single(prob, steps):
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob)
+    g.step(steps)
+    T = g.temperature()
+    g.close()
+    return T
+
+
+def test_batch_members_equal_single_runs_and_oracle():
+    from paper_2505_13097_amd import StefanBatch
+    probs = _mixed("f64")
+    # plain Newton cannot share a batch with safeguarded instances
+    probs = [p for p in probs if p.newton_mode == "safeguarded"]
+    b = StefanBatch(probs)
+    b.step(300)
+    st = b.stats()
+    for k, p in enumerate(probs):
+        T = b.temperature(k)
+        assert np.array_equal(T, _single(p, 300)), k
+        assert st[k]["nonconverged"] == 0
+    for k in (0, 1, 2):
+        p = probs[k]
+        f, _ = O.run(p, O.init(p, p.T0), 300)
+        err = np.abs(b.temperature(k) - O.temperature(p, f)).max()
+        print(f"batch member {k} ({p.nx}x{p.ny}): max|dT| vs oracle {err:.2e}")
+        assert err <= 1e-12
+    b.close()
+
+
+def test_batch_fp32_against_oracle():
+    from paper_2505_13097_amd import StefanBatch
+    probs = [p for p in _mixed("f32") if p.newton_mode == "safeguarded"]
+    b = StefanBatch(probs)
+    b.step(300)
+    for k in (0, 2, 4):
+        p = probs[k]
+        f, _ = O.run(p, O.init(p, p.T0), 300)
+        To = O.temperature(p, f)
+        assert np.abs(b.temperature(k) - To).max() <= 1e-5
+        cr = np.abs(b.front(k, "crossing") - O.front(p, f, O.FRONT_CROSSING))
+        assert cr.max() <= p.dx
+    b.close()
+
+
+def test_batch_plain_newton_batch():
+    from paper_2505_13097_amd import StefanBatch
+    probs = [p.with_(newton_mode="plain") for p in _mixed("f64", count=4)]
+    b = StefanBatch(probs)
+    b.step(200)
+    for k, p in enumerate(probs):
+        assert np.array_equal(b.temperature(k), _single(p, 200))
+    b.close()
+
+
+@pytest.mark.parametrize("graph_steps", [2, 6])
+def test_graph_replays_equal_eager_steps(graph_steps):
+    from paper_2505_13097_amd import StefanBatch
+    probs = [p for p in _mixed("f64") if p.newton_mode == "safeguarded"]
+    eager = StefanBatch(probs)
+    graph = StefanBatch(probs)
+    graph.set_schedule(-1, 4, graph_steps)
+    done = 0
+    for rnd, n in enumerate([graph_steps, graph_steps + 1, 3 * graph_steps, 1]):
+        graph.step(n)
+        eager.step(n)
+        done += n
+        # eager work between replays (queries launch kernels of their own)
+        for k in range(len(probs)):
+            assert np.array_equal(graph.temperature(k), eager.temperature(k)), (rnd, k)
+        graph.front(0)
+    sg, se = graph.stats(), eager.stats()
+    for a, c in zip(sg, se):
+        assert a["energy"] == c["energy"]
+        assert a["steps"] == c["steps"] == done
+    graph.close()
+    eager.close()
+
+
+def test_autotune_keeps_state_and_result():
+    from paper_2505_13097_amd import StefanBatch
+    probs = [p for p in _mixed("f32") if p.newton_mode == "safeguarded"]
+    a = StefanBatch(probs)
+    ref = StefanBatch(probs)
+    a.step(20)
+    ref.step(20)
+    before = [a.temperature(k) for k in range(len(probs))]
+    v, bpc, ms = a.autotune(steps=3)
+    print(f"autotune: variant {v}, {bpc} blocks/CU, {ms:.4f} ms/step")
+    assert ms > 0
+    for k in range(len(probs)):
+        assert np.array_equal(a.temperature(k), before[k])
+    a.step(30)
+    ref.step(30)
+    for k in range(len(probs)):
+        assert np.array_equal(a.temperature(k), ref.temperature(k))
+    a.close()
+    ref.close()
+
+
+def test_single_lattice_autotune_keeps_state():
+    from paper_2505_13097_amd import Stefan
+    prob = synth.cavity_2d(n=300, ny=200, storage="f32")
+    g = Stefan(prob)
+    r = Stefan(prob)
+    g.step(10)
+    r.step(10)
+    T = g.temperature()
+    v, ms = g.autotune(steps=3)
+    assert np.array_equal(g.temperature(), T)
+    g.step(25)
+    r.step(25)
+    assert np.array_equal(g.temperature(), r.temperature())
+    g.close()
+    r.close()
+
+
+def test_batch_energy_balance_per_instance():
+    from paper_2505_13097_amd import StefanBatch
+    probs = [p for p in _mixed("f64") if p.newton_mode == "safeguarded"]
+    b = StefanBatch(probs)
+    E0 = [b.energy(k) for k in range(len(probs))]
+    b.step(200)
+    for k, s in enumerate(b.stats()):
+        dE = s["energy"] - E0[k]
+        assert abs(dE - (s["flux_in"] - s["flux_out"])) < 1e-9 * max(1, abs(dE))
+    b.close()
