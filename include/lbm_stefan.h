@@ -227,6 +227,89 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
 int lbm_stefan_destroy(lbm_stefan_t *h);
 
 /* ---------------------------------------------------------------------
+ * Reverse mode (handle created with LBM_FLAG_ADJOINT).  The reverse step
+ * is the exact adjoint of the forward step of this library (Algorithm 3,
+ * Section 4.1, with the closures of Section 4.2): the transposes of the
+ * collision, pull, source and closures, and the implicit-function theorem
+ * at the Newton root (dT~/dm0 = 1/J, dT~/dT = (phi'(T)/Ste)/J,
+ * J = 1 + phi'(T~)/Ste), exact where the solve converged.  Adjoint arrays
+ * ("abar": the adjoint of the state, q planes [q][ny][nx]) are FP64 device
+ * memory in every storage mode.  Gradients with respect to Ste, delta and
+ * every Dirichlet wall node's temperature accumulate in the handle until
+ * lbm_stefan_adjoint_reset.
+ * --------------------------------------------------------------------- */
+
+/* Zero the gradient accumulators (asynchronous). */
+int lbm_stefan_adjoint_reset(lbm_stefan_t *h);
+
+/*
+ * Seed from the front position (LBM_FRONT_LIQUID_INTEGRAL) of `state`
+ * (device, state layout): abar = d(sum_y g(y) xf(y))/dOmega with g =
+ * dL_dfront (host, ny doubles), i.e. g(y) dx w_x phi'(T(x, y)) in every
+ * plane; adds the delta-dependence of the front to the delta gradient.
+ * abar: device, q*nx*ny doubles, overwritten.  Waits for the stream.
+ */
+int lbm_stefan_front_vjp(lbm_stefan_t *h, const void *state,
+                         const double *dL_dfront, double *abar);
+
+/*
+ * One reverse step at forward state state_n (device): abar_n = (dOmega^{n+1}
+ * /dOmega^n)^T abar_np1, and the step's Ste, delta and wall-temperature
+ * terms are added to the accumulators.  abar_np1 and abar_n: device FP64,
+ * distinct.  Asynchronous.
+ */
+int lbm_stefan_adjoint_step(lbm_stefan_t *h, const void *state_n,
+                            const double *abar_np1, double *abar_n);
+
+/* Add the dependence of the equilibrium initial state (Dirichlet nodes at
+   w_i T_D) on the wall temperatures, given abar_0 (device).  Asynchronous. */
+int lbm_stefan_adjoint_initial_state(lbm_stefan_t *h, const double *abar_0);
+
+/*
+ * Read the accumulated gradients: g_wall (host, nullable) receives the
+ * wall-temperature gradients of the x-, x+ walls (ny values each) then
+ * the y-, y+ walls (nx values each), one per Dirichlet wall node (zero
+ * elsewhere); g_ste and g_delta (host, nullable).  Fixed-order FP64 sums.
+ * Waits for the stream.  Errors: ENAN, EDEVICE.
+ */
+int lbm_stefan_adjoint_gradients(lbm_stefan_t *h, double *g_wall,
+                                 double *g_ste, double *g_delta);
+
+/* Device pointers of the handle's two adjoint work arrays (q*nx*ny FP64
+   each), usable as abar arguments; valid for the handle's lifetime. */
+int lbm_stefan_adjoint_buffers(lbm_stefan_t *h, double **abar0,
+                               double **abar1);
+
+/*
+ * Checkpointed gradient of a front functional ("tape").  Checkpoints are
+ * taken every `interval` steps (sqrt(nsteps) balances memory and
+ * recomputation); the reverse sweep recomputes each segment from its
+ * checkpoint, then runs its reverse steps.
+ *   lbm_stefan_tape_bytes: device bytes of a tape for (p, nsteps,
+ *     interval): (ceil(nsteps/interval) + 1 + interval) states.
+ *   lbm_stefan_forward_tape: advance the handle nsteps from its current
+ *     state (the state the gradient is taken at: normally the initial state
+ *     built by lbm_stefan_init), storing checkpoints in `tape` (device,
+ *     256-byte aligned, caller-owned).  Asynchronous.
+ *   lbm_stefan_backward_tape: with g = dL_dfront (host, ny doubles) the
+ *     derivative of a loss with respect to the final integral front,
+ *     compute dL/d(wall temperatures) (g_wall, layout as in
+ *     lbm_stefan_adjoint_gradients), dL/dSte and dL/ddelta, including the
+ *     initial state's dependence on the wall temperatures.  Resets the
+ *     accumulators first; the handle's state stays the final state; the
+ *     statistics also count the recomputed steps.  Waits for the stream.
+ * Errors: EINVAL (no LBM_FLAG_ADJOINT, bad sizes, a tape that is not the
+ * one of the last forward_tape), ENAN, EDEVICE.
+ */
+int lbm_stefan_tape_bytes(const lbm_stefan_params *p, int64_t nsteps,
+                          int64_t interval, size_t *bytes);
+int lbm_stefan_forward_tape(lbm_stefan_t *h, int64_t nsteps, int64_t interval,
+                            void *tape, size_t bytes);
+int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
+                             void *tape, size_t bytes, double *g_wall,
+                             double *g_ste, double *g_delta);
+
+/* ---------------------------------------------------------------------
  * Batched form: many independent lattices with their own sizes and
  * parameters, advanced together by one persistent kernel launch per time
  * step (optionally replayed from a captured hipGraph).  Every instance is

@@ -8,7 +8,8 @@ memory and streams.  There is no CPU fallback: if the library is not
 built, using it raises LibraryMissing.
 """
 from ._lib import LbmError, LibraryMissing  # noqa: F401
-from .stefan import (Stefan, StefanBatch, make_params, variant_names,  # noqa: F401
+from .stefan import (HotWallFront, Stefan, StefanBatch, make_params,  # noqa: F401
+                     variant_names,
                      workspace_bytes)
 
 __version__ = "0.1.0"

@@ -76,6 +76,21 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int32),
                                            _c_double_p]),
     "lbm_stefan_destroy": (ctypes.c_int, [_vp]),
+    "lbm_stefan_adjoint_reset": (ctypes.c_int, [_vp]),
+    "lbm_stefan_front_vjp": (ctypes.c_int, [_vp, _vp, _c_double_p, _vp]),
+    "lbm_stefan_adjoint_step": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "lbm_stefan_adjoint_initial_state": (ctypes.c_int, [_vp, _vp]),
+    "lbm_stefan_adjoint_gradients": (ctypes.c_int, [_vp, _c_double_p, _c_double_p,
+                                                    _c_double_p]),
+    "lbm_stefan_adjoint_buffers": (ctypes.c_int, [_vp, ctypes.POINTER(_vp),
+                                                  ctypes.POINTER(_vp)]),
+    "lbm_stefan_tape_bytes": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_stefan_forward_tape": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64,
+                                               _vp, ctypes.c_size_t]),
+    "lbm_stefan_backward_tape": (ctypes.c_int, [_vp, _c_double_p, _vp,
+                                                ctypes.c_size_t, _c_double_p,
+                                                _c_double_p, _c_double_p]),
     "lbm_stefan_batch_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int32,
                                                         ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_stefan_batch_init": (ctypes.c_int, [_P, ctypes.c_int32,

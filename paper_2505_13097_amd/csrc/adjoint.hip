@@ -1,8 +1,560 @@
-// adjoint.hip -- reverse mode of the IREBM step (filled in below).
+// adjoint.hip -- reverse mode of the IREBM step on the post-collision
+// state, and a checkpointed driver (tape) for front-misfit gradients.
+//
+// Forward step at node x (Algorithm 3 in the Omega form of this library):
+//   T = sum_j Omega_j(x),  q_i = Omega_i(x - e_i) (or a closure),
+//   m0 = sum q_i,  T~ solves R = T~ + phi(T~)/Ste - m0 - phi(T)/Ste = 0,
+//   s = (phi(T) - phi(T~))/Ste,  f~_i = q_i + w_i s,
+//   T' = sum f~_i,  Omega'_i = a f~_i + (w_i/tau) T'      (a = 1 - 1/tau).
+// Reverse, given Omega'bar at x:
+//   T'bar = sum (w_i/tau) Omega'bar_i,  f~bar_i = a Omega'bar_i + T'bar,
+//   sbar = sum w_i f~bar_i,  qbar_i = f~bar_i,
+//   source: Tbar += sbar phi'(T)/Ste,  T~bar = -sbar phi'(T~)/Ste,
+//   Newton root by the implicit-function theorem (J = 1 + phi'(T~)/Ste,
+//   exact at converged nodes): m0bar = T~bar/J,
+//   Tbar += T~bar (phi'(T)/Ste)/J, plus the Ste and delta terms,
+//   qbar_i += m0bar, then the closures in reverse order,
+// and the transposes of the pull and of T = sum Omega:
+//   Omegabar_i(y) = qbar_i(y + e_i) + Tbar(y).
+// The pull transpose is again a radius-1 stencil, so a reverse step is two
+// kernels: adj_local (per node: recompute the forward, write qbar and
+// Tbar) and adj_pull (gather).  Parameter gradients are summed per block
+// in a fixed order and accumulated across steps in per-block slots;
+// Dirichlet wall-temperature gradients are accumulated per wall node by
+// the one thread owning it.  Adjoint arrays are FP64 in every storage mode.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_util.hpp"
+#include "kernels.hpp"
+#include "lbm_stefan.h"
 #include "lbm_stefan_internal.hpp"
 
-size_t irebm::adjoint_bytes(const lbm_stefan_params *p, int64_t max_tiles) {
-  (void)p;
-  (void)max_tiles;
-  return 0;
+using namespace irebm;
+
+namespace {
+
+struct AdjArgs {
+  StepArgs A;              // A.src: the forward state at step n
+  const double *abar_in;   // Omega'bar (q planes) / abar_0 for the init term
+  double *qbar;            // q planes
+  double *tbar;            // n
+  double *abar_out;        // q planes
+  double *gS, *gD;         // per-block partial sums (accumulated)
+  double *gwall[4];        // per wall node (accumulated)
+  const double *r;         // dL/dfront per row (front vjp)
+  double dx, delta, ste;
+};
+
+__device__ inline double dphi_ddelta(double t, double tm, double delta,
+                                     double dph) {
+  return -((t - tm) / delta) * dph;
 }
+
+__device__ inline void block_add2(double a, double b, double *ga, double *gb) {
+  __shared__ double s[8];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s[w] = a;
+    s[4 + w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ga[blockIdx.x] += (s[0] + s[1]) + (s[2] + s[3]);
+    gb[blockIdx.x] += (s[4] + s[5]) + (s[6] + s[7]);
+  }
+}
+
+__device__ inline int wall_index(int wall, int x, int y) {
+  return wall < 2 ? y : x;
+}
+
+// per node: recompute the forward step, reverse it down to qbar and Tbar
+template <int Q, typename S, bool PLAIN>
+__global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs G) {
+  const StepArgs &A = G.A;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double accS = 0.0, accD = 0.0;
+  if (k < A.plane) {
+    const int x = (int)(k % A.nx), y = (int)(k / A.nx);
+    NodeLoad<Q, S> L;
+    load_node<Q, S, false>(A, x, y, L);
+    double om[Q], q[Q], th = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      om[j] = (double)L.own[j];
+      th += om[j];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
+    CloseInfo ci;
+    if (L.known != (1u << Q) - 1u) close_node<Q>(A, x, y, th, om, q, L.known, &ci);
+    double m0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) m0 += q[i];
+    const double S_ = G.ste, is = A.inv_ste, tm = A.tm, dl = G.delta;
+    const double P = phi_only(th, tm, A.inv_delta);
+    int it;
+    bool conv;
+    const double tn = newton<PLAIN>(m0, th, P, A, it, conv);
+    double Pt, dt, Pd_, d;
+    phi_dphi(tn, tm, A.inv_delta, Pt, dt);
+    phi_dphi(th, tm, A.inv_delta, Pd_, d);
+    const double dP = dphi_ddelta(th, tm, dl, d);
+    const double dPt = dphi_ddelta(tn, tm, dl, dt);
+    // reverse of Omega' = a f~ + (w/tau) sum f~
+    double ab[Q], qb[Q];
+    double tpb = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      ab[i] = G.abar_in[i * A.plane + k];
+      tpb += A.wtau[i] * ab[i];
+    }
+    double sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      qb[i] = A.a * ab[i] + tpb;
+      sb += wt<Q>(i) * qb[i];
+    }
+    // source s = (P - Pt)/Ste
+    double thl = sb * d * is;
+    const double tnb = -sb * dt * is;
+    double Sb = -sb * (P - Pt) * is * is;
+    double Db_ = sb * (dP - dPt) * is;
+    // Newton root (implicit-function theorem)
+    const double J = 1.0 + dt * is;
+    const double m0b = tnb / J;
+    thl += tnb * (d * is) / J;
+    Sb += tnb * (Pt - P) * is * is / J;
+    Db_ += -tnb * (dPt - dP) * is / J;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) qb[i] += m0b;
+    // closures, reversed: Dirichlet share, then bounce-back
+    if (ci.share) {
+      double Db = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (ci.share >> i & 1u) Db += qb[i] * (wt<Q>(i) / ci.wu);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (!(ci.share >> i & 1u) && !(ci.own >> i & 1u)) qb[i] -= Db;
+      double PD, dPD;
+      phi_dphi(ci.TD, tm, A.inv_delta, PD, dPD);
+      G.gwall[ci.wall][wall_index(ci.wall, x, y)] += Db * (1.0 + dPD * is);
+      thl += -Db * d * is;
+      Sb += -Db * (PD - P) * is * is;
+      Db_ += Db * (dphi_ddelta(ci.TD, tm, dl, dPD) - dP) * is;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      if (ci.bb >> i & 1u) qb[opp<Q>(i)] += qb[i];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) G.qbar[i * A.plane + k] = qb[i];
+    G.tbar[k] = thl;
+    (void)S_;
+    accS = Sb;
+    accD = Db_;
+  }
+  block_add2(accS, accD, G.gS, G.gD);
+}
+
+// Omegabar_i(y) = qbar_i(y + e_i) (where that node pulls direction i from
+// y) + Tbar(y) + own-population closures at y
+template <int Q>
+__global__ __launch_bounds__(256) void adj_pull_kernel(AdjArgs G) {
+  const StepArgs &A = G.A;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= A.plane) return;
+  const int x = (int)(k % A.nx), y = (int)(k / A.nx);
+  double out[Q];
+  const double tb = G.tbar[k];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[i] = tb;
+  uint32_t known = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int ex = cx<Q>(i), ey = cy<Q>(i);
+    // destination z = y + e_i
+    int zx = x + ex, zy = y + ey;
+    bool ok = true;
+    if (zx < 0 || zx >= A.nx) {
+      if (A.periodic_x) zx = (zx + A.nx) % A.nx; else ok = false;
+    }
+    if (zy < 0 || zy >= A.ny) {
+      if (A.periodic_y) zy = (zy + A.ny) % A.ny; else ok = false;
+    }
+    if (ok) out[i] += G.qbar[i * A.plane + (int64_t)zy * A.nx + zx];
+    // source x - e_i of this node (for its own closures)
+    int sx = x - ex, sy = y - ey;
+    bool sk = true;
+    if (sx < 0 || sx >= A.nx) sk = A.periodic_x != 0;
+    if (sy < 0 || sy >= A.ny) sk = sk && A.periodic_y != 0;
+    if (sk) known |= 1u << i;
+  }
+  if (known != (1u << Q) - 1u && dirichlet_wall<Q>(A, x, y) < 0) {
+    // unknowns closed by the node's own Omega_opp (both directions unknown)
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int o = opp<Q>(i);
+      const bool bb = (known >> o & 1u) && leaves_by_bounceback<Q>(A, x, y, i);
+      if (!(known >> i & 1u) && !bb) out[o] += G.qbar[i * A.plane + k];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) G.abar_out[i * A.plane + k] = out[i];
+}
+
+// seed: Omegabar_j(x, y) = r(y) dx w_x phi'(T(x, y)) for every j, and the
+// delta-dependence of the front itself
+template <int Q, typename S>
+__global__ __launch_bounds__(256) void front_vjp_kernel(AdjArgs G) {
+  const StepArgs &A = G.A;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double accD = 0.0;
+  if (k < A.plane) {
+    const int x = (int)(k % A.nx), y = (int)(k / A.nx);
+    const S *src = (const S *)A.src;
+    double T = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) T += (double)src[j * A.plane + k];
+    double P, d;
+    phi_dphi(T, A.tm, A.inv_delta, P, d);
+    const double wx = (x == 0 || x == A.nx - 1) ? 0.5 : 1.0;
+    const double c = G.r[y] * G.dx * wx;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) G.abar_out[j * A.plane + k] = c * d;
+    accD = c * dphi_ddelta(T, A.tm, G.delta, d);
+  }
+  block_add2(0.0, accD, G.gS, G.gD);
+}
+
+// initial state: Omega_i = w_i T_D at Dirichlet nodes
+template <int Q>
+__global__ __launch_bounds__(256) void init_term_kernel(AdjArgs G) {
+  const StepArgs &A = G.A;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= A.plane) return;
+  const int x = (int)(k % A.nx), y = (int)(k / A.nx);
+  const int wall = dirichlet_wall<Q>(A, x, y);
+  if (wall < 0) return;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) s += wt<Q>(i) * G.abar_in[i * A.plane + k];
+  G.gwall[wall][wall_index(wall, x, y)] += s;
+}
+
+struct AdjLayout {
+  size_t abar0, abar1, qbar, tbar, gS, gD, gwall, r, out, total;
+  int64_t nblocks, wlen;
+};
+
+AdjLayout adj_layout(const lbm_stefan_params *p) {
+  AdjLayout L;
+  const int64_t n = p->nx * p->ny;
+  L.nblocks = (n + 255) / 256;
+  L.wlen = std::max(p->nx, p->ny);
+  size_t o = 0;
+  L.abar0 = o;
+  o += align256((size_t)p->q * n * 8);
+  L.abar1 = o;
+  o += align256((size_t)p->q * n * 8);
+  L.qbar = o;
+  o += align256((size_t)p->q * n * 8);
+  L.tbar = o;
+  o += align256((size_t)n * 8);
+  L.gS = o;
+  o += align256((size_t)L.nblocks * 8);
+  L.gD = o;
+  o += align256((size_t)L.nblocks * 8);
+  L.gwall = o;
+  o += align256((size_t)4 * L.wlen * 8);
+  L.r = o;
+  o += align256((size_t)p->ny * 8);
+  L.out = o;
+  o += 256;
+  L.total = o;
+  return L;
+}
+
+int check_adj(lbm_stefan_t *h) {
+  if (!h) return fail(nullptr, LBM_STEFAN_EINVAL, "handle is NULL");
+  if (!h->layout.adjoint)
+    return fail(h, LBM_STEFAN_EINVAL,
+                "handle was created without LBM_FLAG_ADJOINT");
+  return LBM_STEFAN_OK;
+}
+
+AdjArgs make_args(lbm_stefan_t *h) {
+  const AdjLayout L = adj_layout(&h->p);
+  AdjArgs G;
+  std::memset(&G, 0, sizeof(G));
+  fill_step_args(h, &G.A);
+  char *base = h->adj;
+  G.qbar = (double *)(base + L.qbar);
+  G.tbar = (double *)(base + L.tbar);
+  G.gS = (double *)(base + L.gS);
+  G.gD = (double *)(base + L.gD);
+  for (int w = 0; w < 4; ++w) G.gwall[w] = (double *)(base + L.gwall) + w * L.wlen;
+  G.r = (const double *)(base + L.r);
+  G.dx = h->p.dx;
+  G.delta = h->p.delta;
+  G.ste = h->p.ste;
+  return G;
+}
+
+unsigned node_blocks(const lbm_stefan_t *h) {
+  return (unsigned)((h->p.nx * h->p.ny + 255) / 256);
+}
+
+hipError_t adjoint_step_async(lbm_stefan_t *h, const void *state,
+                              const double *abar_in, double *abar_out) {
+  AdjArgs G = make_args(h);
+  G.A.src = state;
+  G.abar_in = abar_in;
+  G.abar_out = abar_out;
+  const bool plain = h->p.newton_mode == LBM_NEWTON_PLAIN;
+  const unsigned nb = node_blocks(h);
+  hipError_t e = dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    if (plain)
+      adj_local_kernel<Q, S, true><<<nb, 256, 0, h->stream>>>(G);
+    else
+      adj_local_kernel<Q, S, false><<<nb, 256, 0, h->stream>>>(G);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    (void)sizeof(S);
+    adj_pull_kernel<Q><<<nb, 256, 0, h->stream>>>(G);
+    return hipGetLastError();
+  });
+}
+
+hipError_t front_vjp_async(lbm_stefan_t *h, const void *state,
+                           const double *dL_dfront_host, double *abar) {
+  const AdjLayout L = adj_layout(&h->p);
+  hipError_t e = hipMemcpyAsync(h->adj + L.r, dL_dfront_host, h->p.ny * 8,
+                                hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return e;
+  AdjArgs G = make_args(h);
+  G.A.src = state;
+  G.abar_out = abar;
+  const unsigned nb = node_blocks(h);
+  return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    front_vjp_kernel<Q, S><<<nb, 256, 0, h->stream>>>(G);
+    return hipGetLastError();
+  });
+}
+
+hipError_t init_term_async(lbm_stefan_t *h, const double *abar0) {
+  AdjArgs G = make_args(h);
+  G.abar_in = abar0;
+  const unsigned nb = node_blocks(h);
+  return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    (void)sizeof(S);
+    init_term_kernel<Q><<<nb, 256, 0, h->stream>>>(G);
+    return hipGetLastError();
+  });
+}
+
+hipError_t reset_async(lbm_stefan_t *h) {
+  const AdjLayout L = adj_layout(&h->p);
+  hipError_t e = zero_async(h->adj + L.gS, L.nblocks * 8, h->stream);
+  if (e == hipSuccess) e = zero_async(h->adj + L.gD, L.nblocks * 8, h->stream);
+  if (e == hipSuccess)
+    e = zero_async(h->adj + L.gwall, 4 * L.wlen * 8, h->stream);
+  return e;
+}
+
+// gradients to host: g_wall (x-, x+ of length ny, then y-, y+ of length
+// nx; nullable), dL/dSte and dL/ddelta (nullable)
+int read_gradients(lbm_stefan_t *h, double *g_wall, double *g_ste,
+                   double *g_delta) {
+  const AdjLayout L = adj_layout(&h->p);
+  double *out = (double *)(h->adj + L.out);
+  sum_kernel<<<1, 256, 0, h->stream>>>((const double *)(h->adj + L.gS),
+                                       L.nblocks, out);
+  sum_kernel<<<1, 256, 0, h->stream>>>((const double *)(h->adj + L.gD),
+                                       L.nblocks, out + 1);
+  HIPCHK(h, hipGetLastError());
+  double sd[2];
+  HIPCHK(h, hipMemcpyAsync(sd, out, 16, hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> gw;
+  if (g_wall) {
+    gw.resize(4 * L.wlen);
+    HIPCHK(h, hipMemcpyAsync(gw.data(), h->adj + L.gwall, gw.size() * 8,
+                             hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (g_ste) *g_ste = sd[0];
+  if (g_delta) *g_delta = sd[1];
+  if (g_wall) {
+    const int64_t nx = h->p.nx, ny = h->p.ny;
+    std::copy(gw.begin(), gw.begin() + ny, g_wall);
+    std::copy(gw.begin() + L.wlen, gw.begin() + L.wlen + ny, g_wall + ny);
+    std::copy(gw.begin() + 2 * L.wlen, gw.begin() + 2 * L.wlen + nx,
+              g_wall + 2 * ny);
+    std::copy(gw.begin() + 3 * L.wlen, gw.begin() + 3 * L.wlen + nx,
+              g_wall + 2 * ny + nx);
+  }
+  if (!std::isfinite(sd[0]) || !std::isfinite(sd[1]))
+    return fail(h, LBM_STEFAN_ENAN, "a gradient is not finite");
+  return LBM_STEFAN_OK;
+}
+
+size_t state_bytes(const lbm_stefan_params &p) {
+  return (size_t)p.q * p.nx * p.ny * (p.storage == LBM_STORE_F64 ? 8 : 4);
+}
+
+}  // namespace
+
+size_t irebm::adjoint_bytes(const lbm_stefan_params *p, int64_t max_tiles) {
+  (void)max_tiles;
+  return adj_layout(p).total;
+}
+
+extern "C" {
+
+int lbm_stefan_adjoint_reset(lbm_stefan_t *h) {
+  if (int rc = check_adj(h)) return rc;
+  DeviceGuard g(h->device);
+  HIPCHK(h, reset_async(h));
+  return LBM_STEFAN_OK;
+}
+
+int lbm_stefan_front_vjp(lbm_stefan_t *h, const void *state,
+                         const double *dL_dfront, double *abar) {
+  if (int rc = check_adj(h)) return rc;
+  if (!state || !dL_dfront || !abar)
+    return fail(h, LBM_STEFAN_EINVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  HIPCHK(h, front_vjp_async(h, state, dL_dfront, abar));
+  // dL_dfront is host memory read by an asynchronous copy
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return LBM_STEFAN_OK;
+}
+
+int lbm_stefan_adjoint_step(lbm_stefan_t *h, const void *state_n,
+                            const double *abar_np1, double *abar_n) {
+  if (int rc = check_adj(h)) return rc;
+  if (!state_n || !abar_np1 || !abar_n || abar_np1 == abar_n)
+    return fail(h, LBM_STEFAN_EINVAL, "NULL or aliased argument");
+  DeviceGuard g(h->device);
+  HIPCHK(h, adjoint_step_async(h, state_n, abar_np1, abar_n));
+  return LBM_STEFAN_OK;
+}
+
+int lbm_stefan_adjoint_initial_state(lbm_stefan_t *h, const double *abar_0) {
+  if (int rc = check_adj(h)) return rc;
+  if (!abar_0) return fail(h, LBM_STEFAN_EINVAL, "NULL argument");
+  DeviceGuard g(h->device);
+  HIPCHK(h, init_term_async(h, abar_0));
+  return LBM_STEFAN_OK;
+}
+
+int lbm_stefan_adjoint_gradients(lbm_stefan_t *h, double *g_wall,
+                                 double *g_ste, double *g_delta) {
+  if (int rc = check_adj(h)) return rc;
+  DeviceGuard g(h->device);
+  return read_gradients(h, g_wall, g_ste, g_delta);
+}
+
+int lbm_stefan_tape_bytes(const lbm_stefan_params *p, int64_t nsteps,
+                          int64_t interval, size_t *bytes) {
+  const std::string e = validate_params(p);
+  if (!e.empty()) return fail(nullptr, LBM_STEFAN_EINVAL, e);
+  if (nsteps < 1 || interval < 1 || !bytes)
+    return fail(nullptr, LBM_STEFAN_EINVAL, "nsteps and interval must be >= 1");
+  const int64_t I = std::min(interval, nsteps);
+  const int64_t K = (nsteps + I - 1) / I;
+  *bytes = (size_t)(K + 1 + I) * align256(state_bytes(*p));
+  return LBM_STEFAN_OK;
+}
+
+int lbm_stefan_forward_tape(lbm_stefan_t *h, int64_t nsteps, int64_t interval,
+                            void *tape, size_t bytes) {
+  if (int rc = check_adj(h)) return rc;
+  size_t need;
+  if (lbm_stefan_tape_bytes(&h->p, nsteps, interval, &need))
+    return fail(h, LBM_STEFAN_EINVAL, lbm_stefan_last_error(nullptr));
+  if (!tape || bytes < need || (uintptr_t)tape % 256)
+    return fail(h, LBM_STEFAN_EINVAL, "tape too small or misaligned");
+  DeviceGuard g(h->device);
+  const int64_t I = std::min(interval, nsteps);
+  const int64_t K = (nsteps + I - 1) / I;
+  const size_t sb = state_bytes(h->p), slot = align256(sb);
+  char *t = (char *)tape;
+  HIPCHK(h, hipMemcpyAsync(t, h->buf[h->cur], sb, hipMemcpyDeviceToDevice,
+                           h->stream));
+  for (int64_t k = 1; k <= K; ++k) {
+    const int64_t n = std::min(I, nsteps - (k - 1) * I);
+    for (int64_t s = 0; s < n; ++s) {
+      HIPCHK(h, launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]));
+      h->cur ^= 1;
+      h->steps++;
+    }
+    HIPCHK(h, hipMemcpyAsync(t + k * slot, h->buf[h->cur], sb,
+                             hipMemcpyDeviceToDevice, h->stream));
+  }
+  h->tape = tape;
+  h->tape_steps = nsteps;
+  h->tape_interval = I;
+  return LBM_STEFAN_OK;
+}
+
+int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
+                             void *tape, size_t bytes, double *g_wall,
+                             double *g_ste, double *g_delta) {
+  if (int rc = check_adj(h)) return rc;
+  if (!tape || tape != h->tape || !dL_dfront)
+    return fail(h, LBM_STEFAN_EINVAL,
+                "tape is not the one of the last lbm_stefan_forward_tape");
+  const int64_t N = h->tape_steps, I = h->tape_interval;
+  const int64_t K = (N + I - 1) / I;
+  const size_t sb = state_bytes(h->p), slot = align256(sb);
+  if (bytes < (size_t)(K + 1 + I) * slot)
+    return fail(h, LBM_STEFAN_EINVAL, "tape too small");
+  DeviceGuard g(h->device);
+  const AdjLayout L = adj_layout(&h->p);
+  double *ab[2] = {(double *)(h->adj + L.abar0), (double *)(h->adj + L.abar1)};
+  char *t = (char *)tape;
+  char *seg = t + (K + 1) * slot;
+  HIPCHK(h, reset_async(h));
+  HIPCHK(h, front_vjp_async(h, t + K * slot, dL_dfront, ab[0]));
+  int c = 0;
+  for (int64_t k = K - 1; k >= 0; --k) {
+    const int64_t n = std::min(I, N - k * I);
+    // recompute the states of segment k
+    HIPCHK(h, hipMemcpyAsync(seg, t + k * slot, sb, hipMemcpyDeviceToDevice,
+                             h->stream));
+    for (int64_t j = 1; j < n; ++j)
+      HIPCHK(h, launch_step(h, seg + (j - 1) * slot, seg + j * slot));
+    for (int64_t j = n - 1; j >= 0; --j) {
+      HIPCHK(h, adjoint_step_async(h, seg + j * slot, ab[c], ab[c ^ 1]));
+      c ^= 1;
+    }
+  }
+  HIPCHK(h, init_term_async(h, ab[c]));
+  return read_gradients(h, g_wall, g_ste, g_delta);
+}
+
+int lbm_stefan_adjoint_buffers(lbm_stefan_t *h, double **abar0,
+                               double **abar1) {
+  if (int rc = check_adj(h)) return rc;
+  const AdjLayout L = adj_layout(&h->p);
+  if (abar0) *abar0 = (double *)(h->adj + L.abar0);
+  if (abar1) *abar1 = (double *)(h->adj + L.abar1);
+  return LBM_STEFAN_OK;
+}
+
+}  // extern "C"

@@ -271,10 +271,19 @@ __device__ inline double wall_value(const StepArgs &A, int wall, int x,
 //    temperature is T_D; the deficit is shared by weight among the
 //    remaining unknowns;
 // 3. anything left (corner of two bounce-back walls): own Omega_opp(i).
+// Masks of how each unknown was closed (for the reverse mode).
+struct CloseInfo {
+  uint32_t bb = 0;     // bounce-back from a known opposite
+  uint32_t share = 0;  // Dirichlet deficit share
+  uint32_t own = 0;    // own post-collision opposite population
+  int wall = -1;       // Dirichlet wall of the node
+  double TD = 0.0, wu = 0.0;
+};
+
 template <int Q>
 __device__ inline double close_node(const StepArgs &A, int x, int y,
                                     double th, const double *om, double *q,
-                                    uint32_t known) {
+                                    uint32_t known, CloseInfo *ci = nullptr) {
   uint32_t set = known;
   double fill = 0.0;
 #pragma unroll
@@ -285,9 +294,11 @@ __device__ inline double close_node(const StepArgs &A, int x, int y,
       q[i] = q[o];
       set |= 1u << i;
       fill += q[i];
+      if (ci) ci->bb |= 1u << i;
     }
   }
   const int wall = dirichlet_wall<Q>(A, x, y);
+  if (ci) ci->wall = wall;
   if (wall >= 0) {
     const double TD = wall_value(A, wall, x, y);
     double D = TD + (phi_only(TD, A.tm, A.inv_delta) -
@@ -303,7 +314,12 @@ __device__ inline double close_node(const StepArgs &A, int x, int y,
       if (!(set >> i & 1u)) {
         q[i] = D * (wt<Q>(i) / wu);
         fill += q[i];
+        if (ci) ci->share |= 1u << i;
       }
+    if (ci) {
+      ci->TD = TD;
+      ci->wu = wu;
+    }
     set = (1u << Q) - 1u;
   }
 #pragma unroll
@@ -311,6 +327,7 @@ __device__ inline double close_node(const StepArgs &A, int x, int y,
     if (!(set >> i & 1u)) {
       q[i] = om[opp<Q>(i)];
       fill += q[i];
+      if (ci) ci->own |= 1u << i;
     }
   return fill;
 }

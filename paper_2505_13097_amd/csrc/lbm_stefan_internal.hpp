@@ -46,6 +46,8 @@ struct lbm_stefan {
   char *adj = nullptr;
   int variant = 0;
   int64_t steps = 0;
+  void *tape = nullptr;          // last forward tape
+  int64_t tape_steps = 0, tape_interval = 0;
   std::string err;
 };
 

@@ -177,6 +177,79 @@ class Stefan:
         del scratch
         return v.value, ms.value
 
+    # -- reverse mode (handle created with flags=FLAG_ADJOINT) -----------
+    def adjoint_buffers(self):
+        a = ctypes.c_void_p()
+        b = ctypes.c_void_p()
+        C.check(self._lib.lbm_stefan_adjoint_buffers(self.h, ctypes.byref(a),
+                                                     ctypes.byref(b)), self.h)
+        return a.value, b.value
+
+    def adjoint_reset(self):
+        C.check(self._lib.lbm_stefan_adjoint_reset(self.h), self.h)
+
+    def front_vjp(self, state_ptr, dL_dfront, abar_ptr):
+        g = np.ascontiguousarray(dL_dfront, dtype=np.float64)
+        C.check(self._lib.lbm_stefan_front_vjp(
+            self.h, ctypes.c_void_p(state_ptr),
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            ctypes.c_void_p(abar_ptr)), self.h)
+
+    def adjoint_step(self, state_ptr, abar_in_ptr, abar_out_ptr):
+        C.check(self._lib.lbm_stefan_adjoint_step(
+            self.h, ctypes.c_void_p(state_ptr), ctypes.c_void_p(abar_in_ptr),
+            ctypes.c_void_p(abar_out_ptr)), self.h)
+
+    def adjoint_initial_state(self, abar_ptr):
+        C.check(self._lib.lbm_stefan_adjoint_initial_state(
+            self.h, ctypes.c_void_p(abar_ptr)), self.h)
+
+    def adjoint_gradients(self):
+        """Returns ({'x-','x+','y-','y+'}: wall gradients, dL/dSte,
+        dL/ddelta)."""
+        pr = self.prob
+        gw = np.zeros(2 * pr.ny + 2 * pr.nx)
+        gs = ctypes.c_double()
+        gd = ctypes.c_double()
+        C.check(self._lib.lbm_stefan_adjoint_gradients(
+            self.h, gw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            ctypes.byref(gs), ctypes.byref(gd)), self.h)
+        walls = {"x-": gw[:pr.ny], "x+": gw[pr.ny:2 * pr.ny],
+                 "y-": gw[2 * pr.ny:2 * pr.ny + pr.nx],
+                 "y+": gw[2 * pr.ny + pr.nx:]}
+        return walls, gs.value, gd.value
+
+    def forward_tape(self, nsteps, interval):
+        """Advance nsteps storing checkpoints every `interval` steps;
+        returns the tape (a device tensor) for backward_tape."""
+        n = ctypes.c_size_t()
+        C.check(self._lib.lbm_stefan_tape_bytes(ctypes.byref(self._params),
+                                                int(nsteps), int(interval),
+                                                ctypes.byref(n)))
+        tape = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        C.check(self._lib.lbm_stefan_forward_tape(
+            self.h, int(nsteps), int(interval), ctypes.c_void_p(tape.data_ptr()),
+            n.value), self.h)
+        return tape
+
+    def backward_tape(self, dL_dfront, tape):
+        """Gradients of a loss with dL/d(final integral front) = dL_dfront
+        with respect to the wall temperatures, Ste and delta."""
+        pr = self.prob
+        g = np.ascontiguousarray(dL_dfront, dtype=np.float64)
+        gw = np.zeros(2 * pr.ny + 2 * pr.nx)
+        gs = ctypes.c_double()
+        gd = ctypes.c_double()
+        dp = ctypes.POINTER(ctypes.c_double)
+        C.check(self._lib.lbm_stefan_backward_tape(
+            self.h, g.ctypes.data_as(dp), ctypes.c_void_p(tape.data_ptr()),
+            tape.numel(), gw.ctypes.data_as(dp), ctypes.byref(gs),
+            ctypes.byref(gd)), self.h)
+        walls = {"x-": gw[:pr.ny], "x+": gw[pr.ny:2 * pr.ny],
+                 "y-": gw[2 * pr.ny:2 * pr.ny + pr.nx],
+                 "y+": gw[2 * pr.ny + pr.nx:]}
+        return walls, gs.value, gd.value
+
     def close(self):
         if getattr(self, "h", None):
             C.check(self._lib.lbm_stefan_destroy(self.h))
@@ -288,3 +361,41 @@ class StefanBatch:
             self.close()
         except Exception:
             pass
+
+
+class HotWallFront(torch.autograd.Function):
+    """Final integral front position xf(y) of an IREBM run as a function of
+    the hot-wall (x-) temperature profile, Ste and delta.
+
+    forward(wall, ste, delta, prob, nsteps, interval): builds the lattice
+    of `prob` with these three values, runs nsteps on the GPU keeping a
+    checkpoint tape (every `interval` steps, sqrt(nsteps) by default) and
+    returns xf (ny,) as a float64 CPU tensor.  backward runs the reverse
+    sweep of the tape (recomputing each segment, implicit-function theorem
+    at every Newton root) and returns dL/dwall, dL/dSte, dL/ddelta.
+    """
+
+    @staticmethod
+    def forward(ctx, wall, ste, delta, prob, nsteps, interval=None):
+        import math
+        interval = interval or max(1, int(round(math.sqrt(nsteps))))
+        w = wall.detach().to("cpu", torch.float64).numpy()
+        p = prob.with_(wall_profile=(w, prob.wall_profile[1],
+                                     prob.wall_profile[2], prob.wall_profile[3]),
+                       ste=float(ste), delta=float(delta))
+        s = Stefan(p, flags=C.FLAG_ADJOINT)
+        tape = s.forward_tape(nsteps, interval)
+        xf = torch.from_numpy(s.front("integral"))
+        ctx.s, ctx.tape = s, tape
+        ctx.dtypes = (wall.dtype, wall.device)
+        return xf
+
+    @staticmethod
+    def backward(ctx, g):
+        walls, gs, gd = ctx.s.backward_tape(g.detach().cpu().numpy(), ctx.tape)
+        ctx.s.close()
+        ctx.tape = None
+        dt, dev = ctx.dtypes
+        gw = torch.from_numpy(walls["x-"].copy()).to(dev, dt)
+        return (gw, torch.tensor(gs, dtype=torch.float64),
+                torch.tensor(gd, dtype=torch.float64), None, None, None)

@@ -119,3 +119,26 @@ def test_variants_listed(L):
         assert len(names) >= 3
         assert all(re.fullmatch(r"\d+x\d+/npt\d", n) for n in names)
     assert L.lib().lbm_stefan_variant_name(5, 1, 999) == b""
+
+
+def test_tape_bytes(L):
+    p, _ = _params(L, synth.adjoint_2d(n=64, ny=32))
+    n = ctypes.c_size_t()
+    lib = L.lib()
+    assert lib.lbm_stefan_tape_bytes(ctypes.byref(p), 0, 8, ctypes.byref(n)) == L.EINVAL
+    assert lib.lbm_stefan_tape_bytes(ctypes.byref(p), 100, 0, ctypes.byref(n)) == L.EINVAL
+    assert lib.lbm_stefan_tape_bytes(ctypes.byref(p), 100, 10, ctypes.byref(n)) == L.OK
+    state = 5 * 64 * 32 * 4
+    assert n.value >= (10 + 1 + 10) * state
+
+
+def test_batch_rejects_mixed_lattices(L):
+    from paper_2505_13097_amd.stefan import make_params
+    a, _ = make_params(synth.planar_2d(n=64, ny=32))
+    b, _ = make_params(synth.cavity_2d(n=64, ny=32))
+    arr = (L.Params * 2)(a, b)
+    n = ctypes.c_size_t()
+    assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.EINVAL
+    arr = (L.Params * 2)(a, a)
+    assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.OK
+    assert n.value >= 2 * 2 * 5 * 64 * 32 * 4

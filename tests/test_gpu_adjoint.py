@@ -1,0 +1,171 @@
+"""GPU tests of the reverse mode: gradients of a front misfit with respect
+to the hot-wall temperature profile, Ste and delta, against the CPU
+oracle's adjoint (itself pinned by complex-step and finite differences),
+against central differences of the GPU forward in FP64, and the exactness
+of one reverse step (dot-product test)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _oracle_target(prob):
+    """Front of the twin run with the seeded target wall profile (oracle)."""
+    tw = synth.wall_target_profile(prob.ny)
+    tp = prob.with_(wall_profile=(tw, None, None, None))
+    f, _ = O.run(tp, O.init(tp, tp.T0), prob.nsteps)
+    return O.front(tp, f)
+
+
+def _gpu_grad(prob, target, interval):
+    from paper_2505_13097_amd import Stefan, _lib
+    s = Stefan(prob, flags=_lib.FLAG_ADJOINT)
+    tape = s.forward_tape(prob.nsteps, interval)
+    xf = s.front("integral")
+    walls, gs, gd = s.backward_tape(xf - target, tape)
+    s.close()
+    L = 0.5 * float(np.sum((xf - target) ** 2))
+    return L, walls["x-"], gs, gd
+
+
+CASES = [
+    ("d2q5_periodic", lambda st: synth.adjoint_2d(n=20, ny=8, nsteps=60,
+                                                  storage=st).with_(max_it=40)),
+    ("d2q9_cavity_profile", lambda st: synth.cavity_2d(
+        n=22, ny=9, nsteps=50, storage=st).with_(
+            tau=0.8, ste=0.2, delta=1.5 / 21, max_it=40,
+            wall_profile=(np.ones(9), None, None, None))),
+]
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-9), ("f32", 1e-3)])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_gradient_matches_oracle_adjoint(case, storage, tol):
+    name, make = CASES[case]
+    prob = make(storage)
+    po = prob.with_(storage="f64")
+    target = _oracle_target(po)
+    Lo, gwo, gso, gdo = O.front_loss_grad(po, po.T0, po.nsteps, target)
+    L, gw, gs, gd = _gpu_grad(prob, target, interval=8)
+    print(f"{name} {storage}: L {L:.6e} vs {Lo:.6e}; dSte {gs:.6e} vs {gso:.6e};"
+          f" ddelta {gd:.6e} vs {gdo:.6e}")
+    assert abs(L - Lo) <= max(tol, 1e-12) * abs(Lo) + 1e-20
+    assert abs(gs - gso) <= tol * abs(gso)
+    assert abs(gd - gdo) <= tol * abs(gdo)
+    assert np.max(np.abs(gw - gwo)) <= tol * np.max(np.abs(gwo))
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    prob = CASES[0][1]("f64")
+    target = _oracle_target(prob)
+    ref = _gpu_grad(prob, target, interval=prob.nsteps)
+    for interval in (1, 7, 8):
+        got = _gpu_grad(prob, target, interval)
+        assert got[0] == ref[0] and got[2] == ref[2] and got[3] == ref[3]
+        assert np.array_equal(got[1], ref[1])
+
+
+def test_reverse_step_dot_product_against_differences():
+    """<J v, w> = <v, J^T w> for one step in FP64, J v by central
+    differences of the GPU step."""
+    import torch
+    from paper_2505_13097_amd import Stefan, _lib
+    prob = synth.adjoint_2d(n=48, ny=24, storage="f64").with_(
+        wall_profile=(1.0 + 0.1 * np.sin(np.arange(24) / 3.0), None, None, None))
+    s = Stefan(prob, flags=_lib.FLAG_ADJOINT)
+    s.step(300)                         # a state with a front
+    base = s.state()
+    rng = np.random.Generator(np.random.PCG64(9))
+    v = rng.standard_normal(base.shape)
+    w = rng.standard_normal(base.shape)
+    eps = 1e-6
+
+    def step_from(st):
+        s.set_state(st)
+        s.step(1)
+        return s.state()
+    jv = (step_from(base + eps * v) - step_from(base - eps * v)) / (2 * eps)
+    # J^T w, with torch-allocated FP64 device arrays as abar buffers
+    st_dev = torch.from_numpy(base).cuda()
+    wt = torch.from_numpy(w).cuda()
+    jtw = torch.empty_like(wt)
+    s.adjoint_reset()
+    s.adjoint_step(st_dev.data_ptr(), wt.data_ptr(), jtw.data_ptr())
+    torch.cuda.synchronize()
+    lhs = float(np.sum(jv * w))
+    rhs = float(np.sum(v * jtw.cpu().numpy()))
+    print(f"dot product: {lhs:.12e} vs {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-7 * abs(lhs)
+    s.close()
+
+
+def _gpu_loss(prob, target):
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob)
+    g.step(prob.nsteps)
+    xf = g.front("integral")
+    g.close()
+    return 0.5 * float(np.sum((xf - target) ** 2))
+
+
+def test_full_size_adjoint_against_central_differences():
+    """The inverse-problem workload: D2Q5 512 x 512, 4096 steps, FP32
+    storage, checkpoints every 64 steps; gradients with respect to Ste,
+    delta and a seeded direction of the 512-value wall profile agree with
+    central differences of the FP64 forward to 1e-3 relative."""
+    prob = synth.adjoint_2d()
+    p64 = prob.with_(storage="f64")
+    tw = synth.wall_target_profile(prob.ny)
+    target = None
+    from paper_2505_13097_amd import Stefan
+    t = Stefan(p64.with_(wall_profile=(tw, None, None, None)))
+    t.step(prob.nsteps)
+    target = t.front("integral")
+    t.close()
+    L, gw, gs, gd = _gpu_grad(prob, target, interval=64)
+    assert L > 0
+    h = 1e-4
+    fd_s = (_gpu_loss(p64.with_(ste=prob.ste * (1 + h)), target) -
+            _gpu_loss(p64.with_(ste=prob.ste * (1 - h)), target)) / (2 * h * prob.ste)
+    fd_d = (_gpu_loss(p64.with_(delta=prob.delta * (1 + h)), target) -
+            _gpu_loss(p64.with_(delta=prob.delta * (1 - h)), target)) / (2 * h * prob.delta)
+    rng = np.random.Generator(np.random.PCG64(17))
+    u = rng.standard_normal(prob.ny)
+    w0 = prob.wall_profile[0]
+    fd_w = (_gpu_loss(p64.with_(wall_profile=(w0 + h * u, None, None, None)), target) -
+            _gpu_loss(p64.with_(wall_profile=(w0 - h * u, None, None, None)), target)) / (2 * h)
+    print(f"adjoint 512^2: dSte {gs:.6e} fd {fd_s:.6e}; ddelta {gd:.6e} fd {fd_d:.6e};"
+          f" dwall.u {gw @ u:.6e} fd {fd_w:.6e}")
+    assert abs(gs - fd_s) <= 1e-3 * abs(fd_s)
+    assert abs(gd - fd_d) <= 1e-3 * abs(fd_d)
+    assert abs(gw @ u - fd_w) <= 1e-3 * abs(fd_w)
+
+
+def test_autograd_function_matches_tape():
+    import torch
+    from paper_2505_13097_amd import HotWallFront
+    prob = CASES[0][1]("f32")
+    target = torch.from_numpy(_oracle_target(prob.with_(storage="f64")))
+    wall = torch.ones(prob.ny, dtype=torch.float64, requires_grad=True)
+    ste = torch.tensor(prob.ste, dtype=torch.float64, requires_grad=True)
+    delta = torch.tensor(prob.delta, dtype=torch.float64, requires_grad=True)
+    xf = HotWallFront.apply(wall, ste, delta, prob, prob.nsteps, 8)
+    L = 0.5 * torch.sum((xf - target) ** 2)
+    L.backward()
+    L2, gw, gs, gd = _gpu_grad(prob, target.numpy(), interval=8)
+    assert abs(float(L) - L2) <= 1e-12 * L2
+    assert np.array_equal(wall.grad.numpy(), gw)
+    assert float(ste.grad) == gs and float(delta.grad) == gd

@@ -23,7 +23,8 @@ def _mixed(storage, count=7, seed=11):
     probs = synth.batch_table(count=count, seed=seed, sizes=[64, 128, 192],
                               storage=storage, nsteps=300)
     # uneven: one non-square, one with a wall profile, one plain Newton
-    probs[1] = probs[1].with_(ny=96, T0=probs[1].T0[:96])
+    ny1 = probs[1].nx // 2 + 16
+    probs[1] = probs[1].with_(ny=ny1, T0=probs[1].T0[:ny1])
     probs[2] = probs[2].with_(wall_profile=(
         0.8 + 0.4 * np.sin(np.arange(probs[2].ny) / 7.0), None, None, None))
     probs[3] = probs[3].with_(newton_mode="plain")
