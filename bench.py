@@ -118,6 +118,50 @@ def time_batched(probs, steps, warmup, autotune=True, graph_steps=100):
     }
 
 
+def time_adjoint(prob, interval):
+    """The reverse mode: forward run keeping a checkpoint tape, then the
+    reverse sweep (segment recompute + reverse steps) giving dL/dT_wall
+    (512 values), dL/dSte and dL/ddelta for L = 1/2 sum (xf - xf*)^2,
+    with xf* the front of a twin run with a seeded wall profile."""
+    import numpy as np
+    import torch
+    import synth as S
+    from paper_2505_13097_amd import Stefan, _lib
+    twin = Stefan(prob.with_(wall_profile=(S.wall_target_profile(prob.ny),
+                                           None, None, None)))
+    twin.step(prob.nsteps)
+    target = twin.front("integral")
+    twin.close()
+    s = Stefan(prob, flags=_lib.FLAG_ADJOINT)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    tape = s.forward_tape(prob.nsteps, interval)
+    ev[1].record(stream)
+    xf = s.front("integral")
+    walls, gs, gd = s.backward_tape(xf - target, tape)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.close()
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    bwd_ms = ev[1].elapsed_time(ev[2])
+    lups = prob.nodes * prob.nsteps
+    return {
+        "workload": prob.name, "steps": prob.nsteps,
+        "checkpoint_interval": interval,
+        "value": round(lups / (bwd_ms * 1e-3) / 1e6, 1),
+        "unit": "MLUPS (reverse sweep: recompute + reverse steps)",
+        "forward_tape_mlups": round(lups / (fwd_ms * 1e-3) / 1e6, 1),
+        "total_s": round(t1 - t0, 4),
+        "loss": float(0.5 * np.sum((xf - target) ** 2)),
+        "grad_norms": {"wall": float(np.linalg.norm(walls["x-"])),
+                       "ste": gs, "delta": gd},
+    }
+
+
 def cpu_baseline(prob, steps=1):
     """The oracle, as it stands, on `steps` steps of the same lattice from
     the same initial state (single thread)."""
@@ -143,7 +187,7 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--forms", default="plain,batched",
+    ap.add_argument("--forms", default="plain,batched,adjoint",
                     help="comma list of extra forms to time: batched, adjoint")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--batch-count", type=int, default=512)
@@ -235,6 +279,11 @@ def main():
         probs = S.batch_table(count=args.batch_count, nsteps=args.batch_steps)
         forms["batched"] = time_batched(probs, args.batch_steps, 10)
         print("[bench] batched done", file=sys.stderr, flush=True)
+    if "adjoint" in args.forms.split(","):
+        import synth as S
+        print("[bench] adjoint form", file=sys.stderr, flush=True)
+        forms["adjoint"] = time_adjoint(S.adjoint_2d(), 64)
+        print("[bench] adjoint done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

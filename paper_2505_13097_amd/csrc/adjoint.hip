@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs G) {
   if (k < A.plane) {
     const int x = (int)(k % A.nx), y = (int)(k / A.nx);
     NodeLoad<Q, S> L;
-    load_node<Q, S, false>(A, x, y, L);
+    load_node<Q, S, false>(A, (const S *)A.src, x, y, L);
     double om[Q], q[Q], th = 0.0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {

@@ -40,14 +40,14 @@ __global__ __launch_bounds__(256) void batch_step_kernel(
   const int t_end = min(ntiles, (xcd + 1) * chunk);
   for (int t = xcd * chunk + lane; t < t_end; t += per_xcd_blocks) {
     const int2 e = tiles[t];
-    StepArgs A = descs[e.x];
-    if (parity) {
-      const void *s = A.src;
-      A.src = A.dst;
-      A.dst = const_cast<void *>(s);
-    }
-    step_tile<Q, S, NPT, PLAIN>(A, e.y % A.tiles_x, e.y / A.tiles_x,
-                                A.slots + e.y);
+    // block-uniform: the descriptor is read in place with scalar loads
+    const int inst = __builtin_amdgcn_readfirstlane(e.x);
+    const int tile = __builtin_amdgcn_readfirstlane(e.y);
+    const StepArgs &A = descs[inst];
+    const S *src = (const S *)(parity ? A.dst : A.src);
+    S *dst = (S *)(parity ? A.src : A.dst);
+    step_tile<Q, S, NPT, PLAIN>(A, src, dst, tile % A.tiles_x,
+                                tile / A.tiles_x, A.slots + tile);
   }
 }
 

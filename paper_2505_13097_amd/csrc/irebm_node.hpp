@@ -187,9 +187,8 @@ struct NodeLoad {
 // FAST: every pull source and destination of the node lies inside the
 // lattice without wrapping (interior tile); no checks are compiled.
 template <int Q, typename S, bool FAST>
-__device__ inline void load_node(const StepArgs &A, int x, int y,
-                                 NodeLoad<Q, S> &L) {
-  const S *__restrict__ src = (const S *)A.src;
+__device__ inline void load_node(const StepArgs &A, const S *__restrict__ src,
+                                 int x, int y, NodeLoad<Q, S> &L) {
   const int64_t P = A.plane;
   const int nx = A.nx;
   int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
@@ -334,8 +333,9 @@ __device__ inline double close_node(const StepArgs &A, int x, int y,
 
 // The update of one node from its loads; writes the next state.
 template <int Q, typename S, bool PLAIN, bool FAST>
-__device__ inline void update_node(const StepArgs &A, int x, int y,
-                                   const NodeLoad<Q, S> &L, NodeStats &st) {
+__device__ inline void update_node(const StepArgs &A, S *__restrict__ dst,
+                                   int x, int y, const NodeLoad<Q, S> &L,
+                                   NodeStats &st) {
   double om[Q], q[Q];
   double th = 0.0;
 #pragma unroll
@@ -370,7 +370,6 @@ __device__ inline void update_node(const StepArgs &A, int x, int y,
     f[i] = q[i] + A.wste[i] * dphi_s;
     tsum += f[i];
   }
-  S *__restrict__ dst = (S *)A.dst;
   const int64_t base = (int64_t)y * A.nx + x;
 #pragma unroll
   for (int i = 0; i < Q; ++i)

@@ -73,9 +73,11 @@ __device__ inline void block_stats_to_slot(const NodeStats &st, bool fast,
   __syncthreads();
 }
 
-// One tile (tx, ty) of the lattice described by A: load, update, stats.
+// One tile (tx, ty) of the lattice described by A, from state src to
+// state dst: load, update, stats.
 template <int Q, typename S, int NPT, bool PLAIN>
-__device__ inline void step_tile(const StepArgs &A, int tx, int ty,
+__device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
+                                 S *__restrict__ dst, int tx, int ty,
                                  StatSlot *slot) {
   const int bx = blockDim.x, by = blockDim.y;
   const int TW = bx * NPT;
@@ -88,19 +90,19 @@ __device__ inline void step_tile(const StepArgs &A, int tx, int ty,
     NodeLoad<Q, S> L[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
-      load_node<Q, S, true>(A, x0 + (int)threadIdx.x + k * bx, y, L[k]);
+      load_node<Q, S, true>(A, src, x0 + (int)threadIdx.x + k * bx, y, L[k]);
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
-      update_node<Q, S, PLAIN, true>(A, x0 + (int)threadIdx.x + k * bx, y,
-                                     L[k], st);
+      update_node<Q, S, PLAIN, true>(A, dst, x0 + (int)threadIdx.x + k * bx,
+                                     y, L[k], st);
   } else {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int x = x0 + (int)threadIdx.x + k * bx;
       if (x < A.nx && y < A.ny) {
         NodeLoad<Q, S> L;
-        load_node<Q, S, false>(A, x, y, L);
-        update_node<Q, S, PLAIN, false>(A, x, y, L, st);
+        load_node<Q, S, false>(A, src, x, y, L);
+        update_node<Q, S, PLAIN, false>(A, dst, x, y, L, st);
       }
     }
   }
@@ -117,7 +119,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int b = blockIdx.x;
   const int t = (b & 7) * A.per_xcd + (b >> 3);
   if (t >= A.ntiles) return;
-  step_tile<Q, S, NPT, PLAIN>(A, t % A.tiles_x, t / A.tiles_x, A.slots + t);
+  step_tile<Q, S, NPT, PLAIN>(A, (const S *)A.src, (S *)A.dst, t % A.tiles_x,
+                              t / A.tiles_x, A.slots + t);
 }
 
 // ---------------------------------------------------------------------
