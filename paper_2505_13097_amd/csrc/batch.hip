@@ -29,26 +29,44 @@ using namespace irebm;
 
 namespace {
 
-// tiles[t] = (instance, tile index within the instance)
-template <int Q, typename S, int NPT, bool PLAIN>
+// one tile of the table: tiles[t] = (instance, tile index within it); the
+// descriptor is block-uniform and read in place with scalar loads
+template <int Q, typename S, int NPT, bool PLAIN, bool NT>
+__device__ inline void batch_tile(const StepArgs *__restrict__ descs,
+                                  const int2 *__restrict__ tiles, int t,
+                                  int parity) {
+  const int2 e = tiles[t];
+  const int inst = __builtin_amdgcn_readfirstlane(e.x);
+  const int tile = __builtin_amdgcn_readfirstlane(e.y);
+  const StepArgs &A = descs[inst];
+  const S *src = (const S *)(parity ? A.dst : A.src);
+  S *dst = (S *)(parity ? A.src : A.dst);
+  step_tile<Q, S, NPT, PLAIN, NT>(A, src, dst, tile % A.tiles_x,
+                                  tile / A.tiles_x, A.slots + tile);
+}
+
+// persistent == 0: one block per tile, blocks of XCD k taking the k-th
+// contiguous chunk of the table.  persistent != 0: a grid sized to the
+// machine, each block walking its XCD's chunk with a stride.
+template <int Q, typename S, int NPT, bool PLAIN, bool NT>
 __global__ __launch_bounds__(256) void batch_step_kernel(
     const StepArgs *__restrict__ descs, const int2 *__restrict__ tiles,
-    int32_t ntiles, int32_t parity) {
+    int32_t ntiles, int32_t parity, int32_t reverse, int32_t persistent) {
+  const int chunk = (ntiles + 7) >> 3;
+  if (!persistent) {
+    const int b = (int)blockIdx.x;
+    if ((b & 7) * chunk + (b >> 3) >= ntiles) return;
+    batch_tile<Q, S, NPT, PLAIN, NT>(descs, tiles,
+                                     xcd_tile(b, chunk, ntiles, reverse),
+                                     parity);
+    return;
+  }
   const int per_xcd_blocks = (int)(gridDim.x >> 3);
   const int xcd = (int)(blockIdx.x & 7), lane = (int)(blockIdx.x >> 3);
-  const int chunk = (ntiles + 7) >> 3;
   const int t_end = min(ntiles, (xcd + 1) * chunk);
-  for (int t = xcd * chunk + lane; t < t_end; t += per_xcd_blocks) {
-    const int2 e = tiles[t];
-    // block-uniform: the descriptor is read in place with scalar loads
-    const int inst = __builtin_amdgcn_readfirstlane(e.x);
-    const int tile = __builtin_amdgcn_readfirstlane(e.y);
-    const StepArgs &A = descs[inst];
-    const S *src = (const S *)(parity ? A.dst : A.src);
-    S *dst = (S *)(parity ? A.src : A.dst);
-    step_tile<Q, S, NPT, PLAIN>(A, src, dst, tile % A.tiles_x,
-                                tile / A.tiles_x, A.slots + tile);
-  }
+  for (int t = xcd * chunk + lane; t < t_end; t += per_xcd_blocks)
+    batch_tile<Q, S, NPT, PLAIN, NT>(descs, tiles,
+                                     reverse ? ntiles - 1 - t : t, parity);
 }
 
 }  // namespace
@@ -71,7 +89,7 @@ struct lbm_stefan_batch {
   std::vector<int64_t> first_tile, ntiles_inst;
   int64_t max_tiles = 0, ntiles = 0;
   int cur = 0;
-  int variant = kDefaultVariant2D, blocks_per_cu = 4, graph_steps = 0;
+  int variant = kDefaultVariant2D, blocks_per_cu = 0, graph_steps = 0;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int64_t steps = 0;
   std::string err;
@@ -214,23 +232,31 @@ hipError_t launch_batch_t(const lbm_stefan_batch_t *b, hipStream_t stream,
                           int parity) {
   int nv;
   const Variant &v = variants(Q, &nv)[b->variant];
-  const int64_t want = (int64_t)b->cus * b->blocks_per_cu;
-  const int64_t g8 = std::min<int64_t>((want + 7) / 8, (b->ntiles + 7) / 8);
+  const int64_t chunk = (b->ntiles + 7) / 8;
+  int64_t g8 = chunk;  // one block per tile
+  if (b->blocks_per_cu > 0)
+    g8 = std::min<int64_t>(((int64_t)b->cus * b->blocks_per_cu + 7) / 8, chunk);
   dim3 grid((unsigned)(8 * std::max<int64_t>(g8, 1))), block(v.bx, v.by);
   const int32_t nt = (int32_t)b->ntiles;
-#define BLAUNCH(NPT, PL)                                                \
-  batch_step_kernel<Q, S, NPT, PL><<<grid, block, 0, stream>>>(b->descs, \
-                                                               b->tiles, \
-                                                               nt, parity)
+  const int32_t rev = v.rev && parity;
+  const int32_t pers = b->blocks_per_cu > 0;
+#define BLAUNCH(NPT, PL, NTS)                                          \
+  batch_step_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>(   \
+      b->descs, b->tiles, nt, parity, rev, pers)
+#define BLAUNCH_NPT(PL, NTS)                  \
+  do {                                        \
+    if (v.npt == 1) BLAUNCH(1, PL, NTS);      \
+    else if (v.npt == 2) BLAUNCH(2, PL, NTS); \
+    else BLAUNCH(4, PL, NTS);                 \
+  } while (0)
   if (b->plain) {
-    if (v.npt == 1) BLAUNCH(1, true);
-    else if (v.npt == 2) BLAUNCH(2, true);
-    else BLAUNCH(4, true);
+    if (v.nt) BLAUNCH_NPT(true, true);
+    else BLAUNCH_NPT(true, false);
   } else {
-    if (v.npt == 1) BLAUNCH(1, false);
-    else if (v.npt == 2) BLAUNCH(2, false);
-    else BLAUNCH(4, false);
+    if (v.nt) BLAUNCH_NPT(false, true);
+    else BLAUNCH_NPT(false, false);
   }
+#undef BLAUNCH_NPT
 #undef BLAUNCH
   return hipGetLastError();
 }
@@ -387,8 +413,8 @@ int lbm_stefan_batch_set_schedule(lbm_stefan_batch_t *b, int32_t variant,
   variants(b->q, &nv);
   if (variant < -1 || variant >= nv)
     return bfail(b, LBM_STEFAN_EINVAL, "unknown kernel variant");
-  if (blocks_per_cu < 1 || blocks_per_cu > 32)
-    return bfail(b, LBM_STEFAN_EINVAL, "blocks_per_cu must be in 1..32");
+  if (blocks_per_cu < 0 || blocks_per_cu > 32)
+    return bfail(b, LBM_STEFAN_EINVAL, "blocks_per_cu must be in 0..32");
   if (graph_steps < 0 || graph_steps % 2 || graph_steps > 100000)
     return bfail(b, LBM_STEFAN_EINVAL,
                  "graph_steps must be even and in 0..100000");
@@ -554,7 +580,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
   }
   int nv;
   variants(b->q, &nv);
-  const int bpcs[] = {1, 2, 4, 8};
+  const int bpcs[] = {0, 2, 4, 8};
   const int v0 = b->variant, bpc0 = b->blocks_per_cu;
   int best_v = v0, best_bpc = bpc0;
   float best_ms = -1.0f;

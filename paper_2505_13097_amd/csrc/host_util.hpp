@@ -14,17 +14,22 @@
 namespace irebm {
 
 // A kernel variant: block of bx x by threads, each thread updating npt
-// nodes bx apart along x; the tile is (bx * npt) x by nodes.
+// nodes bx apart along x; the tile is (bx * npt) x by nodes.  nt: stores
+// bypass the caches (non-temporal); rev: the tile order is reversed on
+// every other step, so that the rows written last (still in the
+// memory-side cache) are read first.
 struct Variant {
-  int bx, by, npt;
+  int bx, by, npt, nt, rev;
 };
 
 inline const Variant *variants(int q, int *n) {
-  static const Variant v1[] = {{256, 1, 1}, {128, 1, 1}, {64, 1, 1},
-                               {256, 1, 2}};
-  static const Variant v2[] = {{64, 4, 1},  {256, 1, 1}, {128, 2, 1},
-                               {64, 4, 2},  {128, 2, 2}, {256, 1, 2},
-                               {64, 2, 2},  {64, 4, 4}};
+  static const Variant v1[] = {{256, 1, 1, 0, 0}, {128, 1, 1, 0, 0},
+                               {64, 1, 1, 0, 0}, {256, 1, 2, 0, 0}};
+  static const Variant v2[] = {
+      {64, 4, 1, 0, 0},  {256, 1, 1, 0, 0}, {128, 2, 1, 0, 0},
+      {64, 4, 2, 0, 0},  {128, 2, 2, 0, 0}, {256, 1, 2, 0, 0},
+      {64, 2, 2, 0, 0},  {64, 4, 4, 0, 0},  {64, 4, 2, 1, 0},
+      {64, 4, 2, 0, 1},  {64, 4, 2, 1, 1},  {128, 2, 2, 0, 1}};
   if (q == 3) {
     *n = (int)(sizeof(v1) / sizeof(Variant));
     return v1;

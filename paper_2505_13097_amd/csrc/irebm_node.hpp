@@ -68,6 +68,7 @@ struct StepArgs {
   int32_t nx, ny;
   int64_t plane;        // nx * ny
   int32_t tiles_x, ntiles, per_xcd;
+  int32_t reverse;      // sweep the tiles in reverse order
   int32_t periodic_x, periodic_y;
   double a;             // 1 - 1/tau
   double wtau[9];       // w_i / tau
@@ -332,7 +333,7 @@ __device__ inline double close_node(const StepArgs &A, int x, int y,
 }
 
 // The update of one node from its loads; writes the next state.
-template <int Q, typename S, bool PLAIN, bool FAST>
+template <int Q, typename S, bool PLAIN, bool FAST, bool NT = false>
 __device__ inline void update_node(const StepArgs &A, S *__restrict__ dst,
                                    int x, int y, const NodeLoad<Q, S> &L,
                                    NodeStats &st) {
@@ -372,8 +373,11 @@ __device__ inline void update_node(const StepArgs &A, S *__restrict__ dst,
   }
   const int64_t base = (int64_t)y * A.nx + x;
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    dst[i * A.plane + base] = (S)(A.a * f[i] + A.wtau[i] * tsum);
+  for (int i = 0; i < Q; ++i) {
+    const S v = (S)(A.a * f[i] + A.wtau[i] * tsum);
+    if (NT) __builtin_nontemporal_store(v, dst + i * A.plane + base);
+    else dst[i * A.plane + base] = v;
+  }
   const double res = fabs(tn + pnew * A.inv_ste - (m0 + pth * A.inv_ste));
   st.max_it = it > st.max_it ? it : st.max_it;
   st.nonconv += conv ? 0 : 1;

@@ -74,8 +74,9 @@ __device__ inline void block_stats_to_slot(const NodeStats &st, bool fast,
 }
 
 // One tile (tx, ty) of the lattice described by A, from state src to
-// state dst: load, update, stats.
-template <int Q, typename S, int NPT, bool PLAIN>
+// state dst: all loads of the thread's nodes first (memory-level
+// parallelism), then the updates, then the statistics.
+template <int Q, typename S, int NPT, bool PLAIN, bool NT = false>
 __device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
                                  S *__restrict__ dst, int tx, int ty,
                                  StatSlot *slot) {
@@ -86,41 +87,49 @@ __device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
   const int y = y0 + (int)threadIdx.y;
   NodeStats st;
+  NodeLoad<Q, S> L[NPT];
   if (fast) {
-    NodeLoad<Q, S> L[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
       load_node<Q, S, true>(A, src, x0 + (int)threadIdx.x + k * bx, y, L[k]);
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
-      update_node<Q, S, PLAIN, true>(A, dst, x0 + (int)threadIdx.x + k * bx,
-                                     y, L[k], st);
+      update_node<Q, S, PLAIN, true, NT>(A, dst, x0 + (int)threadIdx.x + k * bx,
+                                         y, L[k], st);
   } else {
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int x = x0 + (int)threadIdx.x + k * bx;
-      if (x < A.nx && y < A.ny) {
-        NodeLoad<Q, S> L;
-        load_node<Q, S, false>(A, src, x, y, L);
-        update_node<Q, S, PLAIN, false>(A, dst, x, y, L, st);
-      }
+      if (x < A.nx && y < A.ny) load_node<Q, S, false>(A, src, x, y, L[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int x = x0 + (int)threadIdx.x + k * bx;
+      if (x < A.nx && y < A.ny)
+        update_node<Q, S, PLAIN, false, NT>(A, dst, x, y, L[k], st);
     }
   }
   block_stats_to_slot(st, fast, slot);
 }
 
+// tile of block b: the blocks of XCD k (b mod 8 = k) take the k-th
+// contiguous chunk of the tile order, optionally swept backwards
+__device__ inline int xcd_tile(int b, int per_xcd, int ntiles, int reverse) {
+  const int t = (b & 7) * per_xcd + (b >> 3);
+  return reverse ? ntiles - 1 - t : t;
+}
+
 namespace {
 
 
-// one time step of one lattice; block b works on tile
-// (b mod 8) * per_xcd + b div 8 (XCD-aware order)
-template <int Q, typename S, int NPT, bool PLAIN>
+// one time step of one lattice, one block per tile (XCD-aware order)
+template <int Q, typename S, int NPT, bool PLAIN, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int b = blockIdx.x;
-  const int t = (b & 7) * A.per_xcd + (b >> 3);
-  if (t >= A.ntiles) return;
-  step_tile<Q, S, NPT, PLAIN>(A, (const S *)A.src, (S *)A.dst, t % A.tiles_x,
-                              t / A.tiles_x, A.slots + t);
+  if ((b & 7) * A.per_xcd + (b >> 3) >= A.ntiles) return;
+  const int t = xcd_tile(b, A.per_xcd, A.ntiles, A.reverse);
+  step_tile<Q, S, NPT, PLAIN, NT>(A, (const S *)A.src, (S *)A.dst,
+                                  t % A.tiles_x, t / A.tiles_x, A.slots + t);
 }
 
 // ---------------------------------------------------------------------

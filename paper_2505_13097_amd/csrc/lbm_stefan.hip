@@ -161,18 +161,24 @@ hipError_t launch_step_t(const lbm_stefan_t *h, const StepArgs &A,
   B.tiles_x = (int32_t)tiles_x_for(v, h->p.nx);
   B.ntiles = (int32_t)ntiles;
   B.per_xcd = per_xcd;
+  B.reverse = v.rev && (h->steps & 1);
   dim3 grid(8 * per_xcd), block(v.bx, v.by);
-#define LAUNCH(NPT, PL) \
-  step_kernel<Q, S, NPT, PL><<<grid, block, 0, h->stream>>>(B)
+#define LAUNCH(NPT, PL, NT) \
+  step_kernel<Q, S, NPT, PL, NT><<<grid, block, 0, h->stream>>>(B)
+#define LAUNCH_NPT(PL, NT)                 \
+  do {                                     \
+    if (v.npt == 1) LAUNCH(1, PL, NT);     \
+    else if (v.npt == 2) LAUNCH(2, PL, NT); \
+    else LAUNCH(4, PL, NT);                \
+  } while (0)
   if (plain) {
-    if (v.npt == 1) LAUNCH(1, true);
-    else if (v.npt == 2) LAUNCH(2, true);
-    else LAUNCH(4, true);
+    if (v.nt) LAUNCH_NPT(true, true);
+    else LAUNCH_NPT(true, false);
   } else {
-    if (v.npt == 1) LAUNCH(1, false);
-    else if (v.npt == 2) LAUNCH(2, false);
-    else LAUNCH(4, false);
+    if (v.nt) LAUNCH_NPT(false, true);
+    else LAUNCH_NPT(false, false);
   }
+#undef LAUNCH_NPT
 #undef LAUNCH
   return hipGetLastError();
 }
@@ -469,8 +475,9 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
     return "";
   const Variant *v = variants(q, &n);
   if (variant < 0 || variant >= n) return "";
-  std::snprintf(buf, sizeof(buf), "%dx%d/npt%d", v[variant].bx * v[variant].npt,
-                v[variant].by, v[variant].npt);
+  std::snprintf(buf, sizeof(buf), "%dx%d/npt%d%s%s",
+                v[variant].bx * v[variant].npt, v[variant].by, v[variant].npt,
+                v[variant].nt ? "/nt" : "", v[variant].rev ? "/rev" : "");
   return buf;
 }
 

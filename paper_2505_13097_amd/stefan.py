@@ -301,7 +301,7 @@ class StefanBatch:
     def __len__(self):
         return len(self.probs)
 
-    def set_schedule(self, variant=-1, blocks_per_cu=4, graph_steps=0):
+    def set_schedule(self, variant=-1, blocks_per_cu=0, graph_steps=0):
         C.check_batch(self._lib.lbm_stefan_batch_set_schedule(
             self.h, int(variant), int(blocks_per_cu), int(graph_steps)), self.h)
 
