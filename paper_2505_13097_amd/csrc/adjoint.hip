@@ -51,12 +51,12 @@ struct AdjArgs {
   double dx, delta, ste;
 };
 
-__device__ inline double dphi_ddelta(double t, double tm, double delta,
+__device__ __forceinline__ double dphi_ddelta(double t, double tm, double delta,
                                      double dph) {
   return -((t - tm) / delta) * dph;
 }
 
-__device__ inline void block_add2(double a, double b, double *ga, double *gb) {
+__device__ __forceinline__ void block_add2(double a, double b, double *ga, double *gb) {
   __shared__ double s[8];
   a = wave_sum(a);
   b = wave_sum(b);
@@ -72,7 +72,7 @@ __device__ inline void block_add2(double a, double b, double *ga, double *gb) {
   }
 }
 
-__device__ inline int wall_index(int wall, int x, int y) {
+__device__ __forceinline__ int wall_index(int wall, int x, int y) {
   return wall < 2 ? y : x;
 }
 

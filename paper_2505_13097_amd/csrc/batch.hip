@@ -32,7 +32,7 @@ namespace {
 // one tile of the table: tiles[t] = (instance, tile index within it); the
 // descriptor is block-uniform and read in place with scalar loads
 template <int Q, typename S, int NPT, bool PLAIN, bool NT>
-__device__ inline void batch_tile(const StepArgs *__restrict__ descs,
+__device__ __forceinline__ void batch_tile(const StepArgs *__restrict__ descs,
                                   const int2 *__restrict__ tiles, int t,
                                   int parity) {
   const int2 e = tiles[t];
@@ -45,22 +45,26 @@ __device__ inline void batch_tile(const StepArgs *__restrict__ descs,
                                   tile / A.tiles_x, A.slots + tile);
 }
 
-// persistent == 0: one block per tile, blocks of XCD k taking the k-th
-// contiguous chunk of the table.  persistent != 0: a grid sized to the
-// machine, each block walking its XCD's chunk with a stride.
+// one block per tile, the blocks of XCD k taking the k-th contiguous
+// chunk of the table
 template <int Q, typename S, int NPT, bool PLAIN, bool NT>
 __global__ __launch_bounds__(256) void batch_step_kernel(
     const StepArgs *__restrict__ descs, const int2 *__restrict__ tiles,
-    int32_t ntiles, int32_t parity, int32_t reverse, int32_t persistent) {
+    int32_t ntiles, int32_t parity, int32_t reverse) {
   const int chunk = (ntiles + 7) >> 3;
-  if (!persistent) {
-    const int b = (int)blockIdx.x;
-    if ((b & 7) * chunk + (b >> 3) >= ntiles) return;
-    batch_tile<Q, S, NPT, PLAIN, NT>(descs, tiles,
-                                     xcd_tile(b, chunk, ntiles, reverse),
-                                     parity);
-    return;
-  }
+  const int b = (int)blockIdx.x;
+  if ((b & 7) * chunk + (b >> 3) >= ntiles) return;
+  batch_tile<Q, S, NPT, PLAIN, NT>(descs, tiles,
+                                   xcd_tile(b, chunk, ntiles, reverse), parity);
+}
+
+// persistent grid sized to the machine: each block walks its XCD's chunk
+// of the table with a stride
+template <int Q, typename S, int NPT, bool PLAIN, bool NT>
+__global__ __launch_bounds__(256) void batch_persistent_kernel(
+    const StepArgs *__restrict__ descs, const int2 *__restrict__ tiles,
+    int32_t ntiles, int32_t parity, int32_t reverse) {
+  const int chunk = (ntiles + 7) >> 3;
   const int per_xcd_blocks = (int)(gridDim.x >> 3);
   const int xcd = (int)(blockIdx.x & 7), lane = (int)(blockIdx.x >> 3);
   const int t_end = min(ntiles, (xcd + 1) * chunk);
@@ -240,9 +244,15 @@ hipError_t launch_batch_t(const lbm_stefan_batch_t *b, hipStream_t stream,
   const int32_t nt = (int32_t)b->ntiles;
   const int32_t rev = v.rev && parity;
   const int32_t pers = b->blocks_per_cu > 0;
-#define BLAUNCH(NPT, PL, NTS)                                          \
-  batch_step_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>(   \
-      b->descs, b->tiles, nt, parity, rev, pers)
+#define BLAUNCH(NPT, PL, NTS)                                              \
+  do {                                                                     \
+    if (pers)                                                              \
+      batch_persistent_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>( \
+          b->descs, b->tiles, nt, parity, rev);                            \
+    else                                                                   \
+      batch_step_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>(   \
+          b->descs, b->tiles, nt, parity, rev);                            \
+  } while (0)
 #define BLAUNCH_NPT(PL, NTS)                  \
   do {                                        \
     if (v.npt == 1) BLAUNCH(1, PL, NTS);      \

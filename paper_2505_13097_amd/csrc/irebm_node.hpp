@@ -86,7 +86,7 @@ struct StepArgs {
 // phi'(T) = (1 - tanh^2 u)/(2 delta) = 2 e/(1 + e)^2 / delta with
 // e = exp(-2u).  Past |u| > 20, tanh(u) rounds to +-1 in double, so
 // phi is exactly 0 or 1 there and phi' is 0.
-__device__ inline void phi_dphi(double t, double tm, double inv_delta,
+__device__ __forceinline__ void phi_dphi(double t, double tm, double inv_delta,
                                 double &ph, double &dph) {
   const double u = (t - tm) * inv_delta;
   if (u > 20.0) {
@@ -103,7 +103,7 @@ __device__ inline void phi_dphi(double t, double tm, double inv_delta,
   }
 }
 
-__device__ inline double phi_only(double t, double tm, double inv_delta) {
+__device__ __forceinline__ double phi_only(double t, double tm, double inv_delta) {
   const double u = (t - tm) * inv_delta;
   if (u > 20.0) return 1.0;
   if (u < -20.0) return 0.0;
@@ -119,7 +119,7 @@ __device__ inline double phi_only(double t, double tm, double inv_delta) {
 // the bracket or fails to halve the step before the last.  Stops when
 // |t_{k+1} - t_k| <= tol, then takes one more Newton step (below).
 template <bool PLAIN>
-__device__ inline double newton(double m0, double th, double pth,
+__device__ __forceinline__ double newton(double m0, double th, double pth,
                                 const StepArgs &A, int &iters, bool &conv) {
   const double s = A.inv_ste;
   const double c = m0 + pth * s;
@@ -187,26 +187,35 @@ struct NodeLoad {
 
 // FAST: every pull source and destination of the node lies inside the
 // lattice without wrapping (interior tile); no checks are compiled.
+// Otherwise sources are wrapped on periodic axes and clamped into the
+// lattice elsewhere, so every load is issued unconditionally (no branch
+// around a load); the values of unknown directions are then zeroed and
+// left to the closure.
 template <int Q, typename S, bool FAST>
-__device__ inline void load_node(const StepArgs &A, const S *__restrict__ src,
-                                 int x, int y, NodeLoad<Q, S> &L) {
+__device__ __forceinline__ void load_node(const StepArgs &A,
+                                          const S *__restrict__ src, int x,
+                                          int y, NodeLoad<Q, S> &L) {
   const int64_t P = A.plane;
   const int nx = A.nx;
   int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
   bool vxm = true, vxp = true, vym = true, vyp = true;
   if (!FAST) {
     if (xm < 0) {
-      if (A.periodic_x) xm += nx; else vxm = false;
+      vxm = A.periodic_x != 0;
+      xm = vxm ? xm + nx : 0;
     }
     if (xp >= nx) {
-      if (A.periodic_x) xp -= nx; else vxp = false;
+      vxp = A.periodic_x != 0;
+      xp = vxp ? xp - nx : nx - 1;
     }
     if (Q > 3) {
       if (ym < 0) {
-        if (A.periodic_y) ym += A.ny; else vym = false;
+        vym = A.periodic_y != 0;
+        ym = vym ? ym + A.ny : 0;
       }
       if (yp >= A.ny) {
-        if (A.periodic_y) yp -= A.ny; else vyp = false;
+        vyp = A.periodic_y != 0;
+        yp = vyp ? yp - A.ny : A.ny - 1;
       }
     }
   }
@@ -221,24 +230,25 @@ __device__ inline void load_node(const StepArgs &A, const S *__restrict__ src,
     const int ex = cx<Q>(i), ey = cy<Q>(i);
     const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
     const int sy = ey == 1 ? ym : (ey == -1 ? yp : y);
-    const bool ok = (ex == 1 ? vxm : (ex == -1 ? vxp : true)) &&
-                    (ey == 1 ? vym : (ey == -1 ? vyp : true));
-    const bool leaves = (ex == 1 ? !vxp : (ex == -1 ? !vxm : false)) ||
-                        (ey == 1 ? !vyp : (ey == -1 ? !vym : false));
-    if (FAST || ok) {
-      L.pull[i] = src[i * P + (int64_t)sy * nx + sx];
-      L.known |= 1u << i;
+    L.pull[i] = src[i * P + (int64_t)sy * nx + sx];
+    if (!FAST) {
+      const bool ok = (ex == 1 ? vxm : (ex == -1 ? vxp : true)) &&
+                      (ey == 1 ? vym : (ey == -1 ? vyp : true));
+      const bool leaves = (ex == 1 ? !vxp : (ex == -1 ? !vxm : false)) ||
+                          (ey == 1 ? !vyp : (ey == -1 ? !vym : false));
+      if (ok) L.known |= 1u << i;
+      else L.pull[i] = (S)0;
+      if (leaves) L.out |= 1u << i;
     } else {
-      L.pull[i] = (S)0;
+      L.known |= 1u << i;
     }
-    if (!FAST && leaves) L.out |= 1u << i;
   }
 }
 
 // Does the unknown direction i of node (x, y) leave the lattice only
 // through bounce-back walls?
 template <int Q>
-__device__ inline bool leaves_by_bounceback(const StepArgs &A, int x, int y,
+__device__ __forceinline__ bool leaves_by_bounceback(const StepArgs &A, int x, int y,
                                             int i) {
   const int sx = x - cx<Q>(i), sy = y - cy<Q>(i);
   if (sx < 0 && A.bc[0] != BC_BOUNCEBACK) return false;
@@ -249,7 +259,7 @@ __device__ inline bool leaves_by_bounceback(const StepArgs &A, int x, int y,
 }
 
 template <int Q>
-__device__ inline int dirichlet_wall(const StepArgs &A, int x, int y) {
+__device__ __forceinline__ int dirichlet_wall(const StepArgs &A, int x, int y) {
   if (x == 0 && A.bc[0] == BC_DIRICHLET) return 0;
   if (x == A.nx - 1 && A.bc[1] == BC_DIRICHLET) return 1;
   if (Q > 3 && y == 0 && A.bc[2] == BC_DIRICHLET) return 2;
@@ -257,7 +267,7 @@ __device__ inline int dirichlet_wall(const StepArgs &A, int x, int y) {
   return -1;
 }
 
-__device__ inline double wall_value(const StepArgs &A, int wall, int x,
+__device__ __forceinline__ double wall_value(const StepArgs &A, int wall, int x,
                                     int y) {
   const double *p = A.prof[wall];
   return p ? p[wall < 2 ? y : x] : A.wall_T[wall];
@@ -281,7 +291,7 @@ struct CloseInfo {
 };
 
 template <int Q>
-__device__ inline double close_node(const StepArgs &A, int x, int y,
+__device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
                                     double th, const double *om, double *q,
                                     uint32_t known, CloseInfo *ci = nullptr) {
   uint32_t set = known;
@@ -334,7 +344,7 @@ __device__ inline double close_node(const StepArgs &A, int x, int y,
 
 // The update of one node from its loads; writes the next state.
 template <int Q, typename S, bool PLAIN, bool FAST, bool NT = false>
-__device__ inline void update_node(const StepArgs &A, S *__restrict__ dst,
+__device__ __forceinline__ void update_node(const StepArgs &A, S *__restrict__ dst,
                                    int x, int y, const NodeLoad<Q, S> &L,
                                    NodeStats &st) {
   double om[Q], q[Q];
@@ -385,22 +395,22 @@ __device__ inline void update_node(const StepArgs &A, S *__restrict__ dst,
 }
 
 // ---- wave and block reductions (wave64)
-__device__ inline double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
-__device__ inline double wave_max(double v) {
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
-__device__ inline int wave_max_i(int v) {
+__device__ __forceinline__ int wave_max_i(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
 }
-__device__ inline int wave_sum_i(int v) {
+__device__ __forceinline__ int wave_sum_i(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

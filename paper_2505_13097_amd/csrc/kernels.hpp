@@ -30,7 +30,7 @@ constexpr int kEnergyChunk = 2048;  // nodes per energy partial
 // Statistics of one block (already reduced over the node loop of each
 // thread), combined across the block and added to the tile's slot by
 // thread 0.
-__device__ inline void block_stats_to_slot(const NodeStats &st, bool fast,
+__device__ __forceinline__ void block_stats_to_slot(const NodeStats &st, bool fast,
                                            StatSlot *sl) {
   __shared__ int s_it[4], s_nc[4];
   __shared__ double s_res[4], s_fin[4], s_fout[4];
@@ -74,10 +74,10 @@ __device__ inline void block_stats_to_slot(const NodeStats &st, bool fast,
 }
 
 // One tile (tx, ty) of the lattice described by A, from state src to
-// state dst: all loads of the thread's nodes first (memory-level
-// parallelism), then the updates, then the statistics.
+// state dst: on interior tiles all loads of the thread's nodes first
+// (memory-level parallelism), then the updates; then the statistics.
 template <int Q, typename S, int NPT, bool PLAIN, bool NT = false>
-__device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
+__device__ __forceinline__ void step_tile(const StepArgs &A, const S *__restrict__ src,
                                  S *__restrict__ dst, int tx, int ty,
                                  StatSlot *slot) {
   const int bx = blockDim.x, by = blockDim.y;
@@ -87,8 +87,8 @@ __device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
   const int y = y0 + (int)threadIdx.y;
   NodeStats st;
-  NodeLoad<Q, S> L[NPT];
   if (fast) {
+    NodeLoad<Q, S> L[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
       load_node<Q, S, true>(A, src, x0 + (int)threadIdx.x + k * bx, y, L[k]);
@@ -97,16 +97,16 @@ __device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
       update_node<Q, S, PLAIN, true, NT>(A, dst, x0 + (int)threadIdx.x + k * bx,
                                          y, L[k], st);
   } else {
+    // boundary tiles: one node at a time keeps the register count of the
+    // interior path; the loads of a node are still issued together
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int x = x0 + (int)threadIdx.x + k * bx;
-      if (x < A.nx && y < A.ny) load_node<Q, S, false>(A, src, x, y, L[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      const int x = x0 + (int)threadIdx.x + k * bx;
-      if (x < A.nx && y < A.ny)
-        update_node<Q, S, PLAIN, false, NT>(A, dst, x, y, L[k], st);
+      if (x < A.nx && y < A.ny) {
+        NodeLoad<Q, S> L;
+        load_node<Q, S, false>(A, src, x, y, L);
+        update_node<Q, S, PLAIN, false, NT>(A, dst, x, y, L, st);
+      }
     }
   }
   block_stats_to_slot(st, fast, slot);
@@ -114,7 +114,7 @@ __device__ inline void step_tile(const StepArgs &A, const S *__restrict__ src,
 
 // tile of block b: the blocks of XCD k (b mod 8 = k) take the k-th
 // contiguous chunk of the tile order, optionally swept backwards
-__device__ inline int xcd_tile(int b, int per_xcd, int ntiles, int reverse) {
+__device__ __forceinline__ int xcd_tile(int b, int per_xcd, int ntiles, int reverse) {
   const int t = (b & 7) * per_xcd + (b >> 3);
   return reverse ? ntiles - 1 - t : t;
 }
@@ -165,7 +165,7 @@ __global__ void zero_kernel(uint64_t *p, int64_t n) {
 // ---------------------------------------------------------------------
 // fixed-order reductions
 
-__device__ inline double block_sum_256(double v) {
+__device__ __forceinline__ double block_sum_256(double v) {
   __shared__ double s[4];
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void front_integral_kernel(
 }
 
 template <int Q, typename S>
-__device__ inline double temp_at(const S *src, int64_t plane, int64_t k) {
+__device__ __forceinline__ double temp_at(const S *src, int64_t plane, int64_t k) {
   double T = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
