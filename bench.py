@@ -39,6 +39,37 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_SOURCES = ("irebm_node.hpp", "kernels.hpp", "host_util.hpp",
+                  "lbm_stefan.hip")
+
+
+def kernel_source_hash():
+    """sha256 of the sources that define the single-lattice step kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2505_13097_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, variant_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken with the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (rec.get("sources_sha256") != kernel_source_hash() or
+            rec.get("workload") != workload or
+            rec.get("kernel_variant") != variant_name):
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def bytes_per_node(prob):
     s = 8 if prob.storage == "f64" else 4
     return 2 * prob.q * s
@@ -74,14 +105,15 @@ def time_plain(prob, steps, warmup, variant=-1, autotune=True):
             "tuned": tuned}
 
 
-def time_batched(probs, steps, warmup, autotune=True, graph_steps=100):
+def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
+                 variant=-1, bpc=0):
     """The batched form: all instances advanced by one persistent launch
     per step, replayed from a captured hipGraph of graph_steps launches."""
     import torch
     from paper_2505_13097_amd import StefanBatch, variant_names
     b = StefanBatch(probs)
     tuned = None
-    v, bpc = -1, 4
+    v = variant
     if autotune:
         v, bpc, ms = b.autotune(steps=3)
         tuned = {"variant": variant_names(probs[0].q, probs[0].storage)[v],
@@ -191,6 +223,8 @@ def main():
                     help="comma list of extra forms to time: batched, adjoint")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-variant", type=int, default=-1)
+    ap.add_argument("--batch-bpc", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
@@ -260,7 +294,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(prob.name, vname),
             "kernel": "step_kernel",
             "bytes_per_node": bpn,
             "avg_launch_us": round(launch_ms * 1e3, 2),
@@ -277,7 +311,9 @@ def main():
         print(f"[bench] batched form: {args.batch_count} instances, "
               f"{args.batch_steps} steps", file=sys.stderr, flush=True)
         probs = S.batch_table(count=args.batch_count, nsteps=args.batch_steps)
-        forms["batched"] = time_batched(probs, args.batch_steps, 10)
+        forms["batched"] = time_batched(
+            probs, args.batch_steps, 10, autotune=not args.no_autotune,
+            variant=args.batch_variant, bpc=args.batch_bpc)
         print("[bench] batched done", file=sys.stderr, flush=True)
     if "adjoint" in args.forms.split(","):
         import synth as S

@@ -31,7 +31,7 @@ namespace {
 
 // one tile of the table: tiles[t] = (instance, tile index within it); the
 // descriptor is block-uniform and read in place with scalar loads
-template <int Q, typename S, int NPT, bool PLAIN, bool NT>
+template <int Q, typename S, int NPT, bool PLAIN, bool NT, bool LOOP>
 __device__ __forceinline__ void batch_tile(const StepArgs *__restrict__ descs,
                                   const int2 *__restrict__ tiles, int t,
                                   int parity) {
@@ -41,8 +41,8 @@ __device__ __forceinline__ void batch_tile(const StepArgs *__restrict__ descs,
   const StepArgs &A = descs[inst];
   const S *src = (const S *)(parity ? A.dst : A.src);
   S *dst = (S *)(parity ? A.src : A.dst);
-  step_tile<Q, S, NPT, PLAIN, NT>(A, src, dst, tile % A.tiles_x,
-                                  tile / A.tiles_x, A.slots + tile);
+  step_tile<Q, S, NPT, PLAIN, NT, LOOP>(A, src, dst, tile % A.tiles_x,
+                                        tile / A.tiles_x, A.slots + tile);
 }
 
 // one block per tile, the blocks of XCD k taking the k-th contiguous
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(256) void batch_step_kernel(
   const int chunk = (ntiles + 7) >> 3;
   const int b = (int)blockIdx.x;
   if ((b & 7) * chunk + (b >> 3) >= ntiles) return;
-  batch_tile<Q, S, NPT, PLAIN, NT>(descs, tiles,
-                                   xcd_tile(b, chunk, ntiles, reverse), parity);
+  batch_tile<Q, S, NPT, PLAIN, NT, false>(
+      descs, tiles, xcd_tile(b, chunk, ntiles, reverse), parity);
 }
 
 // persistent grid sized to the machine: each block walks its XCD's chunk
@@ -69,8 +69,8 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(
   const int xcd = (int)(blockIdx.x & 7), lane = (int)(blockIdx.x >> 3);
   const int t_end = min(ntiles, (xcd + 1) * chunk);
   for (int t = xcd * chunk + lane; t < t_end; t += per_xcd_blocks)
-    batch_tile<Q, S, NPT, PLAIN, NT>(descs, tiles,
-                                     reverse ? ntiles - 1 - t : t, parity);
+    batch_tile<Q, S, NPT, PLAIN, NT, true>(descs, tiles,
+                                           reverse ? ntiles - 1 - t : t, parity);
 }
 
 }  // namespace

@@ -28,10 +28,15 @@ namespace irebm {
 constexpr int kEnergyChunk = 2048;  // nodes per energy partial
 
 // Statistics of one block (already reduced over the node loop of each
-// thread), combined across the block and added to the tile's slot by
-// thread 0.
-__device__ __forceinline__ void block_stats_to_slot(const NodeStats &st, bool fast,
-                                           StatSlot *sl) {
+// thread), combined across the block and added by thread 0 to the tile's
+// slot, whose previous value `pre` thread 0 loaded when the tile started
+// (so that the read's latency hides under the tile's own loads).  LOOP: the
+// block goes on to another tile, so the shared arrays are fenced again.
+template <bool LOOP>
+__device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
+                                                    bool fast,
+                                                    const StatSlot &pre,
+                                                    StatSlot *sl) {
   __shared__ int s_it[4], s_nc[4];
   __shared__ double s_res[4], s_fin[4], s_fout[4];
   const int lin = (int)(threadIdx.x + threadIdx.y * blockDim.x);
@@ -62,30 +67,36 @@ __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st, bool fa
       bfin += s_fin[w];
       bfout += s_fout[w];
     }
-    sl->max_it = max(sl->max_it, bit);
-    sl->nonconv += bnc;
-    sl->max_res = fmax(sl->max_res, bres);
+    StatSlot out = pre;
+    out.max_it = max(pre.max_it, bit);
+    out.nonconv = pre.nonconv + bnc;
+    out.max_res = fmax(pre.max_res, bres);
     if (!fast) {
-      sl->flux_in += bfin;
-      sl->flux_out += bfout;
+      out.flux_in = pre.flux_in + bfin;
+      out.flux_out = pre.flux_out + bfout;
     }
+    *sl = out;
   }
-  __syncthreads();
+  if (LOOP) __syncthreads();
 }
 
 // One tile (tx, ty) of the lattice described by A, from state src to
 // state dst: on interior tiles all loads of the thread's nodes first
 // (memory-level parallelism), then the updates; then the statistics.
-template <int Q, typename S, int NPT, bool PLAIN, bool NT = false>
-__device__ __forceinline__ void step_tile(const StepArgs &A, const S *__restrict__ src,
-                                 S *__restrict__ dst, int tx, int ty,
-                                 StatSlot *slot) {
+template <int Q, typename S, int NPT, bool PLAIN, bool NT = false,
+          bool LOOP = false>
+__device__ __forceinline__ void step_tile(const StepArgs &A,
+                                          const S *__restrict__ src,
+                                          S *__restrict__ dst, int tx, int ty,
+                                          StatSlot *slot) {
   const int bx = blockDim.x, by = blockDim.y;
   const int TW = bx * NPT;
   const int x0 = tx * TW, y0 = ty * by;
   const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
   const int y = y0 + (int)threadIdx.y;
+  StatSlot pre{};
+  if (threadIdx.x == 0 && threadIdx.y == 0) pre = *slot;
   NodeStats st;
   if (fast) {
     NodeLoad<Q, S> L[NPT];
@@ -109,7 +120,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const S *__restrict
       }
     }
   }
-  block_stats_to_slot(st, fast, slot);
+  block_stats_to_slot<LOOP>(st, fast, pre, slot);
 }
 
 // tile of block b: the blocks of XCD k (b mod 8 = k) take the k-th
