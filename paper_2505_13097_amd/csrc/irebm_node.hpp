@@ -125,6 +125,22 @@ __device__ __forceinline__ double newton(double m0, double th, double pth,
   const double c = m0 + pth * s;
   double lo = c - s, hi = c;
   double dx = hi - lo, dxold = dx;
+  // Solid node far from the melting band (phi(T) = 0 and phi(m0) = 0
+  // exactly, phi' = 0): then c = m0, the first iterate is T - (T - m0),
+  // and when that equals m0 (the difference is exact) the second iterate
+  // and the final step change nothing.  Evaluate those iterations in closed
+  // form: same result (up to the sign of a zero, which only enters phi),
+  // same iteration count and convergence flag.  The guard also checks
+  // that the safeguard's step test would have kept the first step.
+  if (pth == 0.0 && (m0 - A.tm) * A.inv_delta < -20.0) {
+    const double d = th - m0;
+    if (th - d == m0 && (PLAIN || 2.0 * fabs(d) <= fabs(dx))) {
+      const bool one = fabs(d) <= A.tol;
+      conv = one || A.max_it >= 2;
+      iters = (one || A.max_it < 2) ? 1 : 2;
+      return m0;
+    }
+  }
   double cur = th, cand = th;
   int k = 0;
   conv = false;

@@ -278,3 +278,28 @@ def test_full_size_planar_properties():
     cross = g.front("crossing")
     assert cross.max() - cross.min() < 2 * prob.dx
     g.close()
+
+
+@pytest.mark.parametrize("max_it", [1, 2, 3])
+def test_newton_iteration_cap_against_oracle(max_it):
+    """A tight iteration cap: the same nodes stop unconverged on both sides
+    (the counts may differ only where rounding moves an iterate across
+    the tolerance), the largest iteration count agrees, and converged
+    nodes still match the oracle."""
+    for make in (lambda: synth.cavity_2d(n=150, ny=77, storage="f64"),
+                 lambda: _smooth_mushy(synth.planar_2d(n=131, ny=67,
+                                                       storage="f64"))):
+        prob = make().with_(max_it=max_it)
+        g = _gpu_run(prob, 60)
+        o = _oracle_run(prob, 60)
+        gs, os_ = g["stats"], o["stats"]
+        print(f"{prob.name} cap {max_it}: nonconverged {gs['nonconverged']}"
+              f" vs {os_['nonconverged']}, max it {gs['max_newton_it']}"
+              f" vs {os_['max_it']}", flush=True)
+        assert gs["max_newton_it"] == os_["max_it"]
+        assert abs(gs["nonconverged"] - os_["nonconverged"]) <= \
+            1e-3 * prob.nodes * 60
+        if os_["nonconverged"] == 0:
+            assert gs["nonconverged"] == 0
+            err = np.max(np.abs(g["T"] - o["T"]))
+            assert err <= TOL64 * max(1.0, np.max(np.abs(o["T"])))
