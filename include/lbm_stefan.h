@@ -201,9 +201,10 @@ int lbm_stefan_set_state(lbm_stefan_t *h, const void *state,
 int lbm_stefan_state_ptr(lbm_stefan_t *h, void **dev_state);
 
 /* Number of compiled kernel variants for a lattice/storage pair, and the
-   name of one ("<tile_x>x<tile_y>/npt<k>[/nt][/rev]": tile size, nodes
-   per thread, non-temporal stores, tile order reversed every other step);
-   used by autotuners. */
+   name of one ("<tile_x>x<tile_y>/npt<k>[/r<m>][/nt][/rev]": tile size,
+   nodes per thread, m tiles stacked along y per thread block,
+   non-temporal stores, block order reversed every other step); used by
+   autotuners. */
 int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count);
 const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
                                     int32_t variant);
@@ -333,7 +334,8 @@ int lbm_stefan_batch_workspace_bytes(const lbm_stefan_params *params,
  * lbm_stefan_init.  T0: host, nullable array of `count` nullable host
  * arrays [ny_k][nx_k].  workspace: device, 256-byte aligned, >= the size
  * above, owned by the caller.  Default schedule: the library's default
- * variant, one block per tile, no graph.  Blocks until built.
+ * variant, one block per work item (a stack of tiles), no graph.  Blocks
+ * until built.
  */
 int lbm_stefan_batch_init(const lbm_stefan_params *params, int32_t count,
                           const double *const *T0, void *workspace,
@@ -342,7 +344,7 @@ int lbm_stefan_batch_init(const lbm_stefan_params *params, int32_t count,
 
 /*
  * Schedule: kernel variant (-1: default); blocks_per_cu 0 launches one
- * block per tile (in XCD-contiguous chunks of the tile table), 1..32 a
+ * block per work item (in XCD-contiguous chunks of the item table), 1..32 a
  * persistent grid of blocks_per_cu x compute units walking the table; and
  * graph_steps (even, 0..1e5):
  * when > 0, lbm_stefan_batch_step replays a captured hipGraph of that many

@@ -418,8 +418,8 @@ size_t state_bytes(const lbm_stefan_params &p) {
 
 }  // namespace
 
-size_t irebm::adjoint_bytes(const lbm_stefan_params *p, int64_t max_tiles) {
-  (void)max_tiles;
+size_t irebm::adjoint_bytes(const lbm_stefan_params *p, int64_t max_items) {
+  (void)max_items;
   return adj_layout(p).total;
 }
 

@@ -2,13 +2,14 @@
 // parameters advanced by one persistent kernel launch per time step.
 //
 // Every instance gets a descriptor (its StepArgs: sizes, physics,
-// boundaries, buffers, statistics base) and its tiles are listed in one
-// flat table, instance by instance and row by row within an instance.  A
-// persistent grid of (compute units x blocks per CU) blocks walks that
-// table: the table is cut into eight contiguous chunks, one per XCD
-// (block b runs on XCD b mod 8), so neighbouring tiles of an instance are
-// swept by the same XCD and share its L2.  The node update is the one of
-// the single-lattice step (step_tile), so a batch member evolves exactly
+// boundaries, buffers, statistics base) and its work items (stacks of
+// tiles, see step_item) are listed in one flat table, instance by
+// instance and row by row within an instance.  A grid of one block per
+// item, or a persistent grid of (compute units x blocks per CU) blocks,
+// walks that table: the table is cut into eight contiguous chunks, one per
+// XCD (block b runs on XCD b mod 8), so neighbouring tiles of an instance
+// are swept by the same XCD and share its L2.  The node update is the one of
+// the single-lattice step (step_item), so a batch member evolves exactly
 // as the same lattice run alone.  Steps can be captured in a hipGraph;
 // the autotuner picks the tile variant and the grid size.
 #include <hip/hip_runtime.h>
@@ -29,48 +30,47 @@ using namespace irebm;
 
 namespace {
 
-// one tile of the table: tiles[t] = (instance, tile index within it); the
-// descriptor is block-uniform and read in place with scalar loads
+// one work item of the table: items[t] = (instance, item index within
+// it); the descriptor is block-uniform and read in place with scalar loads
 template <int Q, typename S, int NPT, bool PLAIN, bool NT, bool LOOP>
-__device__ __forceinline__ void batch_tile(const StepArgs *__restrict__ descs,
-                                  const int2 *__restrict__ tiles, int t,
-                                  int parity) {
-  const int2 e = tiles[t];
+__device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
+                                           const int2 *__restrict__ items,
+                                           int t, int parity) {
+  const int2 e = items[t];
   const int inst = __builtin_amdgcn_readfirstlane(e.x);
-  const int tile = __builtin_amdgcn_readfirstlane(e.y);
+  const int item = __builtin_amdgcn_readfirstlane(e.y);
   const StepArgs &A = descs[inst];
   const S *src = (const S *)(parity ? A.dst : A.src);
   S *dst = (S *)(parity ? A.src : A.dst);
-  step_tile<Q, S, NPT, PLAIN, NT, LOOP>(A, src, dst, tile % A.tiles_x,
-                                        tile / A.tiles_x, A.slots + tile);
+  step_item<Q, S, NPT, PLAIN, NT, LOOP>(A, src, dst, item, A.slots + item);
 }
 
-// one block per tile, the blocks of XCD k taking the k-th contiguous
+// one block per work item, the blocks of XCD k taking the k-th contiguous
 // chunk of the table
 template <int Q, typename S, int NPT, bool PLAIN, bool NT>
 __global__ __launch_bounds__(256) void batch_step_kernel(
-    const StepArgs *__restrict__ descs, const int2 *__restrict__ tiles,
-    int32_t ntiles, int32_t parity, int32_t reverse) {
-  const int chunk = (ntiles + 7) >> 3;
+    const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
+    int32_t nitems, int32_t parity, int32_t reverse) {
+  const int chunk = (nitems + 7) >> 3;
   const int b = (int)blockIdx.x;
-  if ((b & 7) * chunk + (b >> 3) >= ntiles) return;
-  batch_tile<Q, S, NPT, PLAIN, NT, false>(
-      descs, tiles, xcd_tile(b, chunk, ntiles, reverse), parity);
+  if ((b & 7) * chunk + (b >> 3) >= nitems) return;
+  batch_item<Q, S, NPT, PLAIN, NT, false>(
+      descs, items, xcd_item(b, chunk, nitems, reverse), parity);
 }
 
 // persistent grid sized to the machine: each block walks its XCD's chunk
 // of the table with a stride
 template <int Q, typename S, int NPT, bool PLAIN, bool NT>
 __global__ __launch_bounds__(256) void batch_persistent_kernel(
-    const StepArgs *__restrict__ descs, const int2 *__restrict__ tiles,
-    int32_t ntiles, int32_t parity, int32_t reverse) {
-  const int chunk = (ntiles + 7) >> 3;
+    const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
+    int32_t nitems, int32_t parity, int32_t reverse) {
+  const int chunk = (nitems + 7) >> 3;
   const int per_xcd_blocks = (int)(gridDim.x >> 3);
   const int xcd = (int)(blockIdx.x & 7), lane = (int)(blockIdx.x >> 3);
-  const int t_end = min(ntiles, (xcd + 1) * chunk);
+  const int t_end = min(nitems, (xcd + 1) * chunk);
   for (int t = xcd * chunk + lane; t < t_end; t += per_xcd_blocks)
-    batch_tile<Q, S, NPT, PLAIN, NT, true>(descs, tiles,
-                                           reverse ? ntiles - 1 - t : t, parity);
+    batch_item<Q, S, NPT, PLAIN, NT, true>(descs, items,
+                                           reverse ? nitems - 1 - t : t, parity);
 }
 
 }  // namespace
@@ -83,15 +83,15 @@ struct lbm_stefan_batch {
   hipStream_t stream = nullptr, cap_stream = nullptr;
   char *ws = nullptr;
   StepArgs *descs = nullptr;
-  int2 *tiles = nullptr;
+  int2 *items = nullptr;
   StatSlot *slots = nullptr;
   double *profs = nullptr, *partials = nullptr, *small = nullptr;
   char *state[2] = {nullptr, nullptr};
   size_t state_bytes = 0;
   std::vector<size_t> off;          // instance offset in a state region
   std::vector<size_t> prof_off;     // instance offset in the profiles
-  std::vector<int64_t> first_tile, ntiles_inst;
-  int64_t max_tiles = 0, ntiles = 0;
+  std::vector<int64_t> first_item, nitems_inst;
+  int64_t max_items = 0, nitems = 0;
   int cur = 0;
   int variant = kDefaultVariant2D, blocks_per_cu = 0, graph_steps = 0;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -102,9 +102,9 @@ struct lbm_stefan_batch {
 namespace {
 
 struct BLayout {
-  size_t descs, tiles, slots, profs, partials, small, stateA, stateB, total;
+  size_t descs, items, slots, profs, partials, small, stateA, stateB, total;
   size_t state_bytes;
-  int64_t max_tiles, max_parts, small_len;
+  int64_t max_items, max_parts, small_len;
   std::vector<size_t> off, prof_off;
 };
 
@@ -140,11 +140,11 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   const size_t s = ps[0].storage == LBM_STORE_F64 ? 8 : 4;
   int nv;
   const Variant *v = variants(ps[0].q, &nv);
-  L.max_tiles = 0;
+  L.max_items = 0;
   for (int i = 0; i < nv; ++i) {
     int64_t t = 0;
-    for (int k = 0; k < count; ++k) t += tiles_for(v[i], ps[k].nx, ps[k].ny);
-    L.max_tiles = std::max(L.max_tiles, t);
+    for (int k = 0; k < count; ++k) t += items_for(v[i], ps[k].nx, ps[k].ny);
+    L.max_items = std::max(L.max_items, t);
   }
   L.state_bytes = 0;
   L.off.resize(count);
@@ -165,10 +165,10 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   size_t o = 0;
   L.descs = o;
   o += align256(count * sizeof(StepArgs));
-  L.tiles = o;
-  o += align256(L.max_tiles * sizeof(int2));
+  L.items = o;
+  o += align256(L.max_items * sizeof(int2));
   L.slots = o;
-  o += align256(L.max_tiles * sizeof(StatSlot));
+  o += align256(L.max_items * sizeof(StatSlot));
   L.profs = o;
   o += align256(prof_total * 8);
   L.partials = o;
@@ -191,16 +191,16 @@ void drop_graphs(lbm_stefan_batch_t *b) {
     }
 }
 
-// descriptors and tile table for the current variant; uploads both and
-// zeroes the statistics (the tile -> slot map changes with the tiles)
+// descriptors and item table for the current variant; uploads both and
+// zeroes the statistics (the item -> slot map changes with the items)
 int build_schedule(lbm_stefan_batch_t *b) {
   int nv;
   const Variant &v = variants(b->q, &nv)[b->variant];
   std::vector<StepArgs> d(b->count);
   std::vector<int2> t;
-  t.reserve(b->max_tiles);
-  b->first_tile.assign(b->count, 0);
-  b->ntiles_inst.assign(b->count, 0);
+  t.reserve(b->max_items);
+  b->first_item.assign(b->count, 0);
+  b->nitems_inst.assign(b->count, 0);
   for (int k = 0; k < b->count; ++k) {
     const lbm_stefan_params &p = b->ps[k];
     double *prof[4];
@@ -211,21 +211,19 @@ int build_schedule(lbm_stefan_batch_t *b) {
     fill_args(p, prof, &d[k]);
     d[k].src = b->state[0] + b->off[k];
     d[k].dst = b->state[1] + b->off[k];
-    const int64_t nt = tiles_for(v, p.nx, p.ny);
-    d[k].tiles_x = (int32_t)tiles_x_for(v, p.nx);
-    d[k].ntiles = (int32_t)nt;
-    d[k].per_xcd = 0;
+    set_tiling(&d[k], v);
+    const int64_t nt = d[k].nitems;
     d[k].slots = b->slots + t.size();
-    b->first_tile[k] = (int64_t)t.size();
-    b->ntiles_inst[k] = nt;
+    b->first_item[k] = (int64_t)t.size();
+    b->nitems_inst[k] = nt;
     for (int64_t i = 0; i < nt; ++i) t.push_back(make_int2(k, (int)i));
   }
-  b->ntiles = (int64_t)t.size();
+  b->nitems = (int64_t)t.size();
   BCHK(b, hipMemcpyAsync(b->descs, d.data(), d.size() * sizeof(StepArgs),
                          hipMemcpyHostToDevice, b->stream));
-  BCHK(b, hipMemcpyAsync(b->tiles, t.data(), t.size() * sizeof(int2),
+  BCHK(b, hipMemcpyAsync(b->items, t.data(), t.size() * sizeof(int2),
                          hipMemcpyHostToDevice, b->stream));
-  BCHK(b, zero_async(b->slots, b->max_tiles * sizeof(StatSlot), b->stream));
+  BCHK(b, zero_async(b->slots, b->max_items * sizeof(StatSlot), b->stream));
   BCHK(b, hipStreamSynchronize(b->stream));
   drop_graphs(b);
   return LBM_STEFAN_OK;
@@ -236,22 +234,22 @@ hipError_t launch_batch_t(const lbm_stefan_batch_t *b, hipStream_t stream,
                           int parity) {
   int nv;
   const Variant &v = variants(Q, &nv)[b->variant];
-  const int64_t chunk = (b->ntiles + 7) / 8;
-  int64_t g8 = chunk;  // one block per tile
+  const int64_t chunk = (b->nitems + 7) / 8;
+  int64_t g8 = chunk;  // one block per item
   if (b->blocks_per_cu > 0)
     g8 = std::min<int64_t>(((int64_t)b->cus * b->blocks_per_cu + 7) / 8, chunk);
   dim3 grid((unsigned)(8 * std::max<int64_t>(g8, 1))), block(v.bx, v.by);
-  const int32_t nt = (int32_t)b->ntiles;
+  const int32_t nt = (int32_t)b->nitems;
   const int32_t rev = v.rev && parity;
   const int32_t pers = b->blocks_per_cu > 0;
 #define BLAUNCH(NPT, PL, NTS)                                              \
   do {                                                                     \
     if (pers)                                                              \
       batch_persistent_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>( \
-          b->descs, b->tiles, nt, parity, rev);                            \
+          b->descs, b->items, nt, parity, rev);                            \
     else                                                                   \
       batch_step_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>(   \
-          b->descs, b->tiles, nt, parity, rev);                            \
+          b->descs, b->items, nt, parity, rev);                            \
   } while (0)
 #define BLAUNCH_NPT(PL, NTS)                  \
   do {                                        \
@@ -361,7 +359,7 @@ int lbm_stefan_batch_init(const lbm_stefan_params *ps, int32_t count,
   char *ws = (char *)workspace;
   b->ws = ws;
   b->descs = (StepArgs *)(ws + L.descs);
-  b->tiles = (int2 *)(ws + L.tiles);
+  b->items = (int2 *)(ws + L.items);
   b->slots = (StatSlot *)(ws + L.slots);
   b->profs = (double *)(ws + L.profs);
   b->partials = (double *)(ws + L.partials);
@@ -371,7 +369,7 @@ int lbm_stefan_batch_init(const lbm_stefan_params *ps, int32_t count,
   b->state_bytes = L.state_bytes;
   b->off = L.off;
   b->prof_off = L.prof_off;
-  b->max_tiles = L.max_tiles;
+  b->max_items = L.max_items;
   for (int k = 0; k < count; ++k) {
     lbm_stefan_params &p = b->ps[k];
     if (p.dx == 0.0) p.dx = 1.0 / (double)(p.nx - 1);
@@ -467,7 +465,7 @@ int lbm_stefan_batch_step(lbm_stefan_batch_t *b, int64_t nsteps) {
 int lbm_stefan_batch_reset_stats(lbm_stefan_batch_t *b) {
   if (!b) return bfail(nullptr, LBM_STEFAN_EINVAL, "batch is NULL");
   DeviceGuard g(b->device);
-  BCHK(b, zero_async(b->slots, b->max_tiles * sizeof(StatSlot), b->stream));
+  BCHK(b, zero_async(b->slots, b->max_items * sizeof(StatSlot), b->stream));
   return LBM_STEFAN_OK;
 }
 
@@ -477,8 +475,8 @@ int lbm_stefan_batch_stats(lbm_stefan_batch_t *b, lbm_stefan_stats *out) {
   std::vector<double> hs((size_t)b->count * 16);
   for (int k = 0; k < b->count; ++k) {
     const lbm_stefan_params &p = b->ps[k];
-    stats_kernel<<<1, 256, 0, b->stream>>>(b->slots + b->first_tile[k],
-                                           b->ntiles_inst[k], b->small + 16 * k);
+    stats_kernel<<<1, 256, 0, b->stream>>>(b->slots + b->first_item[k],
+                                           b->nitems_inst[k], b->small + 16 * k);
     BCHK(b, hipGetLastError());
     BCHK(b, energy_async(b->q, b->storage, b->state[b->cur] + b->off[k],
                          p.nx * p.ny, p.t_m, p.delta, p.ste, b->partials,
@@ -637,7 +635,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
     rc = build_schedule(b);
     if (rc) return rc;
   } else {
-    BCHK(b, zero_async(b->slots, b->max_tiles * sizeof(StatSlot), b->stream));
+    BCHK(b, zero_async(b->slots, b->max_items * sizeof(StatSlot), b->stream));
   }
   drop_graphs(b);
   BCHK(b, hipStreamSynchronize(b->stream));

@@ -14,22 +14,26 @@
 namespace irebm {
 
 // A kernel variant: block of bx x by threads, each thread updating npt
-// nodes bx apart along x; the tile is (bx * npt) x by nodes.  nt: stores
-// bypass the caches (non-temporal); rev: the tile order is reversed on
-// every other step, so that the rows written last (still in the
-// memory-side cache) are read first.
+// nodes bx apart along x; the tile is (bx * npt) x by nodes, and one block
+// sweeps `rows` tiles stacked along y.  nt: stores bypass the caches
+// (non-temporal); rev: the item order is reversed on every other step, so
+// that the rows written last (still in the memory-side cache) are read
+// first.
 struct Variant {
-  int bx, by, npt, nt, rev;
+  int bx, by, npt, nt, rev, rows;
 };
 
 inline const Variant *variants(int q, int *n) {
-  static const Variant v1[] = {{256, 1, 1, 0, 0}, {128, 1, 1, 0, 0},
-                               {64, 1, 1, 0, 0}, {256, 1, 2, 0, 0}};
+  static const Variant v1[] = {{256, 1, 1, 0, 0, 1}, {128, 1, 1, 0, 0, 1},
+                               {64, 1, 1, 0, 0, 1},  {256, 1, 2, 0, 0, 1}};
   static const Variant v2[] = {
-      {64, 4, 1, 0, 0},  {256, 1, 1, 0, 0}, {128, 2, 1, 0, 0},
-      {64, 4, 2, 0, 0},  {128, 2, 2, 0, 0}, {256, 1, 2, 0, 0},
-      {64, 2, 2, 0, 0},  {64, 4, 4, 0, 0},  {64, 4, 2, 1, 0},
-      {64, 4, 2, 0, 1},  {64, 4, 2, 1, 1},  {128, 2, 2, 0, 1}};
+      {64, 4, 1, 0, 0, 1}, {256, 1, 1, 0, 0, 1}, {128, 2, 1, 0, 0, 1},
+      {64, 4, 2, 0, 0, 1}, {128, 2, 2, 0, 0, 1}, {256, 1, 2, 0, 0, 1},
+      {64, 2, 2, 0, 0, 1}, {64, 4, 4, 0, 0, 1},  {64, 4, 2, 1, 0, 1},
+      {64, 4, 2, 0, 1, 1}, {64, 4, 2, 1, 1, 1},  {128, 2, 2, 0, 1, 1},
+      {64, 4, 2, 1, 0, 2}, {64, 4, 2, 1, 0, 4},  {64, 4, 2, 1, 0, 8},
+      {64, 4, 2, 0, 0, 4}, {64, 4, 1, 1, 0, 4},  {64, 4, 2, 1, 1, 4},
+      {128, 2, 2, 1, 0, 4}, {64, 4, 2, 1, 0, 16}};
   if (q == 3) {
     *n = (int)(sizeof(v1) / sizeof(Variant));
     return v1;
@@ -44,8 +48,20 @@ inline int64_t tiles_x_for(const Variant &v, int64_t nx) {
   const int64_t tw = (int64_t)v.bx * v.npt;
   return (nx + tw - 1) / tw;
 }
-inline int64_t tiles_for(const Variant &v, int64_t nx, int64_t ny) {
-  return tiles_x_for(v, nx) * ((ny + v.by - 1) / v.by);
+inline int64_t tiles_y_for(const Variant &v, int64_t ny) {
+  return (ny + v.by - 1) / v.by;
+}
+// work items (one block each) of an nx x ny lattice
+inline int64_t items_for(const Variant &v, int64_t nx, int64_t ny) {
+  return tiles_x_for(v, nx) * ((tiles_y_for(v, ny) + v.rows - 1) / v.rows);
+}
+// tile grid and work items of A for variant v
+inline void set_tiling(StepArgs *A, const Variant &v) {
+  A->tiles_x = (int32_t)tiles_x_for(v, A->nx);
+  A->tiles_y = (int32_t)tiles_y_for(v, A->ny);
+  A->group = v.rows;
+  A->nitems = (int32_t)items_for(v, A->nx, A->ny);
+  A->per_xcd = (A->nitems + 7) / 8;
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }

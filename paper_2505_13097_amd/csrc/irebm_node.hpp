@@ -67,7 +67,9 @@ struct StepArgs {
   void *dst;            // next state planes
   int32_t nx, ny;
   int64_t plane;        // nx * ny
-  int32_t tiles_x, ntiles, per_xcd;
+  int32_t tiles_x, tiles_y;  // tile grid
+  int32_t group;             // tile rows per work item (one block each)
+  int32_t nitems, per_xcd;   // work items; items per XCD chunk
   int32_t reverse;      // sweep the tiles in reverse order
   int32_t periodic_x, periodic_y;
   double a;             // 1 - 1/tau

@@ -2,19 +2,19 @@
 // Included by each translation unit of the library; the kernels sit in an
 // anonymous namespace so every unit registers its own copies.
 //
-//   step_kernel      one time step, one launch; each block owns one tile of
-//                    the lattice (tile_x = bx * npt columns, tile_y = by
-//                    rows).  Blocks are remapped so that each of the eight
-//                    XCDs sweeps one contiguous band of tile rows: the rows
-//                    a tile pulls from its neighbours then sit in that
-//                    XCD's L2.  Interior tiles take a path with no bounds
-//                    checks.  Per-tile Newton and flux statistics are
+//   step_kernel      one time step, one launch; each block owns a work
+//                    item of `group` tiles stacked along y (a tile is
+//                    bx * npt columns by by rows).  Blocks are remapped so
+//                    that each of the eight XCDs sweeps one contiguous
+//                    band of tile rows: the rows a tile pulls from its
+//                    neighbours then sit in that XCD's L2.  Interior tiles take a path with no bounds
+//                    checks.  Per-item Newton and flux statistics are
 //                    accumulated by the owning block (no atomics).
 //   init_kernel      equilibrium state from a temperature field.
 //   temp_kernel      T = sum_i Omega_i.
 //   energy_*         E = sum [T + phi(T)/Ste], two fixed-order passes.
 //   front_*          per-row front position.
-//   stats_kernel     fixed-order reduction of per-tile slots.
+//   stats_kernel     fixed-order reduction of per-item slots.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,10 +28,9 @@ namespace irebm {
 constexpr int kEnergyChunk = 2048;  // nodes per energy partial
 
 // Statistics of one block (already reduced over the node loop of each
-// thread), combined across the block and added by thread 0 to the tile's
-// slot, whose previous value `pre` thread 0 loaded when the tile started
-// (so that the read's latency hides under the tile's own loads).  LOOP: the
-// block goes on to another tile, so the shared arrays are fenced again.
+// thread), combined across the block and added by thread 0 to the item's
+// slot, whose previous value `pre` thread 0 loaded.  LOOP: the block goes
+// on to another item, so the shared arrays are fenced again.
 template <bool LOOP>
 __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
                                                     bool fast,
@@ -82,22 +81,19 @@ __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
 
 // One tile (tx, ty) of the lattice described by A, from state src to
 // state dst: on interior tiles all loads of the thread's nodes first
-// (memory-level parallelism), then the updates; then the statistics.
-template <int Q, typename S, int NPT, bool PLAIN, bool NT = false,
-          bool LOOP = false>
-__device__ __forceinline__ void step_tile(const StepArgs &A,
+// (memory-level parallelism), then the updates.  Statistics go into st;
+// returns whether the tile took the interior path.
+template <int Q, typename S, int NPT, bool PLAIN, bool NT>
+__device__ __forceinline__ bool step_tile(const StepArgs &A,
                                           const S *__restrict__ src,
                                           S *__restrict__ dst, int tx, int ty,
-                                          StatSlot *slot) {
+                                          NodeStats &st) {
   const int bx = blockDim.x, by = blockDim.y;
   const int TW = bx * NPT;
   const int x0 = tx * TW, y0 = ty * by;
   const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
   const int y = y0 + (int)threadIdx.y;
-  StatSlot pre{};
-  if (threadIdx.x == 0 && threadIdx.y == 0) pre = *slot;
-  NodeStats st;
   if (fast) {
     NodeLoad<Q, S> L[NPT];
 #pragma unroll
@@ -120,27 +116,60 @@ __device__ __forceinline__ void step_tile(const StepArgs &A,
       }
     }
   }
+  return fast;
+}
+
+// One work item: tile rows ty0 .. ty0 + group - 1 of tile column tx
+// (fewer at the top of the lattice), swept upward by one block, so the
+// rows a tile pulls from below were just read by the same block, and the
+// block's start-up (descriptor and slot reads) and statistics reduction
+// are paid once per item.  One statistics slot per item.
+template <int Q, typename S, int NPT, bool PLAIN, bool NT = false,
+          bool LOOP = false>
+__device__ __forceinline__ void step_item(const StepArgs &A,
+                                          const S *__restrict__ src,
+                                          S *__restrict__ dst, int item,
+                                          StatSlot *slot) {
+  const int tx = item % A.tiles_x;
+  const int ty0 = (item / A.tiles_x) * A.group;
+  const int rows = min(A.group, A.tiles_y - ty0);
+  NodeStats st;
+  bool fast = true;
+  for (int r = 0; r < rows; ++r) {
+    // Re-read the (uniform) arguments in every pass: an index the compiler
+    // cannot see through keeps it from hoisting all of them out of the
+    // loop, which would hold ~80 more scalar registers live across it and
+    // spill them into vector registers (lower occupancy).
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    fast &= step_tile<Q, S, NPT, PLAIN, NT>((&A)[z], src, dst, tx, ty0 + r,
+                                           st);
+  }
+  // read after the loop: a prefetched slot would stay live across it
+  StatSlot pre{};
+  if (threadIdx.x == 0 && threadIdx.y == 0) pre = *slot;
   block_stats_to_slot<LOOP>(st, fast, pre, slot);
 }
 
-// tile of block b: the blocks of XCD k (b mod 8 = k) take the k-th
-// contiguous chunk of the tile order, optionally swept backwards
-__device__ __forceinline__ int xcd_tile(int b, int per_xcd, int ntiles, int reverse) {
+// work item of block b: the blocks of XCD k (b mod 8 = k) take the k-th
+// contiguous chunk of the item order, optionally swept backwards
+__device__ __forceinline__ int xcd_item(int b, int per_xcd, int nitems,
+                                        int reverse) {
   const int t = (b & 7) * per_xcd + (b >> 3);
-  return reverse ? ntiles - 1 - t : t;
+  return reverse ? nitems - 1 - t : t;
 }
 
 namespace {
 
 
-// one time step of one lattice, one block per tile (XCD-aware order)
+// one time step of one lattice, one block per work item (XCD-aware order)
 template <int Q, typename S, int NPT, bool PLAIN, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int b = blockIdx.x;
-  if ((b & 7) * A.per_xcd + (b >> 3) >= A.ntiles) return;
-  const int t = xcd_tile(b, A.per_xcd, A.ntiles, A.reverse);
-  step_tile<Q, S, NPT, PLAIN, NT>(A, (const S *)A.src, (S *)A.dst,
-                                  t % A.tiles_x, t / A.tiles_x, A.slots + t);
+  if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
+  const int t = xcd_item(b, A.per_xcd, A.nitems, A.reverse);
+  step_item<Q, S, NPT, PLAIN, NT>(A, (const S *)A.src, (S *)A.dst, t,
+                                  A.slots + t);
 }
 
 // ---------------------------------------------------------------------

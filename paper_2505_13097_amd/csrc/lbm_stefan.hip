@@ -82,8 +82,8 @@ irebm::Layout irebm::layout_for(const lbm_stefan_params *p) {
   int nv;
   const Variant *v = variants(p->q, &nv);
   int64_t mt = 0;
-  for (int i = 0; i < nv; ++i) mt = std::max(mt, tiles_for(v[i], p->nx, p->ny));
-  L.max_tiles = mt;
+  for (int i = 0; i < nv; ++i) mt = std::max(mt, items_for(v[i], p->nx, p->ny));
+  L.max_items = mt;
   L.n_partials = (n + kEnergyChunk - 1) / kEnergyChunk;
   size_t off = 0;
   L.off_buf[0] = off;
@@ -155,14 +155,10 @@ namespace {
 template <int Q, typename S>
 hipError_t launch_step_t(const lbm_stefan_t *h, const StepArgs &A,
                          const Variant &v, bool plain) {
-  const int64_t ntiles = tiles_for(v, h->p.nx, h->p.ny);
-  const int per_xcd = (int)((ntiles + 7) / 8);
   StepArgs B = A;
-  B.tiles_x = (int32_t)tiles_x_for(v, h->p.nx);
-  B.ntiles = (int32_t)ntiles;
-  B.per_xcd = per_xcd;
+  set_tiling(&B, v);
   B.reverse = v.rev && (h->steps & 1);
-  dim3 grid(8 * per_xcd), block(v.bx, v.by);
+  dim3 grid(8 * B.per_xcd), block(v.bx, v.by);
 #define LAUNCH(NPT, PL, NT) \
   step_kernel<Q, S, NPT, PL, NT><<<grid, block, 0, h->stream>>>(B)
 #define LAUNCH_NPT(PL, NT)                 \
@@ -220,11 +216,11 @@ hipError_t handle_energy_async(const lbm_stefan_t *h, const void *src) {
 }  // namespace
 
 hipError_t irebm::zero_stats_async(lbm_stefan_t *h) {
-  return zero_async(h->slots, h->max_tiles * sizeof(StatSlot), h->stream);
+  return zero_async(h->slots, h->max_items * sizeof(StatSlot), h->stream);
 }
 
 int irebm::read_stats(lbm_stefan_t *h, lbm_stefan_stats *st) {
-  stats_kernel<<<1, 256, 0, h->stream>>>(h->slots, h->max_tiles, h->small);
+  stats_kernel<<<1, 256, 0, h->stream>>>(h->slots, h->max_items, h->small);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, handle_energy_async(h, h->buf[h->cur]));
   double hs[kSmallCount];
@@ -297,7 +293,7 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   h->buf[1] = ws + L.off_buf[1];
   h->cur = 0;
   h->slots = (StatSlot *)(ws + L.off_slots);
-  h->max_tiles = L.max_tiles;
+  h->max_items = L.max_items;
   h->partials = (double *)(ws + L.off_partials);
   h->small = (double *)(ws + L.off_small);
   h->adj = ws + L.off_adj;
@@ -475,9 +471,11 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
     return "";
   const Variant *v = variants(q, &n);
   if (variant < 0 || variant >= n) return "";
-  std::snprintf(buf, sizeof(buf), "%dx%d/npt%d%s%s",
-                v[variant].bx * v[variant].npt, v[variant].by, v[variant].npt,
-                v[variant].nt ? "/nt" : "", v[variant].rev ? "/rev" : "");
+  const Variant &w = v[variant];
+  char rows[16] = "";
+  if (w.rows > 1) std::snprintf(rows, sizeof(rows), "/r%d", w.rows);
+  std::snprintf(buf, sizeof(buf), "%dx%d/npt%d%s%s%s", w.bx * w.npt, w.by,
+                w.npt, rows, w.nt ? "/nt" : "", w.rev ? "/rev" : "");
   return buf;
 }
 

@@ -18,7 +18,7 @@ struct Layout {
   size_t off_prof[4] = {0, 0, 0, 0};
   size_t off_slots = 0, off_partials = 0, off_small = 0, off_adj = 0;
   size_t total = 0;
-  int64_t max_tiles = 0, n_partials = 0;
+  int64_t max_items = 0, n_partials = 0;
   bool adjoint = false;
 };
 
@@ -40,7 +40,7 @@ struct lbm_stefan {
   double *prof[4] = {nullptr, nullptr, nullptr, nullptr};
   bool has_prof[4] = {false, false, false, false};
   irebm::StatSlot *slots = nullptr;
-  int64_t max_tiles = 0;
+  int64_t max_items = 0;
   double *partials = nullptr;
   double *small = nullptr;
   char *adj = nullptr;
@@ -55,7 +55,7 @@ namespace irebm {
 
 std::string validate_params(const lbm_stefan_params *p);
 Layout layout_for(const lbm_stefan_params *p);
-size_t adjoint_bytes(const lbm_stefan_params *p, int64_t max_tiles);
+size_t adjoint_bytes(const lbm_stefan_params *p, int64_t max_items);
 int fail(lbm_stefan_t *h, int code, const std::string &msg);
 void set_global_error(const std::string &msg);
 // StepArgs of a lattice from its params (prof: device wall profiles or

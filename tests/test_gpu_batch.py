@@ -110,7 +110,7 @@ def test_graph_replays_equal_eager_steps(graph_steps):
     eager.close()
 
 
-@pytest.mark.parametrize("variant,bpc", [(3, 2), (9, 0), (8, 4)])
+@pytest.mark.parametrize("variant,bpc", [(3, 2), (9, 0), (8, 4), (13, 0), (17, 2)])
 def test_schedules_bitwise_identical(variant, bpc):
     """Persistent or one-block-per-tile, reversed sweeps, non-temporal
     stores: the per-node arithmetic is the same."""
