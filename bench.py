@@ -54,20 +54,23 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+
+
 def measured_traffic(workload, variant_name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    if it was taken with the current kernel sources, else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    """HBM bytes per launch of the step kernel in this variant, from the
+    committed rocprofv3 counter summary, if it was taken with the current
+    kernel sources, else None."""
     try:
-        with open(path) as f:
+        with open(TRAFFIC_JSON) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     if (rec.get("sources_sha256") != kernel_source_hash() or
-            rec.get("workload") != workload or
-            rec.get("kernel_variant") != variant_name):
+            rec.get("workload") != workload):
         return None
-    return rec.get("bytes_per_launch")
+    v = rec.get("variants", {}).get(variant_name)
+    return None if v is None else v.get("bytes_per_launch")
 
 
 def bytes_per_node(prob):
@@ -194,6 +197,177 @@ def time_adjoint(prob, interval):
     }
 
 
+SWEEP_LAUNCHES = 3
+
+
+def traffic_sweep(prob):
+    """For counter runs: every kernel variant of the workload's lattice for
+    SWEEP_LAUNCHES launches each, in table order (the summary maps the
+    step-kernel dispatches to variants by that order)."""
+    import torch
+    from paper_2505_13097_amd import Stefan, variant_names
+    g = Stefan(prob)
+    names = variant_names(prob.q, prob.storage)
+    for v in range(len(names)):
+        g.set_variant(v)
+        g.step(SWEEP_LAUNCHES)
+    torch.cuda.synchronize()
+    g.close()
+    return names
+
+
+def summarize_profiles(run, args):
+    """Write the profiles/ summaries from the rocprofv3 databases of a
+    GPU run: run/prof_all (kernel trace of the bench with a fixed plain
+    variant and batch schedule), run/pmc_fetch and run/pmc_write (one
+    counter each, bench --traffic-sweep)."""
+    import collections
+    import sqlite3
+    import synth
+    from paper_2505_13097_amd import variant_names
+
+    def short(n):
+        n = n.replace("(anonymous namespace)::", "")
+        return n.split("(")[0].replace("void ", "")
+
+    def db(sub):
+        d = os.path.join(run, sub)
+        f = [x for x in os.listdir(d) if x.endswith("_results.db")]
+        return sqlite3.connect(os.path.join(d, f[0]))
+
+    prob = workload(args.workload)
+    names = variant_names(prob.q, prob.storage)
+    bnames = variant_names(5, "f32")
+    V, BV, BB = args.variant, args.batch_variant, args.batch_bpc
+    vname, bvname = names[V], bnames[BV]
+    step_prefix = f"irebm::step_kernel<{prob.q}, float"
+
+    c = db("prof_all")
+    trace = [(short(r[0]), r[1], r[2], r[3], r[4]) for r in c.execute(
+        "select name, total_calls, total_duration, average, percentage "
+        "from top_kernels")]
+    by = collections.defaultdict(list)
+    for name, d in c.execute("select name, duration from kernels "
+                             "order by dispatch_id"):
+        by[short(name)].append(d / 1000.0)          # ns -> us
+    step_us = by[[k for k in by if k.startswith(step_prefix)][0]]
+    # the timed launches are the last args.steps of the step kernel
+    step_avg = sum(step_us[-args.steps:]) / args.steps
+    bat = [k for k in by if k.startswith("batch_step_kernel<5, float") or
+           k.startswith("batch_persistent_kernel<5, float")][0]
+    bat_avg = sum(by[bat][-args.batch_steps:]) / args.batch_steps
+
+    def counters(sub, cn):
+        rows = db(sub).execute(
+            "select kernel_name, value from counters_collection where "
+            "counter_name=? order by dispatch_id", (cn,)).fetchall()
+        return [(short(k), v) for k, v in rows]
+    F = counters("pmc_fetch", "FETCH_SIZE")
+    W = counters("pmc_write", "WRITE_SIZE")
+    gib_kib = 1024.0 * 1024.0
+    copy_f = max(v for k, v in F if "copyBuffer" in k)
+    copy_w = max(v for k, v in W if "copyBuffer" in k)
+    fs, ws = gib_kib / copy_f, gib_kib / copy_w
+    sf = [v for k, v in F if k.startswith(step_prefix)]
+    sw = [v for k, v in W if k.startswith(step_prefix)]
+    n = SWEEP_LAUNCHES
+    if len(sf) != n * len(names) or len(sw) != n * len(names):
+        raise SystemExit(f"expected {n * len(names)} step-kernel dispatches, "
+                         f"found {len(sf)} / {len(sw)}")
+    alg = prob.nodes * bytes_per_node(prob)
+    per_var = {}
+    for i, nm in enumerate(names):
+        fk = sum(sf[i * n:(i + 1) * n]) / n
+        wk = sum(sw[i * n:(i + 1) * n]) / n
+        b = fk * 1024 * fs + wk * 1024 * ws
+        per_var[nm] = {"fetch_kib_per_dispatch": round(fk, 1),
+                       "write_kib_per_dispatch": round(wk, 1),
+                       "bytes_per_launch": round(b),
+                       "ratio_to_algorithmic": round(b / alg, 4)}
+    bf = [v for k, v in F if k == bat][-1]
+    bw = [v for k, v in W if k == bat][-1]
+    bprobs = synth.batch_table(count=args.batch_count, nsteps=args.batch_steps)
+    bnodes = sum(p.nodes for p in bprobs)
+    balg = bnodes * 40
+    bfb, bwb = bf * 1024 * fs, bw * 1024 * ws
+    src = kernel_source_hash()
+
+    trace_cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof_all -o all"
+                 f" -- python bench.py --steps {args.steps} --warmup 5 --variant {V}"
+                 f" --no-autotune --no-cpu-baseline --batch-steps {args.batch_steps}"
+                 f" --batch-variant {BV} --batch-bpc {BB}")
+    pmc_cmd = ("rocprofv3 --pmc {C} -d gpurun_out/{D} -o {O} -- python bench.py"
+               f" --traffic-sweep --batch-steps 4 --batch-variant {BV}"
+               f" --batch-bpc {BB}")
+    out = os.path.join(ROOT, "profiles")
+    cav = step_avg
+    lines = [f"# step_kernel — {prob.nx} x {prob.ny} D2Q{prob.q} {args.workload}, "
+             f"FP32 populations (variant {vname})", "",
+             "Kernel trace (rocprofv3 on MI355X; run from /tmp with TMPDIR=/tmp,",
+             "paths absolute; summary written by bench.py --summarize-profiles):",
+             "", "    " + trace_cmd, "",
+             "| kernel | calls | total us | average us | % |",
+             "|---|---|---|---|---|"]
+    for r in trace[:16]:
+        lines.append(f"| {r[0]} | {r[1]} | {r[2]:.0f} | {r[3]:.1f} | {r[4]:.2f} |")
+    lines += ["", f"The {args.steps} timed launches of the step kernel average "
+              f"{cav:.1f} us (bench.py measures the same launches with HIP events);",
+              f"algorithmic bytes per launch {alg / 1e9:.4f} GB ({prob.nodes:,} nodes"
+              f" x {bytes_per_node(prob)} B) -> {alg / (cav * 1e-6) / 1e9:.0f} GB/s.",
+              "", "HBM traffic per launch of every variant (two counter runs, one "
+              "counter each):", "", "    " + pmc_cmd.format(
+                  C="FETCH_SIZE", D="pmc_fetch", O="fetch"),
+              "    " + pmc_cmd.format(C="WRITE_SIZE", D="pmc_write", O="write"), "",
+              f"Counter scale from a 1 GiB hipMemcpy D2D in the same runs: "
+              f"FETCH_SIZE reads {copy_f:.0f} KiB (x{fs:.4f}), WRITE_SIZE "
+              f"{copy_w:.0f} KiB (x{ws:.4f}).", "",
+              "| variant | FETCH KiB | WRITE KiB | bytes/launch | / algorithmic |",
+              "|---|---|---|---|---|"]
+    for nm, r in per_var.items():
+        lines.append(f"| {nm} | {r['fetch_kib_per_dispatch']:.0f} | "
+                     f"{r['write_kib_per_dispatch']:.0f} | "
+                     f"{r['bytes_per_launch'] / 1e9:.4f} GB | "
+                     f"{r['ratio_to_algorithmic']:.4f} |")
+    t = per_var[vname]["bytes_per_launch"]
+    lines += ["", f"Timed variant {vname}: {t / 1e9:.4f} GB per launch, "
+              f"measured HBM rate {t / (cav * 1e-6) / 1e9:.0f} GB/s.",
+              f"Kernel sources sha256 {src}.", ""]
+    fn = f"step_kernel_{args.workload}{prob.nx}_d2q{prob.q}_f32.md"
+    with open(os.path.join(out, fn), "w") as f:
+        f.write("\n".join(lines))
+    with open(os.path.join(out, "batch_step_kernel_batch512_d2q5_f32.md"), "w") as f:
+        f.write("\n".join([
+            f"# {bat.split('<')[0]} — {args.batch_count} D2Q5 instances "
+            f"(64^2 ... 1024^2), FP32 (variant {bvname}, blocks per CU {BB})", "",
+            f"Same kernel trace as {fn} (the bench's batched form:",
+            f"{args.batch_steps} steps replayed from hipGraphs of 100 launches).", "",
+            f"Average {bat_avg:.1f} us per launch over the timed launches; "
+            f"{bnodes:,} nodes x 40 B = {balg / 1e9:.3f} GB",
+            f"algorithmic per launch -> {balg / (bat_avg * 1e-6) / 1e9:.0f} GB/s.", "",
+            "| counter | KiB/dispatch | scale | bytes |", "|---|---|---|---|",
+            f"| FETCH_SIZE | {bf:.0f} | {fs:.4f} | {bfb / 1e9:.4f} GB |",
+            f"| WRITE_SIZE | {bw:.0f} | {ws:.4f} | {bwb / 1e9:.4f} GB |", "",
+            f"Total {(bfb + bwb) / 1e9:.4f} GB per launch "
+            f"({(bfb + bwb) / balg:.4f}x the algorithmic bytes).", ""]))
+    adj = [r for r in trace if "adj_" in r[0] or "front_vjp" in r[0] or
+           "init_term" in r[0]]
+    with open(os.path.join(out, "adjoint_kernels_adjoint512_d2q5_f32.md"), "w") as f:
+        f.write("\n".join(
+            ["# Reverse-mode kernels — 512 x 512 D2Q5, FP32 states, FP64 adjoint "
+             "arrays, 4096 steps, checkpoints every 64", "",
+             f"Same kernel trace as {fn} (the bench's adjoint form:",
+             "forward tape, then the reverse sweep with segment recompute).", "",
+             "| kernel | calls | total us | average us |", "|---|---|---|---|"] +
+            [f"| {r[0]} | {r[1]} | {r[2]:.0f} | {r[3]:.2f} |" for r in adj] + [""]))
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump({"kernel": step_prefix + ", ...>", "workload": prob.name,
+                   "sources_sha256": src, "fetch_scale": fs, "write_scale": ws,
+                   "algorithmic_bytes_per_launch": alg, "variants": per_var,
+                   "source": "profiles/" + fn}, f, indent=1)
+    print(f"wrote profiles/{fn}, batch and adjoint summaries, "
+          f"{os.path.relpath(TRAFFIC_JSON, ROOT)}")
+
+
 def cpu_baseline(prob, steps=1):
     """The oracle, as it stands, on `steps` steps of the same lattice from
     the same initial state (single thread)."""
@@ -227,9 +401,19 @@ def main():
     ap.add_argument("--batch-bpc", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale)")
+    ap.add_argument("--traffic-sweep", action="store_true",
+                    help="counter runs: 1 GiB copy, every variant for "
+                         f"{SWEEP_LAUNCHES} launches, the batched form; no timing")
+    ap.add_argument("--summarize-profiles", metavar="RUN_DIR",
+                    help="write profiles/ from the rocprofv3 output of a run "
+                         "(CPU only; --variant, --batch-variant, --batch-bpc, "
+                         "--steps and --batch-steps as in the trace run)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "this implementation runs on one GPU; "
                           "--gpus must be 1"}))
         sys.exit(2)
 
@@ -239,6 +423,21 @@ def main():
     torch.cuda.set_device(0)
 
     prob = workload(args.workload)
+    if args.traffic_sweep:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        del a, b
+        names = traffic_sweep(prob)
+        import synth as S
+        probs = S.batch_table(count=args.batch_count, nsteps=args.batch_steps)
+        time_batched(probs, args.batch_steps, 0, autotune=False,
+                     graph_steps=0, variant=args.batch_variant,
+                     bpc=args.batch_bpc)
+        print(json.dumps({"traffic_sweep": prob.name, "variants": names,
+                          "launches_each": SWEEP_LAUNCHES}), flush=True)
+        return
     print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D2Q{prob.q} "
           f"steps {args.steps} warmup {args.warmup}", file=sys.stderr,
           flush=True)
