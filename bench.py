@@ -153,7 +153,7 @@ def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
     }
 
 
-def time_adjoint(prob, interval):
+def time_adjoint(prob, interval, autotune=True):
     """The reverse mode: forward run keeping a checkpoint tape, then the
     reverse sweep (segment recompute + reverse steps) giving dL/dT_wall
     (512 values), dL/dSte and dL/ddelta for L = 1/2 sum (xf - xf*)^2,
@@ -161,13 +161,17 @@ def time_adjoint(prob, interval):
     import numpy as np
     import torch
     import synth as S
-    from paper_2505_13097_amd import Stefan, _lib
+    from paper_2505_13097_amd import Stefan, _lib, variant_names
     twin = Stefan(prob.with_(wall_profile=(S.wall_target_profile(prob.ny),
                                            None, None, None)))
     twin.step(prob.nsteps)
     target = twin.front("integral")
     twin.close()
     s = Stefan(prob, flags=_lib.FLAG_ADJOINT)
+    tuned = None
+    if autotune:
+        v, ms = s.autotune(steps=20)
+        tuned = variant_names(prob.q, prob.storage)[v]
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
@@ -181,12 +185,14 @@ def time_adjoint(prob, interval):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s.close()
+    del tape
+    torch.cuda.empty_cache()
     fwd_ms = ev[0].elapsed_time(ev[1])
     bwd_ms = ev[1].elapsed_time(ev[2])
     lups = prob.nodes * prob.nsteps
     return {
         "workload": prob.name, "steps": prob.nsteps,
-        "checkpoint_interval": interval,
+        "checkpoint_interval": interval, "forward_variant": tuned,
         "value": round(lups / (bwd_ms * 1e-3) / 1e6, 1),
         "unit": "MLUPS (reverse sweep: recompute + reverse steps)",
         "forward_tape_mlups": round(lups / (fwd_ms * 1e-3) / 1e6, 1),
@@ -517,7 +523,10 @@ def main():
     if "adjoint" in args.forms.split(","):
         import synth as S
         print("[bench] adjoint form", file=sys.stderr, flush=True)
-        forms["adjoint"] = time_adjoint(S.adjoint_2d(), 64)
+        adj = S.adjoint_2d()
+        forms["adjoint"] = time_adjoint(adj, 64, not args.no_autotune)
+        # every state kept (no recompute): 4097 states of 5.2 MB fit in HBM
+        forms["adjoint_all_states"] = time_adjoint(adj, 1, not args.no_autotune)
         print("[bench] adjoint done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms

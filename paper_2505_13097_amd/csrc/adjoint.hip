@@ -42,9 +42,12 @@ namespace {
 struct AdjArgs {
   StepArgs A;              // A.src: the forward state at step n
   const double *abar_in;   // Omega'bar (q planes) / abar_0 for the init term
-  double *qbar;            // q planes
+  const double *qbar_in;   // qbar, Tbar of the later step (gather input)
+  const double *tbar_in;
+  double *qbar;            // q planes (node-local output)
   double *tbar;            // n
   double *abar_out;        // q planes
+  int32_t nblocks, per_xcd;  // node blocks of 256, blocks per XCD chunk
   double *gS, *gD;         // per-block partial sums (accumulated)
   double *gwall[4];        // per wall node (accumulated)
   const double *r;         // dL/dfront per row (front vjp)
@@ -56,6 +59,7 @@ __device__ __forceinline__ double dphi_ddelta(double t, double tm, double delta,
   return -((t - tm) / delta) * dph;
 }
 
+// block sums of a and b (fixed order) added to the block's slots *ga, *gb
 __device__ __forceinline__ void block_add2(double a, double b, double *ga, double *gb) {
   __shared__ double s[8];
   a = wave_sum(a);
@@ -67,8 +71,8 @@ __device__ __forceinline__ void block_add2(double a, double b, double *ga, doubl
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    ga[blockIdx.x] += (s[0] + s[1]) + (s[2] + s[3]);
-    gb[blockIdx.x] += (s[4] + s[5]) + (s[6] + s[7]);
+    *ga += (s[0] + s[1]) + (s[2] + s[3]);
+    *gb += (s[4] + s[5]) + (s[6] + s[7]);
   }
 }
 
@@ -76,105 +80,108 @@ __device__ __forceinline__ int wall_index(int wall, int x, int y) {
   return wall < 2 ? y : x;
 }
 
-// per node: recompute the forward step, reverse it down to qbar and Tbar
+// Node of block-local thread `tid` in 1-D blocks of 256 nodes, blocks
+// remapped so that each XCD (block b runs on XCD b mod 8) sweeps one
+// contiguous band of rows; `blk` is the block's slot index.
+__device__ __forceinline__ int64_t adj_node(const AdjArgs &G, int &blk) {
+  blk = (int)((blockIdx.x & 7) * G.per_xcd + (blockIdx.x >> 3));
+  return (int64_t)blk * 256 + threadIdx.x;
+}
+
+// per node: recompute the forward step at (x, y) from the state in G.A.src,
+// then reverse it from ab = Omega'bar(x) down to qbar and Tbar (written to
+// qbar_out, tbar_out) and the parameter and wall-temperature gradients
 template <int Q, typename S, bool PLAIN>
-__global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs G) {
+__device__ __forceinline__ void local_reverse(const AdjArgs &G, int x, int y,
+                                             int64_t k, const double ab[Q],
+                                             double *qbar_out, double *tbar_out,
+                                             double &accS, double &accD) {
   const StepArgs &A = G.A;
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double accS = 0.0, accD = 0.0;
-  if (k < A.plane) {
-    const int x = (int)(k % A.nx), y = (int)(k / A.nx);
-    NodeLoad<Q, S> L;
-    load_node<Q, S, false>(A, (const S *)A.src, x, y, L);
-    double om[Q], q[Q], th = 0.0;
+  NodeLoad<Q, S> L;
+  load_node<Q, S, false>(A, (const S *)A.src, x, y, L);
+  double om[Q], q[Q], th = 0.0;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      om[j] = (double)L.own[j];
-      th += om[j];
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
-    CloseInfo ci;
-    if (L.known != (1u << Q) - 1u) close_node<Q>(A, x, y, th, om, q, L.known, &ci);
-    double m0 = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) m0 += q[i];
-    const double S_ = G.ste, is = A.inv_ste, tm = A.tm, dl = G.delta;
-    const double P = phi_only(th, tm, A.inv_delta);
-    int it;
-    bool conv;
-    const double tn = newton<PLAIN>(m0, th, P, A, it, conv);
-    double Pt, dt, Pd_, d;
-    phi_dphi(tn, tm, A.inv_delta, Pt, dt);
-    phi_dphi(th, tm, A.inv_delta, Pd_, d);
-    const double dP = dphi_ddelta(th, tm, dl, d);
-    const double dPt = dphi_ddelta(tn, tm, dl, dt);
-    // reverse of Omega' = a f~ + (w/tau) sum f~
-    double ab[Q], qb[Q];
-    double tpb = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      ab[i] = G.abar_in[i * A.plane + k];
-      tpb += A.wtau[i] * ab[i];
-    }
-    double sb = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      qb[i] = A.a * ab[i] + tpb;
-      sb += wt<Q>(i) * qb[i];
-    }
-    // source s = (P - Pt)/Ste
-    double thl = sb * d * is;
-    const double tnb = -sb * dt * is;
-    double Sb = -sb * (P - Pt) * is * is;
-    double Db_ = sb * (dP - dPt) * is;
-    // Newton root (implicit-function theorem)
-    const double J = 1.0 + dt * is;
-    const double m0b = tnb / J;
-    thl += tnb * (d * is) / J;
-    Sb += tnb * (Pt - P) * is * is / J;
-    Db_ += -tnb * (dPt - dP) * is / J;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) qb[i] += m0b;
-    // closures, reversed: Dirichlet share, then bounce-back
-    if (ci.share) {
-      double Db = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        if (ci.share >> i & 1u) Db += qb[i] * (wt<Q>(i) / ci.wu);
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        if (!(ci.share >> i & 1u) && !(ci.own >> i & 1u)) qb[i] -= Db;
-      double PD, dPD;
-      phi_dphi(ci.TD, tm, A.inv_delta, PD, dPD);
-      G.gwall[ci.wall][wall_index(ci.wall, x, y)] += Db * (1.0 + dPD * is);
-      thl += -Db * d * is;
-      Sb += -Db * (PD - P) * is * is;
-      Db_ += Db * (dphi_ddelta(ci.TD, tm, dl, dPD) - dP) * is;
-    }
-#pragma unroll
-    for (int i = 1; i < Q; ++i)
-      if (ci.bb >> i & 1u) qb[opp<Q>(i)] += qb[i];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) G.qbar[i * A.plane + k] = qb[i];
-    G.tbar[k] = thl;
-    (void)S_;
-    accS = Sb;
-    accD = Db_;
+  for (int j = 0; j < Q; ++j) {
+    om[j] = (double)L.own[j];
+    th += om[j];
   }
-  block_add2(accS, accD, G.gS, G.gD);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
+  CloseInfo ci;
+  if (L.known != (1u << Q) - 1u) close_node<Q>(A, x, y, th, om, q, L.known, &ci);
+  double m0 = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) m0 += q[i];
+  const double is = A.inv_ste, tm = A.tm, dl = G.delta;
+  const double P = phi_only(th, tm, A.inv_delta);
+  int it;
+  bool conv;
+  const double tn = newton<PLAIN>(m0, th, P, A, it, conv);
+  double Pt, dt, Pd_, d;
+  phi_dphi(tn, tm, A.inv_delta, Pt, dt);
+  phi_dphi(th, tm, A.inv_delta, Pd_, d);
+  const double dP = dphi_ddelta(th, tm, dl, d);
+  const double dPt = dphi_ddelta(tn, tm, dl, dt);
+  // reverse of Omega' = a f~ + (w/tau) sum f~
+  double qb[Q];
+  double tpb = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) tpb += A.wtau[i] * ab[i];
+  double sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    qb[i] = A.a * ab[i] + tpb;
+    sb += wt<Q>(i) * qb[i];
+  }
+  // source s = (P - Pt)/Ste
+  double thl = sb * d * is;
+  const double tnb = -sb * dt * is;
+  double Sb = -sb * (P - Pt) * is * is;
+  double Db_ = sb * (dP - dPt) * is;
+  // Newton root (implicit-function theorem)
+  const double J = 1.0 + dt * is;
+  const double m0b = tnb / J;
+  thl += tnb * (d * is) / J;
+  Sb += tnb * (Pt - P) * is * is / J;
+  Db_ += -tnb * (dPt - dP) * is / J;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) qb[i] += m0b;
+  // closures, reversed: Dirichlet share, then bounce-back
+  if (ci.share) {
+    double Db = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (ci.share >> i & 1u) Db += qb[i] * (wt<Q>(i) / ci.wu);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (!(ci.share >> i & 1u) && !(ci.own >> i & 1u)) qb[i] -= Db;
+    double PD, dPD;
+    phi_dphi(ci.TD, tm, A.inv_delta, PD, dPD);
+    G.gwall[ci.wall][wall_index(ci.wall, x, y)] += Db * (1.0 + dPD * is);
+    thl += -Db * d * is;
+    Sb += -Db * (PD - P) * is * is;
+    Db_ += Db * (dphi_ddelta(ci.TD, tm, dl, dPD) - dP) * is;
+  }
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if (ci.bb >> i & 1u) qb[opp<Q>(i)] += qb[i];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) qbar_out[i * A.plane + k] = qb[i];
+  tbar_out[k] = thl;
+  accS = Sb;
+  accD = Db_;
 }
 
 // Omegabar_i(y) = qbar_i(y + e_i) (where that node pulls direction i from
-// y) + Tbar(y) + own-population closures at y
+// y) + Tbar(y) + own-population closures at y, from the qbar and Tbar a
+// node-local reverse left
 template <int Q>
-__global__ __launch_bounds__(256) void adj_pull_kernel(AdjArgs G) {
+__device__ __forceinline__ void pull_reverse(const AdjArgs &G,
+                                             const double *qbar,
+                                             const double *tbar, int x, int y,
+                                             int64_t k, double out[Q]) {
   const StepArgs &A = G.A;
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= A.plane) return;
-  const int x = (int)(k % A.nx), y = (int)(k / A.nx);
-  double out[Q];
-  const double tb = G.tbar[k];
+  const double tb = tbar[k];
 #pragma unroll
   for (int i = 0; i < Q; ++i) out[i] = tb;
   uint32_t known = 0;
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(256) void adj_pull_kernel(AdjArgs G) {
     if (zy < 0 || zy >= A.ny) {
       if (A.periodic_y) zy = (zy + A.ny) % A.ny; else ok = false;
     }
-    if (ok) out[i] += G.qbar[i * A.plane + (int64_t)zy * A.nx + zx];
+    if (ok) out[i] += qbar[i * A.plane + (int64_t)zy * A.nx + zx];
     // source x - e_i of this node (for its own closures)
     int sx = x - ex, sy = y - ey;
     bool sk = true;
@@ -204,11 +211,55 @@ __global__ __launch_bounds__(256) void adj_pull_kernel(AdjArgs G) {
     for (int i = 1; i < Q; ++i) {
       const int o = opp<Q>(i);
       const bool bb = (known >> o & 1u) && leaves_by_bounceback<Q>(A, x, y, i);
-      if (!(known >> i & 1u) && !bb) out[o] += G.qbar[i * A.plane + k];
+      if (!(known >> i & 1u) && !bb) out[o] += qbar[i * A.plane + k];
     }
   }
+}
+
+// node-local half of a reverse step: Omega'bar from G.abar_in
+template <int Q, typename S, bool PLAIN>
+__global__ __launch_bounds__(256) void adj_local_kernel(AdjArgs G) {
+  int blk;
+  const int64_t k = adj_node(G, blk);
+  double accS = 0.0, accD = 0.0;
+  if (blk < G.nblocks && k < G.A.plane) {
+    const int x = (int)(k % G.A.nx), y = (int)(k / G.A.nx);
+    double ab[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) G.abar_out[i * A.plane + k] = out[i];
+    for (int i = 0; i < Q; ++i) ab[i] = G.abar_in[i * G.A.plane + k];
+    local_reverse<Q, S, PLAIN>(G, x, y, k, ab, G.qbar, G.tbar, accS, accD);
+  }
+  if (blk < G.nblocks) block_add2(accS, accD, G.gS + blk, G.gD + blk);
+}
+
+// gather half of a reverse step: Omegabar into G.abar_out
+template <int Q>
+__global__ __launch_bounds__(256) void adj_pull_kernel(AdjArgs G) {
+  int blk;
+  const int64_t k = adj_node(G, blk);
+  if (blk >= G.nblocks || k >= G.A.plane) return;
+  const int x = (int)(k % G.A.nx), y = (int)(k / G.A.nx);
+  double out[Q];
+  pull_reverse<Q>(G, G.qbar_in, G.tbar_in, x, y, k, out);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) G.abar_out[i * G.A.plane + k] = out[i];
+}
+
+// the gather half of reverse step n + 1 fused with the node-local half of
+// reverse step n: Omega'bar(x) for step n is formed in registers from the
+// qbar/Tbar of step n + 1 (G.qbar_in, G.tbar_in) and never stored
+template <int Q, typename S, bool PLAIN>
+__global__ __launch_bounds__(256) void adj_fused_kernel(AdjArgs G) {
+  int blk;
+  const int64_t k = adj_node(G, blk);
+  double accS = 0.0, accD = 0.0;
+  if (blk < G.nblocks && k < G.A.plane) {
+    const int x = (int)(k % G.A.nx), y = (int)(k / G.A.nx);
+    double ab[Q];
+    pull_reverse<Q>(G, G.qbar_in, G.tbar_in, x, y, k, ab);
+    local_reverse<Q, S, PLAIN>(G, x, y, k, ab, G.qbar, G.tbar, accS, accD);
+  }
+  if (blk < G.nblocks) block_add2(accS, accD, G.gS + blk, G.gD + blk);
 }
 
 // seed: Omegabar_j(x, y) = r(y) dx w_x phi'(T(x, y)) for every j, and the
@@ -232,7 +283,7 @@ __global__ __launch_bounds__(256) void front_vjp_kernel(AdjArgs G) {
     for (int j = 0; j < Q; ++j) G.abar_out[j * A.plane + k] = c * d;
     accD = c * dphi_ddelta(T, A.tm, G.delta, d);
   }
-  block_add2(0.0, accD, G.gS, G.gD);
+  block_add2(0.0, accD, G.gS + blockIdx.x, G.gD + blockIdx.x);
 }
 
 // initial state: Omega_i = w_i T_D at Dirichlet nodes
@@ -251,7 +302,7 @@ __global__ __launch_bounds__(256) void init_term_kernel(AdjArgs G) {
 }
 
 struct AdjLayout {
-  size_t abar0, abar1, qbar, tbar, gS, gD, gwall, r, out, total;
+  size_t abar0, abar1, qbar[2], tbar[2], gS, gD, gwall, r, out, total;
   int64_t nblocks, wlen;
 };
 
@@ -265,10 +316,12 @@ AdjLayout adj_layout(const lbm_stefan_params *p) {
   o += align256((size_t)p->q * n * 8);
   L.abar1 = o;
   o += align256((size_t)p->q * n * 8);
-  L.qbar = o;
-  o += align256((size_t)p->q * n * 8);
-  L.tbar = o;
-  o += align256((size_t)n * 8);
+  for (int c = 0; c < 2; ++c) {
+    L.qbar[c] = o;
+    o += align256((size_t)p->q * n * 8);
+    L.tbar[c] = o;
+    o += align256((size_t)n * 8);
+  }
   L.gS = o;
   o += align256((size_t)L.nblocks * 8);
   L.gD = o;
@@ -297,8 +350,12 @@ AdjArgs make_args(lbm_stefan_t *h) {
   std::memset(&G, 0, sizeof(G));
   fill_step_args(h, &G.A);
   char *base = h->adj;
-  G.qbar = (double *)(base + L.qbar);
-  G.tbar = (double *)(base + L.tbar);
+  G.qbar = (double *)(base + L.qbar[0]);
+  G.tbar = (double *)(base + L.tbar[0]);
+  G.qbar_in = G.qbar;
+  G.tbar_in = G.tbar;
+  G.nblocks = (int32_t)L.nblocks;
+  G.per_xcd = (int32_t)((L.nblocks + 7) / 8);
   G.gS = (double *)(base + L.gS);
   G.gD = (double *)(base + L.gD);
   for (int w = 0; w < 4; ++w) G.gwall[w] = (double *)(base + L.gwall) + w * L.wlen;
@@ -313,29 +370,72 @@ unsigned node_blocks(const lbm_stefan_t *h) {
   return (unsigned)((h->p.nx * h->p.ny + 255) / 256);
 }
 
-hipError_t adjoint_step_async(lbm_stefan_t *h, const void *state,
-                              const double *abar_in, double *abar_out) {
+// grid of the remapped node kernels: eight XCD chunks of per_xcd blocks
+unsigned remapped_grid(const AdjArgs &G) { return 8u * (unsigned)G.per_xcd; }
+
+// node-local half of reverse step n: state_n and Omega'bar (abar_in) ->
+// qbar/Tbar buffer c
+hipError_t local_async(lbm_stefan_t *h, const void *state,
+                       const double *abar_in, int c) {
+  const AdjLayout L = adj_layout(&h->p);
   AdjArgs G = make_args(h);
   G.A.src = state;
   G.abar_in = abar_in;
-  G.abar_out = abar_out;
+  G.qbar = (double *)(h->adj + L.qbar[c]);
+  G.tbar = (double *)(h->adj + L.tbar[c]);
   const bool plain = h->p.newton_mode == LBM_NEWTON_PLAIN;
-  const unsigned nb = node_blocks(h);
-  hipError_t e = dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
+  return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     if (plain)
-      adj_local_kernel<Q, S, true><<<nb, 256, 0, h->stream>>>(G);
+      adj_local_kernel<Q, S, true><<<remapped_grid(G), 256, 0, h->stream>>>(G);
     else
-      adj_local_kernel<Q, S, false><<<nb, 256, 0, h->stream>>>(G);
+      adj_local_kernel<Q, S, false><<<remapped_grid(G), 256, 0, h->stream>>>(G);
     return hipGetLastError();
   });
-  if (e != hipSuccess) return e;
+}
+
+// gather half of a reverse step: qbar/Tbar buffer c -> Omegabar (abar_out)
+hipError_t pull_async(lbm_stefan_t *h, int c, double *abar_out) {
+  const AdjLayout L = adj_layout(&h->p);
+  AdjArgs G = make_args(h);
+  G.qbar_in = (const double *)(h->adj + L.qbar[c]);
+  G.tbar_in = (const double *)(h->adj + L.tbar[c]);
+  G.abar_out = abar_out;
   return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     (void)sizeof(S);
-    adj_pull_kernel<Q><<<nb, 256, 0, h->stream>>>(G);
+    adj_pull_kernel<Q><<<remapped_grid(G), 256, 0, h->stream>>>(G);
     return hipGetLastError();
   });
+}
+
+// gather half of reverse step n + 1 (qbar/Tbar buffer c) fused with the
+// node-local half of reverse step n (state_n) -> buffer c ^ 1
+hipError_t fused_async(lbm_stefan_t *h, const void *state, int c) {
+  const AdjLayout L = adj_layout(&h->p);
+  AdjArgs G = make_args(h);
+  G.A.src = state;
+  G.qbar_in = (const double *)(h->adj + L.qbar[c]);
+  G.tbar_in = (const double *)(h->adj + L.tbar[c]);
+  G.qbar = (double *)(h->adj + L.qbar[c ^ 1]);
+  G.tbar = (double *)(h->adj + L.tbar[c ^ 1]);
+  const bool plain = h->p.newton_mode == LBM_NEWTON_PLAIN;
+  return dispatch_qs(h->p.q, h->p.storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    if (plain)
+      adj_fused_kernel<Q, S, true><<<remapped_grid(G), 256, 0, h->stream>>>(G);
+    else
+      adj_fused_kernel<Q, S, false><<<remapped_grid(G), 256, 0, h->stream>>>(G);
+    return hipGetLastError();
+  });
+}
+
+// one whole reverse step: Omega'bar of step n + 1 -> Omegabar of step n
+hipError_t adjoint_step_async(lbm_stefan_t *h, const void *state,
+                              const double *abar_in, double *abar_out) {
+  hipError_t e = local_async(h, state, abar_in, 0);
+  if (e != hipSuccess) return e;
+  return pull_async(h, 0, abar_out);
 }
 
 hipError_t front_vjp_async(lbm_stefan_t *h, const void *state,
@@ -496,16 +596,21 @@ int lbm_stefan_forward_tape(lbm_stefan_t *h, int64_t nsteps, int64_t interval,
   char *t = (char *)tape;
   HIPCHK(h, hipMemcpyAsync(t, h->buf[h->cur], sb, hipMemcpyDeviceToDevice,
                            h->stream));
+  // segment k starts from checkpoint k - 1 and its last step writes
+  // checkpoint k directly; the steps between use the handle's two buffers
   for (int64_t k = 1; k <= K; ++k) {
     const int64_t n = std::min(I, nsteps - (k - 1) * I);
+    const void *src = t + (k - 1) * slot;
     for (int64_t s = 0; s < n; ++s) {
-      HIPCHK(h, launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]));
-      h->cur ^= 1;
+      void *dst = s == n - 1 ? (void *)(t + k * slot) : h->buf[s & 1];
+      HIPCHK(h, launch_step(h, src, dst));
       h->steps++;
+      src = dst;
     }
-    HIPCHK(h, hipMemcpyAsync(t + k * slot, h->buf[h->cur], sb,
-                             hipMemcpyDeviceToDevice, h->stream));
   }
+  h->cur = 0;
+  HIPCHK(h, hipMemcpyAsync(h->buf[0], t + K * slot, sb,
+                           hipMemcpyDeviceToDevice, h->stream));
   h->tape = tape;
   h->tape_steps = nsteps;
   h->tape_interval = I;
@@ -531,20 +636,30 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
   char *seg = t + (K + 1) * slot;
   HIPCHK(h, reset_async(h));
   HIPCHK(h, front_vjp_async(h, t + K * slot, dL_dfront, ab[0]));
-  int c = 0;
+  // reverse steps N-1 .. 0: the last one node-local only (its Omega'bar is
+  // the front seed), then gather-of-(n+1) fused with local-of-n, then the
+  // final gather; qbar/Tbar alternate between two buffers
+  int c = -1;
   for (int64_t k = K - 1; k >= 0; --k) {
     const int64_t n = std::min(I, N - k * I);
-    // recompute the states of segment k
-    HIPCHK(h, hipMemcpyAsync(seg, t + k * slot, sb, hipMemcpyDeviceToDevice,
-                             h->stream));
+    // states of segment k: the checkpoint itself, then recomputed ones
+    auto state = [&](int64_t j) -> const void * {
+      return j == 0 ? (const void *)(t + k * slot) : (const void *)(seg + j * slot);
+    };
     for (int64_t j = 1; j < n; ++j)
-      HIPCHK(h, launch_step(h, seg + (j - 1) * slot, seg + j * slot));
+      HIPCHK(h, launch_step(h, state(j - 1), seg + j * slot));
     for (int64_t j = n - 1; j >= 0; --j) {
-      HIPCHK(h, adjoint_step_async(h, seg + j * slot, ab[c], ab[c ^ 1]));
-      c ^= 1;
+      if (c < 0) {
+        HIPCHK(h, local_async(h, state(j), ab[0], 0));
+        c = 0;
+      } else {
+        HIPCHK(h, fused_async(h, state(j), c));
+        c ^= 1;
+      }
     }
   }
-  HIPCHK(h, init_term_async(h, ab[c]));
+  HIPCHK(h, pull_async(h, c, ab[1]));
+  HIPCHK(h, init_term_async(h, ab[1]));
   return read_gradients(h, g_wall, g_ste, g_delta);
 }
 

@@ -33,7 +33,8 @@ inline const Variant *variants(int q, int *n) {
       {64, 4, 2, 0, 1, 1}, {64, 4, 2, 1, 1, 1},  {128, 2, 2, 0, 1, 1},
       {64, 4, 2, 1, 0, 2}, {64, 4, 2, 1, 0, 4},  {64, 4, 2, 1, 0, 8},
       {64, 4, 2, 0, 0, 4}, {64, 4, 1, 1, 0, 4},  {64, 4, 2, 1, 1, 4},
-      {128, 2, 2, 1, 0, 4}, {64, 4, 2, 1, 0, 16}};
+      {128, 2, 2, 1, 0, 4}, {64, 4, 2, 1, 0, 16}, {64, 1, 1, 0, 0, 1},
+      {64, 2, 1, 0, 0, 1}};
   if (q == 3) {
     *n = (int)(sizeof(v1) / sizeof(Variant));
     return v1;
