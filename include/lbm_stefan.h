@@ -203,7 +203,10 @@ int lbm_stefan_state_ptr(lbm_stefan_t *h, void **dev_state);
 /* Number of compiled kernel variants for a lattice/storage pair, and the
    name of one ("<tile_x>x<tile_y>/npt<k>[/r<m>][/nt][/rev]": tile size,
    nodes per thread, m tiles stacked along y per thread block,
-   non-temporal stores, block order reversed every other step); used by
+   non-temporal stores, block order reversed every other step; or
+   "256x<b>/t2/r<m>[/nt]": two time steps per launch, a 256-column window
+   sweeping m rows, b rows per pass; a single trailing step then uses the
+   default variant, and the batched form rejects these); used by
    autotuners. */
 int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count);
 const char *lbm_stefan_variant_name(int32_t q, int32_t storage,

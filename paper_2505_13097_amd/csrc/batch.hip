@@ -142,6 +142,7 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   const Variant *v = variants(ps[0].q, &nv);
   L.max_items = 0;
   for (int i = 0; i < nv; ++i) {
+    if (v[i].tb) continue;
     int64_t t = 0;
     for (int k = 0; k < count; ++k) t += items_for(v[i], ps[k].nx, ps[k].ny);
     L.max_items = std::max(L.max_items, t);
@@ -418,9 +419,12 @@ int lbm_stefan_batch_set_schedule(lbm_stefan_batch_t *b, int32_t variant,
                                   int32_t blocks_per_cu, int32_t graph_steps) {
   if (!b) return bfail(nullptr, LBM_STEFAN_EINVAL, "batch is NULL");
   int nv;
-  variants(b->q, &nv);
+  const Variant *vt = variants(b->q, &nv);
   if (variant < -1 || variant >= nv)
     return bfail(b, LBM_STEFAN_EINVAL, "unknown kernel variant");
+  if (variant >= 0 && vt[variant].tb)
+    return bfail(b, LBM_STEFAN_EINVAL,
+                 "two-step variants are for single lattices only");
   if (blocks_per_cu < 0 || blocks_per_cu > 32)
     return bfail(b, LBM_STEFAN_EINVAL, "blocks_per_cu must be in 0..32");
   if (graph_steps < 0 || graph_steps % 2 || graph_steps > 100000)
@@ -587,7 +591,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
     return bfail(b, LBM_STEFAN_EDEVICE, "hipEventCreate failed");
   }
   int nv;
-  variants(b->q, &nv);
+  const Variant *vt = variants(b->q, &nv);
   const int bpcs[] = {0, 2, 4, 8};
   const int v0 = b->variant, bpc0 = b->blocks_per_cu;
   int best_v = v0, best_bpc = bpc0;
@@ -595,6 +599,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
   int rc = LBM_STEFAN_OK;
   hipError_t err = hipSuccess;
   for (int v = 0; v < nv && rc == LBM_STEFAN_OK && err == hipSuccess; ++v) {
+    if (vt[v].tb) continue;  // single lattices only
     if (v != b->variant) {
       b->variant = v;
       rc = build_schedule(b);

@@ -360,11 +360,36 @@ __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
   return fill;
 }
 
-// The update of one node from its loads; writes the next state.
-template <int Q, typename S, bool PLAIN, bool FAST, bool NT = false>
-__device__ __forceinline__ void update_node(const StepArgs &A, S *__restrict__ dst,
-                                   int x, int y, const NodeLoad<Q, S> &L,
-                                   NodeStats &st) {
+// Which pull sources of node (x, y) are lattice nodes (bit i of known,
+// wrapping periodic axes) and which destinations x + e_i leave the lattice
+// (bit i of out): the masks load_node computes, from coordinates only.
+template <int Q>
+__device__ __forceinline__ void node_masks(const StepArgs &A, int x, int y,
+                                           uint32_t &known, uint32_t &out) {
+  const bool vxm = x - 1 >= 0 || A.periodic_x != 0;
+  const bool vxp = x + 1 < A.nx || A.periodic_x != 0;
+  const bool vym = Q == 3 || y - 1 >= 0 || A.periodic_y != 0;
+  const bool vyp = Q == 3 || y + 1 < A.ny || A.periodic_y != 0;
+  known = 1u;
+  out = 0u;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int ex = cx<Q>(i), ey = cy<Q>(i);
+    const bool ok = (ex == 1 ? vxm : (ex == -1 ? vxp : true)) &&
+                    (ey == 1 ? vym : (ey == -1 ? vyp : true));
+    const bool leaves = (ex == 1 ? !vxp : (ex == -1 ? !vxm : false)) ||
+                        (ey == 1 ? !vyp : (ey == -1 ? !vym : false));
+    if (ok) known |= 1u << i;
+    if (leaves) out |= 1u << i;
+  }
+}
+
+// The update of one node from its loads: the next state's populations
+// into v (rounded to the storage type).
+template <int Q, typename S, bool PLAIN, bool FAST>
+__device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
+                                              const NodeLoad<Q, S> &L,
+                                              NodeStats &st, S v[Q]) {
   double om[Q], q[Q];
   double th = 0.0;
 #pragma unroll
@@ -399,17 +424,27 @@ __device__ __forceinline__ void update_node(const StepArgs &A, S *__restrict__ d
     f[i] = q[i] + A.wste[i] * dphi_s;
     tsum += f[i];
   }
-  const int64_t base = (int64_t)y * A.nx + x;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const S v = (S)(A.a * f[i] + A.wtau[i] * tsum);
-    if (NT) __builtin_nontemporal_store(v, dst + i * A.plane + base);
-    else dst[i * A.plane + base] = v;
-  }
+  for (int i = 0; i < Q; ++i) v[i] = (S)(A.a * f[i] + A.wtau[i] * tsum);
   const double res = fabs(tn + pnew * A.inv_ste - (m0 + pth * A.inv_ste));
   st.max_it = it > st.max_it ? it : st.max_it;
   st.nonconv += conv ? 0 : 1;
   st.max_res = res > st.max_res ? res : st.max_res;
+}
+
+// The update of one node from its loads; writes the next state.
+template <int Q, typename S, bool PLAIN, bool FAST, bool NT = false>
+__device__ __forceinline__ void update_node(const StepArgs &A, S *__restrict__ dst,
+                                   int x, int y, const NodeLoad<Q, S> &L,
+                                   NodeStats &st) {
+  S v[Q];
+  update_values<Q, S, PLAIN, FAST>(A, x, y, L, st, v);
+  const int64_t base = (int64_t)y * A.nx + x;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (NT) __builtin_nontemporal_store(v[i], dst + i * A.plane + base);
+    else dst[i * A.plane + base] = v[i];
+  }
 }
 
 // ---- wave and block reductions (wave64)

@@ -29,15 +29,16 @@ constexpr int kEnergyChunk = 2048;  // nodes per energy partial
 
 // Statistics of one block (already reduced over the node loop of each
 // thread), combined across the block and added by thread 0 to the item's
-// slot, whose previous value `pre` thread 0 loaded.  LOOP: the block goes
-// on to another item, so the shared arrays are fenced again.
+// slot, whose previous value `pre` thread 0 loaded (blocks of up to 1024
+// threads).  LOOP: the block goes on to another item, so the shared arrays
+// are fenced again.
 template <bool LOOP>
 __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
                                                     bool fast,
                                                     const StatSlot &pre,
                                                     StatSlot *sl) {
-  __shared__ int s_it[4], s_nc[4];
-  __shared__ double s_res[4], s_fin[4], s_fout[4];
+  __shared__ int s_it[16], s_nc[16];
+  __shared__ double s_res[16], s_fin[16], s_fout[16];
   const int lin = (int)(threadIdx.x + threadIdx.y * blockDim.x);
   const int wid = lin >> 6, nw = (int)(blockDim.x * blockDim.y) >> 6;
   const int it = wave_max_i(st.max_it);
@@ -170,6 +171,138 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int t = xcd_item(b, A.per_xcd, A.nitems, A.reverse);
   step_item<Q, S, NPT, PLAIN, NT>(A, (const S *)A.src, (S *)A.dst, t,
                                   A.slots + t);
+}
+
+// ---------------------------------------------------------------------
+// two time steps per launch (temporal blocking)
+//
+// Each block owns a strip of kStripOut columns and a segment of rows of
+// the output, and sweeps the segment upward with a window of kStripWin =
+// kStripOut + 4 columns (2 halo columns on each side).  Per pass it loads
+// BY new rows of the state at step n into a ring in LDS, computes BY rows
+// of step n + 1 from that ring into a second ring (a halo of one row and
+// one column around the block's part is recomputed by the neighbours as
+// well), and BY rows of step n + 2 from the second ring, which it writes.
+// So a node pair of steps moves q s bytes in and q s bytes out, half of
+// two single steps, and every node update is the same code
+// (update_values) on the same operands, so the result equals two single
+// steps bit for bit.  Statistics count each node once per step: only the
+// nodes of the block's own part, at both levels.
+constexpr int kStripWin = 256;
+constexpr int kStripOut = kStripWin - 4;
+
+// NodeLoad of node (x, y) (lattice coordinates) from a ring of rows in
+// LDS: column t of the window, ring slot of row r at slot(r)
+template <int Q, typename S, int RING>
+__device__ __forceinline__ void load_ring(const StepArgs &A,
+                                          const S (*ring)[Q][kStripWin],
+                                          int x, int y, int t, int r, int base,
+                                          NodeLoad<Q, S> &L) {
+  node_masks<Q>(A, x, y, L.known, L.out);
+  const int so = (r - base) % RING;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) L.own[j] = ring[so][j][t];
+  L.pull[0] = L.own[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int ex = cx<Q>(i), ey = cy<Q>(i);
+    const S v = ring[(r - ey - base) % RING][i][t - ex];
+    L.pull[i] = (L.known >> i & 1u) ? v : (S)0;
+  }
+}
+
+template <int Q, typename S, bool PLAIN, bool NT, int BY>
+__global__ __launch_bounds__(kStripWin * BY) void step2_kernel(
+    StepArgs A, int32_t nstrips, int32_t seg_rows) {
+  constexpr int RING = BY + 2;
+  __shared__ S l0[RING][Q][kStripWin];
+  __shared__ S l1[RING][Q][kStripWin];
+  const int t = (int)threadIdx.x, ty = (int)threadIdx.y;
+  const int strip = (int)blockIdx.x % nstrips;
+  const int seg = (int)blockIdx.x / nstrips;
+  const int s0 = seg * seg_rows;
+  const int s1 = min(s0 + seg_rows, A.ny);       // output rows [s0, s1)
+  const int x = strip * kStripOut - 2 + t;        // window column
+  const int nx = A.nx, ny = A.ny;
+  // lattice column of this window column (wrapped on a periodic axis)
+  int gx = x;
+  bool col = x >= 0 && x < nx;
+  if (!col && A.periodic_x) {
+    gx = (x % nx + nx) % nx;
+    col = true;
+  }
+  const bool own_col = t >= 2 && t < kStripWin - 2 && x >= 0 && x < nx;
+  // ring slots: (row - base) % RING with base a multiple of RING below
+  // every row touched (rows >= s0 - 4)
+  const int base = s0 - 12;
+  const S *src = (const S *)A.src;
+  S *dst = (S *)A.dst;
+  // lattice row of row r (wrapped on a periodic axis), or -1
+  auto lrow = [&](int r) -> int {
+    if (r >= 0 && r < ny) return r;
+    return A.periodic_y ? (r % ny + ny) % ny : -1;
+  };
+  const int iters = (s1 - s0 + 4 + BY - 1) / BY;
+  S pf[Q];
+  {
+    const int gr = lrow(s0 - 2 + ty);
+    const int64_t o = (int64_t)(gr < 0 ? 0 : gr) * nx + (col ? gx : 0);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) pf[j] = src[j * A.plane + o];
+  }
+  NodeStats st, halo;
+  for (int i = 0; i < iters; ++i) {
+    // arguments re-read in every pass (see step_item)
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    const StepArgs &Ai = (&A)[z];
+    const int a = s0 - 2 + i * BY;
+    // rows a .. a + BY - 1 of step n into the first ring
+#pragma unroll
+    for (int j = 0; j < Q; ++j) l0[(a + ty - base) % RING][j][t] = pf[j];
+    if (i + 1 < iters) {
+      const int gr = lrow(a + BY + ty);
+      const int64_t o = (int64_t)(gr < 0 ? 0 : gr) * nx + (col ? gx : 0);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) pf[j] = src[j * Ai.plane + o];
+    }
+    __syncthreads();
+    // step n + 1 at row b (needed rows s0 - 1 .. s1)
+    {
+      const int b = a - 1 + ty;
+      const int gb = lrow(b);
+      if (t >= 1 && t < kStripWin - 1 && col && gb >= 0 && b >= s0 - 1 &&
+          b <= s1) {
+        NodeLoad<Q, S> L;
+        load_ring<Q, S, RING>(Ai, l0, gx, gb, t, b, base, L);
+        S v[Q];
+        const bool mine = own_col && b >= s0 && b < s1;
+        update_values<Q, S, PLAIN, false>(Ai, gx, gb, L, mine ? st : halo, v);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) l1[(b - base) % RING][j][t] = v[j];
+      }
+    }
+    __syncthreads();
+    // step n + 2 at row c, written out
+    {
+      const int c = a - 2 + ty;
+      if (own_col && c >= s0 && c < s1) {
+        NodeLoad<Q, S> L;
+        load_ring<Q, S, RING>(Ai, l1, x, c, t, c, base, L);
+        S v[Q];
+        update_values<Q, S, PLAIN, false>(Ai, x, c, L, st, v);
+        const int64_t o = (int64_t)c * nx + x;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          if (NT) __builtin_nontemporal_store(v[j], dst + j * Ai.plane + o);
+          else dst[j * Ai.plane + o] = v[j];
+        }
+      }
+    }
+  }
+  StatSlot pre{};
+  if (t == 0 && ty == 0) pre = A.slots[blockIdx.x];
+  block_stats_to_slot<false>(st, false, pre, A.slots + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------

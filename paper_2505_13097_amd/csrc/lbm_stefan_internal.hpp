@@ -64,6 +64,12 @@ void fill_args(const lbm_stefan_params &p, double *const prof[4],
                StepArgs *A);
 void fill_step_args(const lbm_stefan_t *h, StepArgs *A);
 hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst);
+// two steps in one launch (the handle's variant is a two-step variant)
+hipError_t launch_step2(const lbm_stefan_t *h, const void *src, void *dst);
+bool two_step_variant(const lbm_stefan_t *h);
+// advance the handle nsteps (pairs of steps in one launch under a two-step
+// variant); updates cur and steps
+hipError_t advance(lbm_stefan_t *h, int64_t nsteps);
 hipError_t zero_stats_async(lbm_stefan_t *h);
 int read_stats(lbm_stefan_t *h, lbm_stefan_stats *st);
 

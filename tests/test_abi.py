@@ -117,7 +117,8 @@ def test_variants_listed(L):
     for q in (3, 5, 9):
         names = variant_names(q)
         assert len(names) >= 3
-        assert all(re.fullmatch(r"\d+x\d+/npt\d(/r\d+)?(/nt)?(/rev)?", n) for n in names)
+        assert all(re.fullmatch(r"\d+x\d+(/npt\d|/t2)(/r\d+)?(/nt)?(/rev)?", n)
+                   for n in names)
     assert L.lib().lbm_stefan_variant_name(5, 1, 999) == b""
 
 

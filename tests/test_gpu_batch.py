@@ -175,3 +175,16 @@ def test_batch_energy_balance_per_instance():
         dE = s["energy"] - E0[k]
         assert abs(dE - (s["flux_in"] - s["flux_out"])) < 1e-9 * max(1, abs(dE))
     b.close()
+
+
+def test_batch_rejects_two_step_variants():
+    from paper_2505_13097_amd import StefanBatch, variant_names, LbmError
+    probs = [p for p in _mixed("f64", count=5) if p.newton_mode == "safeguarded"]
+    b = StefanBatch(probs)
+    tb = [i for i, n in enumerate(variant_names(5, "f64")) if "/t2" in n]
+    assert tb
+    with pytest.raises(LbmError):
+        b.set_schedule(tb[0], 0, 0)
+    b.step(3)
+    b.close()
+

@@ -72,7 +72,9 @@ def _compare(prob, g, o, tol):
         assert np.all(fr <= 2 * sens * max(err, 1e-16) +
                       1e-14 * np.maximum(np.abs(o["front"]), prob.dx))
         cr = np.abs(g["cross"] - o["cross"])
-        assert np.all(cr <= 1e-9 * np.maximum(np.abs(o["cross"]), prob.dx))
+        ok = _crossing_well_posed(prob, o["T"], o["cross"], err)
+        assert ok.sum() >= prob.ny // 2
+        assert np.all(cr[ok] <= 1e-9 * np.maximum(np.abs(o["cross"][ok]), prob.dx))
         assert abs(g["energy"] - o["energy"]) <= 1e-12 * max(1.0, abs(o["energy"])) * 10
         for k in ("flux_in", "flux_out"):
             a, b = g["stats"][k], o["stats"][k]
@@ -82,6 +84,20 @@ def _compare(prob, g, o, tol):
         cr = np.abs(g["cross"] - o["cross"])
         assert np.all(cr <= prob.dx), cr.max()
         assert abs(g["energy"] - o["energy"]) <= 1e-5 * prob.nodes
+
+
+def _crossing_well_posed(prob, T, cross, err):
+    """Rows whose zero-crossing front is a continuous function of T at
+    the observed error: the first crossing from x = 0 jumps to another
+    cell when T - T_m at a node before it (or at the crossing cell's ends)
+    is within a few times the temperature error of zero."""
+    ok = np.ones(prob.ny, dtype=bool)
+    margin = 8.0 * max(err, 1e-16)
+    for y in range(prob.ny):
+        k = int(min(prob.nx - 1, np.floor(cross[y] / prob.dx) + 1))
+        if np.any(np.abs(T[y, :k + 1] - prob.tm) <= margin):
+            ok[y] = False
+    return ok
 
 
 def _smooth_mushy(prob, amp_cells=2.0, walls_cells=2.0):
@@ -156,6 +172,35 @@ def test_variants_bitwise_identical():
         if ref is None:
             ref = T
         assert np.array_equal(T, ref), v
+
+
+def _two_step_variants(q, storage):
+    from paper_2505_13097_amd import variant_names
+    return [i for i, n in enumerate(variant_names(q, storage)) if "/t2" in n]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", [0, 1, 3, 4, 5, 6, 7])
+def test_two_step_variants_against_oracle(case, storage):
+    """Two steps per launch (rings of rows in LDS): the same bars against
+    the oracle, on ragged, periodic, all-bounce-back, mixed-wall and 3x3
+    lattices, with an odd step count (the last step single)."""
+    name, make, steps = CASES[case]
+    prob = make(storage).with_(name=f"{name}_{storage}_t2")
+    o = _oracle_run(prob, steps + 1)
+    for v in _two_step_variants(prob.q, storage):
+        g = _gpu_run(prob, steps + 1, variant=v)
+        _compare(prob, g, o, TOL64 if storage == "f64" else TOL32)
+
+
+def test_two_step_variants_bitwise_equal_single_steps():
+    """Each node update of the two-step kernel is the single-step code on
+    the same operands: equal states after an odd number of steps."""
+    prob = _smooth_mushy(synth.planar_2d(n=600, ny=333, storage="f32")).with_(
+        bc=("dirichlet", "bounceback", "periodic", "periodic"))
+    ref = _gpu_run(prob, 25, variant=3)["T"]
+    for v in _two_step_variants(5, "f32"):
+        assert np.array_equal(_gpu_run(prob, 25, variant=v)["T"], ref), v
 
 
 def test_zero_steps_and_state_roundtrip():
