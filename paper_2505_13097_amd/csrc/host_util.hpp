@@ -18,8 +18,9 @@ namespace irebm {
 // sweeps `rows` tiles stacked along y.  nt: stores bypass the caches
 // (non-temporal); rev: the item order is reversed on every other step, so
 // that the rows written last (still in the memory-side cache) are read
-// first.  tb: two steps per launch (step2_kernel): a window of bx = 256
-// columns, by rows per pass, `rows` rows per block.
+// first.  tb: two steps per launch (step2_kernel): a window of bx columns
+// (bx - 4 written), by rows per pass, `rows` rows per block, non-temporal
+// stores.
 struct Variant {
   int bx, by, npt, nt, rev, rows, tb;
 };
@@ -36,9 +37,10 @@ inline const Variant *variants(int q, int *n) {
       {64, 4, 2, 0, 0, 4}, {64, 4, 1, 1, 0, 4},  {64, 4, 2, 1, 1, 4},
       {128, 2, 2, 1, 0, 4}, {64, 4, 2, 1, 0, 16}, {64, 1, 1, 0, 0, 1},
       {64, 2, 1, 0, 0, 1},
-      {kStripWin, 1, 1, 1, 0, 128, 1}, {kStripWin, 2, 1, 1, 0, 128, 1},
-      {kStripWin, 2, 1, 1, 0, 256, 1}, {kStripWin, 2, 1, 1, 0, 64, 1},
-      {kStripWin, 2, 1, 0, 0, 128, 1}};
+      {256, 2, 1, 1, 0, 64, 1},  {256, 2, 1, 1, 0, 128, 1},
+      {256, 1, 1, 1, 0, 64, 1},  {128, 2, 1, 1, 0, 32, 1},
+      {128, 2, 1, 1, 0, 64, 1},  {128, 2, 1, 1, 0, 128, 1},
+      {128, 4, 1, 1, 0, 64, 1},  {128, 4, 1, 1, 0, 128, 1}};
   if (q == 3) {
     *n = (int)(sizeof(v1) / sizeof(Variant));
     return v1;
@@ -59,7 +61,7 @@ inline int64_t tiles_y_for(const Variant &v, int64_t ny) {
 // work items (one block each) of an nx x ny lattice
 inline int64_t items_for(const Variant &v, int64_t nx, int64_t ny) {
   if (v.tb)
-    return ((nx + kStripOut - 1) / kStripOut) * ((ny + v.rows - 1) / v.rows);
+    return ((nx + v.bx - 5) / (v.bx - 4)) * ((ny + v.rows - 1) / v.rows);
   return tiles_x_for(v, nx) * ((tiles_y_for(v, ny) + v.rows - 1) / v.rows);
 }
 // tile grid and work items of A for variant v

@@ -176,26 +176,30 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
 // ---------------------------------------------------------------------
 // two time steps per launch (temporal blocking)
 //
-// Each block owns a strip of kStripOut columns and a segment of rows of
-// the output, and sweeps the segment upward with a window of kStripWin =
-// kStripOut + 4 columns (2 halo columns on each side).  Per pass it loads
-// BY new rows of the state at step n into a ring in LDS, computes BY rows
-// of step n + 1 from that ring into a second ring (a halo of one row and
-// one column around the block's part is recomputed by the neighbours as
-// well), and BY rows of step n + 2 from the second ring, which it writes.
-// So a node pair of steps moves q s bytes in and q s bytes out, half of
-// two single steps, and every node update is the same code
-// (update_values) on the same operands, so the result equals two single
-// steps bit for bit.  Statistics count each node once per step: only the
-// nodes of the block's own part, at both levels.
-constexpr int kStripWin = 256;
-constexpr int kStripOut = kStripWin - 4;
+// Each block owns a strip of WIN - 4 columns and a segment of rows of the
+// output, and sweeps the segment upward with a window of WIN columns (2
+// halo columns on each side).  Per pass it loads BY new rows of the state
+// at step n into a ring in LDS, computes BY rows of step n + 1 from that
+// ring into a second ring (a halo of one row and one column around the
+// block's part is recomputed by the neighbours as well), and BY rows of
+// step n + 2 from the second ring, which it writes.  So a node pair of
+// steps moves q s bytes in and q s bytes out, half of two single steps,
+// and every node update is the same code (update_values) on the same
+// operands, so the result equals two single steps bit for bit.
+// Statistics count each node once per step: only the nodes of the
+// block's own part, at both levels.
+//
+// Loads and stores share one counter on this chip, and a wait for the
+// prefetched rows waits for every store issued before them as well; so
+// the rows of step n + 2 are stored at the top of the next pass, right
+// after the wait and before the next prefetch, which leaves a whole pass
+// for both to complete.
 
 // NodeLoad of node (x, y) (lattice coordinates) from a ring of rows in
-// LDS: column t of the window, ring slot of row r at slot(r)
-template <int Q, typename S, int RING>
+// LDS: column t of the window, ring slot of row r at (r - base) % RING
+template <int Q, typename S, int RING, int WIN>
 __device__ __forceinline__ void load_ring(const StepArgs &A,
-                                          const S (*ring)[Q][kStripWin],
+                                          const S (*ring)[Q][WIN],
                                           int x, int y, int t, int r, int base,
                                           NodeLoad<Q, S> &L) {
   node_masks<Q>(A, x, y, L.known, L.out);
@@ -211,18 +215,18 @@ __device__ __forceinline__ void load_ring(const StepArgs &A,
   }
 }
 
-template <int Q, typename S, bool PLAIN, bool NT, int BY>
-__global__ __launch_bounds__(kStripWin * BY) void step2_kernel(
+template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
+__global__ __launch_bounds__(WIN * BY) void step2_kernel(
     StepArgs A, int32_t nstrips, int32_t seg_rows) {
   constexpr int RING = BY + 2;
-  __shared__ S l0[RING][Q][kStripWin];
-  __shared__ S l1[RING][Q][kStripWin];
+  __shared__ S l0[RING][Q][WIN];
+  __shared__ S l1[RING][Q][WIN];
   const int t = (int)threadIdx.x, ty = (int)threadIdx.y;
   const int strip = (int)blockIdx.x % nstrips;
   const int seg = (int)blockIdx.x / nstrips;
   const int s0 = seg * seg_rows;
   const int s1 = min(s0 + seg_rows, A.ny);       // output rows [s0, s1)
-  const int x = strip * kStripOut - 2 + t;        // window column
+  const int x = strip * (WIN - 4) - 2 + t;        // window column
   const int nx = A.nx, ny = A.ny;
   // lattice column of this window column (wrapped on a periodic axis)
   int gx = x;
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(kStripWin * BY) void step2_kernel(
     gx = (x % nx + nx) % nx;
     col = true;
   }
-  const bool own_col = t >= 2 && t < kStripWin - 2 && x >= 0 && x < nx;
+  const bool own_col = t >= 2 && t < WIN - 2 && x >= 0 && x < nx;
   // ring slots: (row - base) % RING with base a multiple of RING below
   // every row touched (rows >= s0 - 4)
   const int base = s0 - 12;
@@ -250,7 +254,9 @@ __global__ __launch_bounds__(kStripWin * BY) void step2_kernel(
 #pragma unroll
     for (int j = 0; j < Q; ++j) pf[j] = src[j * A.plane + o];
   }
-  NodeStats st, halo;
+  S w[Q];            // a row of step n + 2 waiting to be stored
+  int64_t wo = -1;   // its offset, or -1
+  NodeStats st;
   for (int i = 0; i < iters; ++i) {
     // arguments re-read in every pass (see step_item)
     int z = 0;
@@ -260,6 +266,14 @@ __global__ __launch_bounds__(kStripWin * BY) void step2_kernel(
     // rows a .. a + BY - 1 of step n into the first ring
 #pragma unroll
     for (int j = 0; j < Q; ++j) l0[(a + ty - base) % RING][j][t] = pf[j];
+    if (wo >= 0) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        if (NT) __builtin_nontemporal_store(w[j], dst + j * Ai.plane + wo);
+        else dst[j * Ai.plane + wo] = w[j];
+      }
+      wo = -1;
+    }
     if (i + 1 < iters) {
       const int gr = lrow(a + BY + ty);
       const int64_t o = (int64_t)(gr < 0 ? 0 : gr) * nx + (col ? gx : 0);
@@ -271,33 +285,40 @@ __global__ __launch_bounds__(kStripWin * BY) void step2_kernel(
     {
       const int b = a - 1 + ty;
       const int gb = lrow(b);
-      if (t >= 1 && t < kStripWin - 1 && col && gb >= 0 && b >= s0 - 1 &&
-          b <= s1) {
+      if (t >= 1 && t < WIN - 1 && col && gb >= 0 && b >= s0 - 1 && b <= s1) {
         NodeLoad<Q, S> L;
-        load_ring<Q, S, RING>(Ai, l0, gx, gb, t, b, base, L);
+        load_ring<Q, S, RING, WIN>(Ai, l0, gx, gb, t, b, base, L);
         S v[Q];
-        const bool mine = own_col && b >= s0 && b < s1;
-        update_values<Q, S, PLAIN, false>(Ai, gx, gb, L, mine ? st : halo, v);
+        NodeStats one;
+        update_values<Q, S, PLAIN, false>(Ai, gx, gb, L, one, v);
+        if (own_col && b >= s0 && b < s1) {
+          st.max_it = max(st.max_it, one.max_it);
+          st.nonconv += one.nonconv;
+          st.max_res = fmax(st.max_res, one.max_res);
+          st.flux_in += one.flux_in;
+          st.flux_out += one.flux_out;
+        }
 #pragma unroll
         for (int j = 0; j < Q; ++j) l1[(b - base) % RING][j][t] = v[j];
       }
     }
     __syncthreads();
-    // step n + 2 at row c, written out
+    // step n + 2 at row c (stored in the next pass)
     {
       const int c = a - 2 + ty;
       if (own_col && c >= s0 && c < s1) {
         NodeLoad<Q, S> L;
-        load_ring<Q, S, RING>(Ai, l1, x, c, t, c, base, L);
-        S v[Q];
-        update_values<Q, S, PLAIN, false>(Ai, x, c, L, st, v);
-        const int64_t o = (int64_t)c * nx + x;
-#pragma unroll
-        for (int j = 0; j < Q; ++j) {
-          if (NT) __builtin_nontemporal_store(v[j], dst + j * Ai.plane + o);
-          else dst[j * Ai.plane + o] = v[j];
-        }
+        load_ring<Q, S, RING, WIN>(Ai, l1, x, c, t, c, base, L);
+        update_values<Q, S, PLAIN, false>(Ai, x, c, L, st, w);
+        wo = (int64_t)c * nx + x;
       }
+    }
+  }
+  if (wo >= 0) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (NT) __builtin_nontemporal_store(w[j], dst + j * A.plane + wo);
+      else dst[j * A.plane + wo] = w[j];
     }
   }
   StatSlot pre{};

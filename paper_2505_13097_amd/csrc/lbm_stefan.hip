@@ -187,25 +187,25 @@ namespace {
 template <int Q, typename S>
 hipError_t launch_step2_t(const lbm_stefan_t *h, const StepArgs &A,
                           const Variant &v, bool plain) {
-  const int32_t nstrips = (int32_t)((h->p.nx + kStripOut - 1) / kStripOut);
+  const int32_t nstrips = (int32_t)((h->p.nx + v.bx - 5) / (v.bx - 4));
   const int64_t nseg = (h->p.ny + v.rows - 1) / v.rows;
-  dim3 grid((unsigned)(nstrips * nseg)), block(kStripWin, v.by);
-#define LAUNCH2(PL, NT, BY)                                          \
-  step2_kernel<Q, S, PL, NT, BY><<<grid, block, 0, h->stream>>>(A, nstrips, \
-                                                                v.rows)
-#define LAUNCH2_BY(PL, NT)               \
-  do {                                   \
-    if (v.by == 1) LAUNCH2(PL, NT, 1);   \
-    else LAUNCH2(PL, NT, 2);             \
+  dim3 grid((unsigned)(nstrips * nseg)), block(v.bx, v.by);
+#define LAUNCH2(PL, BY, WIN)                                            \
+  step2_kernel<Q, S, PL, true, BY, WIN><<<grid, block, 0, h->stream>>>( \
+      A, nstrips, v.rows)
+#define LAUNCH2_SHAPE(PL)                            \
+  do {                                               \
+    if (v.bx == 256) {                               \
+      if (v.by == 1) LAUNCH2(PL, 1, 256);            \
+      else LAUNCH2(PL, 2, 256);                      \
+    } else {                                         \
+      if (v.by == 2) LAUNCH2(PL, 2, 128);            \
+      else LAUNCH2(PL, 4, 128);                      \
+    }                                                \
   } while (0)
-  if (plain) {
-    if (v.nt) LAUNCH2_BY(true, true);
-    else LAUNCH2_BY(true, false);
-  } else {
-    if (v.nt) LAUNCH2_BY(false, true);
-    else LAUNCH2_BY(false, false);
-  }
-#undef LAUNCH2_BY
+  if (plain) LAUNCH2_SHAPE(true);
+  else LAUNCH2_SHAPE(false);
+#undef LAUNCH2_SHAPE
 #undef LAUNCH2
   return hipGetLastError();
 }
