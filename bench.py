@@ -1,18 +1,21 @@
 """Benchmark of the IREBM step on one MI355X.
 
 A step is one IREBM time step (collision, pull streaming, boundary
-closures, local Newton solve, source and update, per-tile Newton and flux
-statistics) over the whole lattice: one kernel launch.  Inputs are
-resident in HBM before the timed region.
+closures, local Newton solve, source and update, per-item Newton and flux
+statistics) over the whole lattice: one kernel launch, or half of one for
+the temporally blocked variants that advance two steps per launch.  Inputs
+are resident in HBM before the timed region.
 
 Default workload: the 8192 x 8192 D2Q9 cavity (FP32 populations, FP64
 per-node arithmetic), heated at x = 0, adiabatic y walls, Ste drawn from
 the seed, delta = 1.5 cells, tau = 0.6, Newton tol 1e-12.
 
 Prints one JSON line.  Roofline: algorithmic bytes per launch
-(2 q sizeof(population) per node: each population read once and written
-once) over the average launch time measured with HIP events on the stream
-the kernels run on.
+(2 q sizeof(population) per lattice update: each population read once and
+written once, times the updates one launch performs) over the average
+launch time measured with HIP events on the stream the kernels run on.  A
+two-step launch moves about half of those bytes (roofline.traffic, from
+the counter runs), so its achieved rate can exceed what HBM delivers.
 """
 import argparse
 import json
@@ -203,20 +206,27 @@ def time_adjoint(prob, interval, autotune=True):
     }
 
 
-SWEEP_LAUNCHES = 3
+SWEEP_STEPS = 4
+
+
+def steps_per_launch(variant_name):
+    """Time steps one launch of this variant advances (two for the
+    temporally blocked "/t2" variants)."""
+    return 2 if "/t2" in variant_name else 1
 
 
 def traffic_sweep(prob):
     """For counter runs: every kernel variant of the workload's lattice for
-    SWEEP_LAUNCHES launches each, in table order (the summary maps the
-    step-kernel dispatches to variants by that order)."""
+    SWEEP_STEPS steps each, in table order (the summary maps the step-kernel
+    dispatches to variants by that order: SWEEP_STEPS launches of a
+    one-step variant, SWEEP_STEPS / 2 of a two-step one)."""
     import torch
     from paper_2505_13097_amd import Stefan, variant_names
     g = Stefan(prob)
     names = variant_names(prob.q, prob.storage)
     for v in range(len(names)):
         g.set_variant(v)
-        g.step(SWEEP_LAUNCHES)
+        g.step(SWEEP_STEPS)
     torch.cuda.synchronize()
     g.close()
     return names
@@ -246,7 +256,10 @@ def summarize_profiles(run, args):
     bnames = variant_names(5, "f32")
     V, BV, BB = args.variant, args.batch_variant, args.batch_bpc
     vname, bvname = names[V], bnames[BV]
-    step_prefix = f"irebm::step_kernel<{prob.q}, float"
+    spl = steps_per_launch(vname)
+    step_prefix = (f"irebm::step2_kernel<{prob.q}, float" if spl == 2 else
+                   f"irebm::step_kernel<{prob.q}, float")
+    launches = args.steps // spl
 
     c = db("prof_all")
     trace = [(short(r[0]), r[1], r[2], r[3], r[4]) for r in c.execute(
@@ -257,8 +270,8 @@ def summarize_profiles(run, args):
                              "order by dispatch_id"):
         by[short(name)].append(d / 1000.0)          # ns -> us
     step_us = by[[k for k in by if k.startswith(step_prefix)][0]]
-    # the timed launches are the last args.steps of the step kernel
-    step_avg = sum(step_us[-args.steps:]) / args.steps
+    # the timed launches are the last ones of the step kernel
+    step_avg = sum(step_us[-launches:]) / launches
     bat = [k for k in by if k.startswith("batch_step_kernel<5, float") or
            k.startswith("batch_persistent_kernel<5, float")][0]
     bat_avg = sum(by[bat][-args.batch_steps:]) / args.batch_steps
@@ -274,22 +287,31 @@ def summarize_profiles(run, args):
     copy_f = max(v for k, v in F if "copyBuffer" in k)
     copy_w = max(v for k, v in W if "copyBuffer" in k)
     fs, ws = gib_kib / copy_f, gib_kib / copy_w
-    sf = [v for k, v in F if k.startswith(step_prefix)]
-    sw = [v for k, v in W if k.startswith(step_prefix)]
-    n = SWEEP_LAUNCHES
-    if len(sf) != n * len(names) or len(sw) != n * len(names):
-        raise SystemExit(f"expected {n * len(names)} step-kernel dispatches, "
+    def is_step(k):
+        return (k.startswith(f"irebm::step_kernel<{prob.q}, float") or
+                k.startswith(f"irebm::step2_kernel<{prob.q}, float"))
+    sf = [v for k, v in F if is_step(k)]
+    sw = [v for k, v in W if is_step(k)]
+    counts = [SWEEP_STEPS // steps_per_launch(nm) for nm in names]
+    if len(sf) != sum(counts) or len(sw) != sum(counts):
+        raise SystemExit(f"expected {sum(counts)} step-kernel dispatches, "
                          f"found {len(sf)} / {len(sw)}")
-    alg = prob.nodes * bytes_per_node(prob)
+    alg = prob.nodes * bytes_per_node(prob)      # per lattice update
     per_var = {}
-    for i, nm in enumerate(names):
-        fk = sum(sf[i * n:(i + 1) * n]) / n
-        wk = sum(sw[i * n:(i + 1) * n]) / n
+    o = 0
+    for nm, n in zip(names, counts):
+        fk = sum(sf[o:o + n]) / n
+        wk = sum(sw[o:o + n]) / n
+        o += n
         b = fk * 1024 * fs + wk * 1024 * ws
-        per_var[nm] = {"fetch_kib_per_dispatch": round(fk, 1),
+        per_var[nm] = {"steps_per_launch": steps_per_launch(nm),
+                       "fetch_kib_per_dispatch": round(fk, 1),
                        "write_kib_per_dispatch": round(wk, 1),
                        "bytes_per_launch": round(b),
-                       "ratio_to_algorithmic": round(b / alg, 4)}
+                       "bytes_per_lattice_update": round(
+                           b / prob.nodes / steps_per_launch(nm), 3),
+                       "ratio_to_algorithmic": round(
+                           b / (alg * steps_per_launch(nm)), 4)}
     bf = [v for k, v in F if k == bat][-1]
     bw = [v for k, v in W if k == bat][-1]
     bprobs = synth.batch_table(count=args.batch_count, nsteps=args.batch_steps)
@@ -316,10 +338,12 @@ def summarize_profiles(run, args):
              "|---|---|---|---|---|"]
     for r in trace[:16]:
         lines.append(f"| {r[0]} | {r[1]} | {r[2]:.0f} | {r[3]:.1f} | {r[4]:.2f} |")
-    lines += ["", f"The {args.steps} timed launches of the step kernel average "
-              f"{cav:.1f} us (bench.py measures the same launches with HIP events);",
-              f"algorithmic bytes per launch {alg / 1e9:.4f} GB ({prob.nodes:,} nodes"
-              f" x {bytes_per_node(prob)} B) -> {alg / (cav * 1e-6) / 1e9:.0f} GB/s.",
+    lines += ["", f"The {launches} timed launches of the step kernel "
+              f"({spl} step(s) each) average {cav:.1f} us (bench.py measures the "
+              "same launches with HIP events);",
+              f"algorithmic bytes per launch {alg * spl / 1e9:.4f} GB ({prob.nodes:,} "
+              f"nodes x {bytes_per_node(prob)} B x {spl} step(s)) -> "
+              f"{alg * spl / (cav * 1e-6) / 1e9:.0f} GB/s.",
               "", "HBM traffic per launch of every variant (two counter runs, one "
               "counter each):", "", "    " + pmc_cmd.format(
                   C="FETCH_SIZE", D="pmc_fetch", O="fetch"),
@@ -327,12 +351,15 @@ def summarize_profiles(run, args):
               f"Counter scale from a 1 GiB hipMemcpy D2D in the same runs: "
               f"FETCH_SIZE reads {copy_f:.0f} KiB (x{fs:.4f}), WRITE_SIZE "
               f"{copy_w:.0f} KiB (x{ws:.4f}).", "",
-              "| variant | FETCH KiB | WRITE KiB | bytes/launch | / algorithmic |",
-              "|---|---|---|---|---|"]
+              "| variant | steps/launch | FETCH KiB | WRITE KiB | bytes/launch | "
+              "B per lattice update | / algorithmic |",
+              "|---|---|---|---|---|---|---|"]
     for nm, r in per_var.items():
-        lines.append(f"| {nm} | {r['fetch_kib_per_dispatch']:.0f} | "
+        lines.append(f"| {nm} | {r['steps_per_launch']} | "
+                     f"{r['fetch_kib_per_dispatch']:.0f} | "
                      f"{r['write_kib_per_dispatch']:.0f} | "
                      f"{r['bytes_per_launch'] / 1e9:.4f} GB | "
+                     f"{r['bytes_per_lattice_update']:.2f} | "
                      f"{r['ratio_to_algorithmic']:.4f} |")
     t = per_var[vname]["bytes_per_launch"]
     lines += ["", f"Timed variant {vname}: {t / 1e9:.4f} GB per launch, "
@@ -366,7 +393,7 @@ def summarize_profiles(run, args):
              "| kernel | calls | total us | average us |", "|---|---|---|---|"] +
             [f"| {r[0]} | {r[1]} | {r[2]:.0f} | {r[3]:.2f} |" for r in adj] + [""]))
     with open(TRAFFIC_JSON, "w") as f:
-        json.dump({"kernel": step_prefix + ", ...>", "workload": prob.name,
+        json.dump({"kernel": "step_kernel / step2_kernel", "workload": prob.name,
                    "sources_sha256": src, "fetch_scale": fs, "write_scale": ws,
                    "algorithmic_bytes_per_launch": alg, "variants": per_var,
                    "source": "profiles/" + fn}, f, indent=1)
@@ -409,7 +436,7 @@ def main():
                     help="also run a plain 1 GiB device copy (counter scale)")
     ap.add_argument("--traffic-sweep", action="store_true",
                     help="counter runs: 1 GiB copy, every variant for "
-                         f"{SWEEP_LAUNCHES} launches, the batched form; no timing")
+                         f"{SWEEP_STEPS} steps, the batched form; no timing")
     ap.add_argument("--summarize-profiles", metavar="RUN_DIR",
                     help="write profiles/ from the rocprofv3 output of a run "
                          "(CPU only; --variant, --batch-variant, --batch-bpc, "
@@ -442,7 +469,7 @@ def main():
                      graph_steps=0, variant=args.batch_variant,
                      bpc=args.batch_bpc)
         print(json.dumps({"traffic_sweep": prob.name, "variants": names,
-                          "launches_each": SWEEP_LAUNCHES}), flush=True)
+                          "steps_each": SWEEP_STEPS}), flush=True)
         return
     print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D2Q{prob.q} "
           f"steps {args.steps} warmup {args.warmup}", file=sys.stderr,
@@ -453,11 +480,16 @@ def main():
           flush=True)
     ms_per_step = r["wall_s"] * 1e3 / args.steps
     mlups = prob.nodes * args.steps / r["wall_s"] / 1e6
-    launch_ms = r["gpu_ms"] / args.steps
-    bpn = bytes_per_node(prob)
-    achieved = prob.nodes * bpn / (launch_ms * 1e-3) / 1e9
     v = r["variant"] if r["variant"] >= 0 else (0 if prob.q == 3 else 3)
     vname = variant_names(prob.q, prob.storage)[v]
+    spl = steps_per_launch(vname)
+    if args.steps % spl:
+        raise SystemExit("--steps must be even for a two-step variant")
+    launch_ms = r["gpu_ms"] / (args.steps // spl)
+    bpn = bytes_per_node(prob)
+    # algorithmic bytes per launch: 2 q s per lattice update, times the
+    # updates one launch performs
+    achieved = prob.nodes * bpn * spl / (launch_ms * 1e-3) / 1e9
 
     if args.copy_probe:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -500,8 +532,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": measured_traffic(prob.name, vname),
-            "kernel": "step_kernel",
-            "bytes_per_node": bpn,
+            "kernel": "step2_kernel" if spl == 2 else "step_kernel",
+            "steps_per_launch": spl,
+            "bytes_per_lattice_update": bpn,
             "avg_launch_us": round(launch_ms * 1e3, 2),
         },
         "newton": {

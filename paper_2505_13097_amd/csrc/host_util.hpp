@@ -37,10 +37,10 @@ inline const Variant *variants(int q, int *n) {
       {64, 4, 2, 0, 0, 4}, {64, 4, 1, 1, 0, 4},  {64, 4, 2, 1, 1, 4},
       {128, 2, 2, 1, 0, 4}, {64, 4, 2, 1, 0, 16}, {64, 1, 1, 0, 0, 1},
       {64, 2, 1, 0, 0, 1},
-      {256, 2, 1, 1, 0, 64, 1},  {256, 2, 1, 1, 0, 128, 1},
-      {256, 1, 1, 1, 0, 64, 1},  {128, 2, 1, 1, 0, 32, 1},
-      {128, 2, 1, 1, 0, 64, 1},  {128, 2, 1, 1, 0, 128, 1},
-      {128, 4, 1, 1, 0, 64, 1},  {128, 4, 1, 1, 0, 128, 1}};
+      {256, 2, 1, 1, 0, 32, 1},  {256, 2, 1, 1, 0, 64, 1},
+      {128, 2, 1, 1, 0, 16, 1},  {128, 2, 1, 1, 0, 24, 1},
+      {128, 2, 1, 1, 0, 32, 1},  {128, 2, 1, 1, 0, 64, 1},
+      {128, 4, 1, 1, 0, 32, 1},  {128, 4, 1, 1, 0, 64, 1}};
   if (q == 3) {
     *n = (int)(sizeof(v1) / sizeof(Variant));
     return v1;

@@ -94,7 +94,8 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
   const int x0 = tx * TW, y0 = ty * by;
   const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
-  const int y = y0 + (int)threadIdx.y;
+  // a wave lies in one row of the tile (bx is a multiple of 64)
+  const int y = y0 + __builtin_amdgcn_readfirstlane((int)threadIdx.y);
   if (fast) {
     NodeLoad<Q, S> L[NPT];
 #pragma unroll
@@ -196,45 +197,73 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
 // for both to complete.
 
 // NodeLoad of node (x, y) (lattice coordinates) from a ring of rows in
-// LDS: column t of the window, ring slot of row r at (r - base) % RING
-template <int Q, typename S, int RING, int WIN>
+// LDS: column t of the window, ring slot of row r at (r - base) % RING.
+// INNER: every pull source is a lattice node and nothing leaves (no masks).
+template <int Q, typename S, int RING, int WIN, bool INNER>
 __device__ __forceinline__ void load_ring(const StepArgs &A,
                                           const S (*ring)[Q][WIN],
                                           int x, int y, int t, int r, int base,
                                           NodeLoad<Q, S> &L) {
-  node_masks<Q>(A, x, y, L.known, L.out);
-  const int so = (r - base) % RING;
+  if (INNER) {
+    L.known = (1u << Q) - 1u;
+    L.out = 0u;
+  } else {
+    node_masks<Q>(A, x, y, L.known, L.out);
+  }
+  const unsigned so = (unsigned)(r - base) % RING;
 #pragma unroll
   for (int j = 0; j < Q; ++j) L.own[j] = ring[so][j][t];
   L.pull[0] = L.own[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const int ex = cx<Q>(i), ey = cy<Q>(i);
-    const S v = ring[(r - ey - base) % RING][i][t - ex];
-    L.pull[i] = (L.known >> i & 1u) ? v : (S)0;
+    const S v = ring[(unsigned)(r - ey - base) % RING][i][t - ex];
+    L.pull[i] = (INNER || (L.known >> i & 1u)) ? v : (S)0;
+  }
+}
+
+// the update of node (x, y) of a window from a ring: the interior form
+// (no masks, no closures) when every neighbour is a lattice node
+template <int Q, typename S, bool PLAIN, int RING, int WIN>
+__device__ __forceinline__ void ring_update(const StepArgs &A,
+                                            const S (*ring)[Q][WIN], int x,
+                                            int y, int t, int r, int base,
+                                            bool inner, NodeStats &st, S v[Q]) {
+  NodeLoad<Q, S> L;
+  if (inner) {
+    load_ring<Q, S, RING, WIN, true>(A, ring, x, y, t, r, base, L);
+    update_values<Q, S, PLAIN, true>(A, x, y, L, st, v);
+  } else {
+    load_ring<Q, S, RING, WIN, false>(A, ring, x, y, t, r, base, L);
+    update_values<Q, S, PLAIN, false>(A, x, y, L, st, v);
   }
 }
 
 template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
-__global__ __launch_bounds__(WIN * BY) void step2_kernel(
+__global__ __launch_bounds__(WIN * BY) __attribute__((amdgpu_waves_per_eu(4))) void step2_kernel(
     StepArgs A, int32_t nstrips, int32_t seg_rows) {
   constexpr int RING = BY + 2;
   __shared__ S l0[RING][Q][WIN];
   __shared__ S l1[RING][Q][WIN];
-  const int t = (int)threadIdx.x, ty = (int)threadIdx.y;
+  // a wave lies in one row of threads (WIN is a multiple of 64)
+  const int t = (int)threadIdx.x;
+  const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
   const int strip = (int)blockIdx.x % nstrips;
   const int seg = (int)blockIdx.x / nstrips;
   const int s0 = seg * seg_rows;
   const int s1 = min(s0 + seg_rows, A.ny);       // output rows [s0, s1)
   const int x = strip * (WIN - 4) - 2 + t;        // window column
   const int nx = A.nx, ny = A.ny;
+  const bool px = A.periodic_x != 0, py = A.periodic_y != 0;
   // lattice column of this window column (wrapped on a periodic axis)
   int gx = x;
   bool col = x >= 0 && x < nx;
-  if (!col && A.periodic_x) {
+  if (!col && px) {
     gx = (x % nx + nx) % nx;
     col = true;
   }
+  // every neighbour of the node at window column t is a lattice node along x
+  const bool inner_x = px || (x >= 1 && x <= nx - 2);
   const bool own_col = t >= 2 && t < WIN - 2 && x >= 0 && x < nx;
   // ring slots: (row - base) % RING with base a multiple of RING below
   // every row touched (rows >= s0 - 4)
@@ -244,7 +273,7 @@ __global__ __launch_bounds__(WIN * BY) void step2_kernel(
   // lattice row of row r (wrapped on a periodic axis), or -1
   auto lrow = [&](int r) -> int {
     if (r >= 0 && r < ny) return r;
-    return A.periodic_y ? (r % ny + ny) % ny : -1;
+    return py ? (r % ny + ny) % ny : -1;
   };
   const int iters = (s1 - s0 + 4 + BY - 1) / BY;
   S pf[Q];
@@ -265,7 +294,8 @@ __global__ __launch_bounds__(WIN * BY) void step2_kernel(
     const int a = s0 - 2 + i * BY;
     // rows a .. a + BY - 1 of step n into the first ring
 #pragma unroll
-    for (int j = 0; j < Q; ++j) l0[(a + ty - base) % RING][j][t] = pf[j];
+    for (int j = 0; j < Q; ++j)
+      l0[(unsigned)(a + ty - base) % RING][j][t] = pf[j];
     if (wo >= 0) {
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
@@ -286,11 +316,11 @@ __global__ __launch_bounds__(WIN * BY) void step2_kernel(
       const int b = a - 1 + ty;
       const int gb = lrow(b);
       if (t >= 1 && t < WIN - 1 && col && gb >= 0 && b >= s0 - 1 && b <= s1) {
-        NodeLoad<Q, S> L;
-        load_ring<Q, S, RING, WIN>(Ai, l0, gx, gb, t, b, base, L);
         S v[Q];
         NodeStats one;
-        update_values<Q, S, PLAIN, false>(Ai, gx, gb, L, one, v);
+        const bool inner = inner_x && (py || (gb >= 1 && gb <= ny - 2));
+        ring_update<Q, S, PLAIN, RING, WIN>(Ai, l0, gx, gb, t, b, base, inner,
+                                            one, v);
         if (own_col && b >= s0 && b < s1) {
           st.max_it = max(st.max_it, one.max_it);
           st.nonconv += one.nonconv;
@@ -299,7 +329,7 @@ __global__ __launch_bounds__(WIN * BY) void step2_kernel(
           st.flux_out += one.flux_out;
         }
 #pragma unroll
-        for (int j = 0; j < Q; ++j) l1[(b - base) % RING][j][t] = v[j];
+        for (int j = 0; j < Q; ++j) l1[(unsigned)(b - base) % RING][j][t] = v[j];
       }
     }
     __syncthreads();
@@ -307,9 +337,9 @@ __global__ __launch_bounds__(WIN * BY) void step2_kernel(
     {
       const int c = a - 2 + ty;
       if (own_col && c >= s0 && c < s1) {
-        NodeLoad<Q, S> L;
-        load_ring<Q, S, RING, WIN>(Ai, l1, x, c, t, c, base, L);
-        update_values<Q, S, PLAIN, false>(Ai, x, c, L, st, w);
+        const bool inner = inner_x && (py || (c >= 1 && c <= ny - 2));
+        ring_update<Q, S, PLAIN, RING, WIN>(Ai, l1, x, c, t, c, base, inner,
+                                            st, w);
         wo = (int64_t)c * nx + x;
       }
     }

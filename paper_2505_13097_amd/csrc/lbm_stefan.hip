@@ -196,8 +196,7 @@ hipError_t launch_step2_t(const lbm_stefan_t *h, const StepArgs &A,
 #define LAUNCH2_SHAPE(PL)                            \
   do {                                               \
     if (v.bx == 256) {                               \
-      if (v.by == 1) LAUNCH2(PL, 1, 256);            \
-      else LAUNCH2(PL, 2, 256);                      \
+      LAUNCH2(PL, 2, 256);                           \
     } else {                                         \
       if (v.by == 2) LAUNCH2(PL, 2, 128);            \
       else LAUNCH2(PL, 4, 128);                      \
