@@ -239,17 +239,25 @@ __device__ __forceinline__ void ring_update(const StepArgs &A,
   }
 }
 
+// Blocks are numbered strip-fastest within a segment of rows, and each
+// XCD takes one contiguous chunk of that order, so neighbouring strips run
+// on the same XCD and share the halo lines (and the cache lines that
+// straddle two strips) in its L2.
 template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
-__global__ __launch_bounds__(WIN * BY) __attribute__((amdgpu_waves_per_eu(4))) void step2_kernel(
-    StepArgs A, int32_t nstrips, int32_t seg_rows) {
+__global__ __launch_bounds__(WIN * BY) __attribute__((amdgpu_waves_per_eu(4)))
+void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
+                  int32_t nitems) {
   constexpr int RING = BY + 2;
   __shared__ S l0[RING][Q][WIN];
   __shared__ S l1[RING][Q][WIN];
+  const int per_xcd = (nitems + 7) >> 3;
+  const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (item >= nitems) return;
   // a wave lies in one row of threads (WIN is a multiple of 64)
   const int t = (int)threadIdx.x;
   const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-  const int strip = (int)blockIdx.x % nstrips;
-  const int seg = (int)blockIdx.x / nstrips;
+  const int strip = item % nstrips;
+  const int seg = item / nstrips;
   const int s0 = seg * seg_rows;
   const int s1 = min(s0 + seg_rows, A.ny);       // output rows [s0, s1)
   const int x = strip * (WIN - 4) - 2 + t;        // window column
@@ -352,8 +360,8 @@ __global__ __launch_bounds__(WIN * BY) __attribute__((amdgpu_waves_per_eu(4))) v
     }
   }
   StatSlot pre{};
-  if (t == 0 && ty == 0) pre = A.slots[blockIdx.x];
-  block_stats_to_slot<false>(st, false, pre, A.slots + blockIdx.x);
+  if (t == 0 && ty == 0) pre = A.slots[item];
+  block_stats_to_slot<false>(st, false, pre, A.slots + item);
 }
 
 // ---------------------------------------------------------------------

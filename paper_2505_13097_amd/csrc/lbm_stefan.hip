@@ -189,10 +189,11 @@ hipError_t launch_step2_t(const lbm_stefan_t *h, const StepArgs &A,
                           const Variant &v, bool plain) {
   const int32_t nstrips = (int32_t)((h->p.nx + v.bx - 5) / (v.bx - 4));
   const int64_t nseg = (h->p.ny + v.rows - 1) / v.rows;
-  dim3 grid((unsigned)(nstrips * nseg)), block(v.bx, v.by);
+  const int32_t nitems = (int32_t)(nstrips * nseg);
+  dim3 grid((unsigned)(8 * ((nitems + 7) / 8))), block(v.bx, v.by);
 #define LAUNCH2(PL, BY, WIN)                                            \
   step2_kernel<Q, S, PL, true, BY, WIN><<<grid, block, 0, h->stream>>>( \
-      A, nstrips, v.rows)
+      A, nstrips, v.rows, nitems)
 #define LAUNCH2_SHAPE(PL)                            \
   do {                                               \
     if (v.bx == 256) {                               \
