@@ -126,7 +126,7 @@ __device__ __forceinline__ void local_reverse(const AdjArgs &G, int x, int y,
   double qb[Q];
   double tpb = 0.0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) tpb += A.wtau[i] * ab[i];
+  for (int i = 0; i < Q; ++i) tpb += A.wtau[wclass<Q>(i)] * ab[i];
   double sb = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {

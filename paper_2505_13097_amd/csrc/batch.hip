@@ -73,6 +73,28 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(
                                            reverse ? nitems - 1 - t : t, parity);
 }
 
+// two steps (or one) per launch: one block per item of the two-step
+// tiling (a strip of one segment of one instance), XCD-contiguous chunks
+template <int Q, typename S, bool PLAIN, int BY, int WIN>
+__global__ __launch_bounds__(WIN * BY)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 4 : 1)))
+void batch_step2_kernel(const StepArgs *__restrict__ descs,
+                        const int2 *__restrict__ items, int32_t nitems,
+                        int32_t parity, int32_t two) {
+  const int per_xcd = (nitems + 7) >> 3;
+  const int t = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (t >= nitems) return;
+  const int2 e = items[t];
+  const int inst = __builtin_amdgcn_readfirstlane(e.x);
+  const int item = __builtin_amdgcn_readfirstlane(e.y);
+  const StepArgs &A = descs[inst];
+  const S *src = (const S *)(parity ? A.dst : A.src);
+  S *dst = (S *)(parity ? A.src : A.dst);
+  step2_body<Q, S, PLAIN, true, BY, WIN>(A, src, dst, item % A.tiles_x,
+                                         item / A.tiles_x, A.group, two != 0,
+                                         A.slots + item);
+}
+
 }  // namespace
 
 struct lbm_stefan_batch {
@@ -142,7 +164,6 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   const Variant *v = variants(ps[0].q, &nv);
   L.max_items = 0;
   for (int i = 0; i < nv; ++i) {
-    if (v[i].tb) continue;
     int64_t t = 0;
     for (int k = 0; k < count; ++k) t += items_for(v[i], ps[k].nx, ps[k].ny);
     L.max_items = std::max(L.max_items, t);
@@ -232,10 +253,32 @@ int build_schedule(lbm_stefan_batch_t *b) {
 
 template <int Q, typename S>
 hipError_t launch_batch_t(const lbm_stefan_batch_t *b, hipStream_t stream,
-                          int parity) {
+                          int parity, bool two) {
   int nv;
   const Variant &v = variants(Q, &nv)[b->variant];
   const int64_t chunk = (b->nitems + 7) / 8;
+  if (v.tb) {
+    if constexpr (Q == 3) {
+      return hipErrorInvalidValue;
+    } else {
+      dim3 grid((unsigned)(8 * std::max<int64_t>(chunk, 1))), block(v.bx, v.by);
+      const int32_t nt = (int32_t)b->nitems, tw = two ? 1 : 0;
+#define B2LAUNCH(PL, BY, WIN)                                              \
+  batch_step2_kernel<Q, S, PL, BY, WIN><<<grid, block, 0, stream>>>(     \
+      b->descs, b->items, nt, parity, tw)
+#define B2LAUNCH_SHAPE(PL)                 \
+  do {                                     \
+    if (v.bx == 256) B2LAUNCH(PL, 2, 256); \
+    else if (v.by == 2) B2LAUNCH(PL, 2, 128); \
+    else B2LAUNCH(PL, 4, 128);             \
+  } while (0)
+      if (b->plain) B2LAUNCH_SHAPE(true);
+      else B2LAUNCH_SHAPE(false);
+#undef B2LAUNCH_SHAPE
+#undef B2LAUNCH
+      return hipGetLastError();
+    }
+  }
   int64_t g8 = chunk;  // one block per item
   if (b->blocks_per_cu > 0)
     g8 = std::min<int64_t>(((int64_t)b->cus * b->blocks_per_cu + 7) / 8, chunk);
@@ -270,23 +313,31 @@ hipError_t launch_batch_t(const lbm_stefan_batch_t *b, hipStream_t stream,
   return hipGetLastError();
 }
 
+// one launch from buffer `parity`: one step, or two under a two-step
+// variant (one if two = false)
 hipError_t launch_batch(const lbm_stefan_batch_t *b, hipStream_t stream,
-                        int parity) {
+                        int parity, bool two = true) {
   return dispatch_qs(b->q, b->storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
-    return launch_batch_t<Q, S>(b, stream, parity);
+    return launch_batch_t<Q, S>(b, stream, parity, two);
   });
 }
 
-// graph of graph_steps launches starting at parity `par` (even length, so
-// it ends on the same parity)
+// time steps one launch advances under the current variant
+int steps_per_launch(const lbm_stefan_batch_t *b) {
+  int nv;
+  return variants(b->q, &nv)[b->variant].tb ? 2 : 1;
+}
+
+// graph of the launches of graph_steps steps starting at parity `par`
 int ensure_graph(lbm_stefan_batch_t *b, int par) {
   if (b->graph[par]) return LBM_STEFAN_OK;
   if (!b->cap_stream)
     BCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   BCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
-  for (int s = 0; s < b->graph_steps && le == hipSuccess; ++s)
+  const int launches = b->graph_steps / steps_per_launch(b);
+  for (int s = 0; s < launches && le == hipSuccess; ++s)
     le = launch_batch(b, b->cap_stream, par ^ (s & 1));
   hipGraph_t g = nullptr;
   const hipError_t ee = hipStreamEndCapture(b->cap_stream, &g);
@@ -419,12 +470,9 @@ int lbm_stefan_batch_set_schedule(lbm_stefan_batch_t *b, int32_t variant,
                                   int32_t blocks_per_cu, int32_t graph_steps) {
   if (!b) return bfail(nullptr, LBM_STEFAN_EINVAL, "batch is NULL");
   int nv;
-  const Variant *vt = variants(b->q, &nv);
+  variants(b->q, &nv);
   if (variant < -1 || variant >= nv)
     return bfail(b, LBM_STEFAN_EINVAL, "unknown kernel variant");
-  if (variant >= 0 && vt[variant].tb)
-    return bfail(b, LBM_STEFAN_EINVAL,
-                 "two-step variants are for single lattices only");
   if (blocks_per_cu < 0 || blocks_per_cu > 32)
     return bfail(b, LBM_STEFAN_EINVAL, "blocks_per_cu must be in 0..32");
   if (graph_steps < 0 || graph_steps % 2 || graph_steps > 100000)
@@ -448,6 +496,7 @@ int lbm_stefan_batch_step(lbm_stefan_batch_t *b, int64_t nsteps) {
   if (!b) return bfail(nullptr, LBM_STEFAN_EINVAL, "batch is NULL");
   if (nsteps < 0) return bfail(b, LBM_STEFAN_EINVAL, "nsteps < 0");
   DeviceGuard g(b->device);
+  const int spl = steps_per_launch(b);
   int64_t left = nsteps;
   if (b->graph_steps > 0) {
     while (left >= b->graph_steps) {
@@ -456,12 +505,13 @@ int lbm_stefan_batch_step(lbm_stefan_batch_t *b, int64_t nsteps) {
       BCHK(b, hipGraphLaunch(b->graph[b->cur], b->stream));
       left -= b->graph_steps;
       b->steps += b->graph_steps;
+      b->cur ^= (b->graph_steps / spl) & 1;
     }
   }
-  for (; left > 0; --left) {
-    BCHK(b, launch_batch(b, b->stream, b->cur));
+  for (; left > 0; left -= std::min<int64_t>(left, spl)) {
+    BCHK(b, launch_batch(b, b->stream, b->cur, left >= 2));
     b->cur ^= 1;
-    b->steps++;
+    b->steps += std::min<int64_t>(left, spl);
   }
   return LBM_STEFAN_OK;
 }
@@ -599,15 +649,19 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
   int rc = LBM_STEFAN_OK;
   hipError_t err = hipSuccess;
   for (int v = 0; v < nv && rc == LBM_STEFAN_OK && err == hipSuccess; ++v) {
-    if (vt[v].tb) continue;  // single lattices only
     if (v != b->variant) {
       b->variant = v;
       rc = build_schedule(b);
     }
+    // a two-step launch covers two steps; the persistent grid is for
+    // one-step variants only
+    const int spl = vt[v].tb ? 2 : 1;
+    const int launches = (steps + spl - 1) / spl;
     for (int bpc : bpcs) {
       if (rc != LBM_STEFAN_OK || err != hipSuccess) break;
+      if (vt[v].tb && bpc > 0) break;
       b->blocks_per_cu = bpc;
-      for (int s = 0; s < steps + 2 && err == hipSuccess; ++s) {
+      for (int s = 0; s < launches + 2 && err == hipSuccess; ++s) {
         if (s == 2) err = hipEventRecord(e0, b->stream);
         if (err == hipSuccess) err = launch_batch(b, b->stream, b->cur);
         b->cur ^= 1;
@@ -616,6 +670,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.0f;
       if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      ms /= (float)(launches * spl);
       if (err == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
         best_ms = ms;
         best_v = v;
@@ -646,7 +701,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
   BCHK(b, hipStreamSynchronize(b->stream));
   if (best_variant) *best_variant = best_v;
   if (best_blocks_per_cu) *best_blocks_per_cu = best_bpc;
-  if (best_ms_per_step) *best_ms_per_step = best_ms / steps;
+  if (best_ms_per_step) *best_ms_per_step = best_ms;
   return LBM_STEFAN_OK;
 }
 

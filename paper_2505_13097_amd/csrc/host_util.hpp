@@ -65,9 +65,16 @@ inline int64_t items_for(const Variant &v, int64_t nx, int64_t ny) {
   return tiles_x_for(v, nx) * ((tiles_y_for(v, ny) + v.rows - 1) / v.rows);
 }
 // tile grid and work items of A for variant v
+// (two-step variants: tiles_x strips of bx - 4 columns, tiles_y segments
+// of `rows` rows, group = rows)
 inline void set_tiling(StepArgs *A, const Variant &v) {
-  A->tiles_x = (int32_t)tiles_x_for(v, A->nx);
-  A->tiles_y = (int32_t)tiles_y_for(v, A->ny);
+  if (v.tb) {
+    A->tiles_x = (A->nx + v.bx - 5) / (v.bx - 4);
+    A->tiles_y = (A->ny + v.rows - 1) / v.rows;
+  } else {
+    A->tiles_x = (int32_t)tiles_x_for(v, A->nx);
+    A->tiles_y = (int32_t)tiles_y_for(v, A->ny);
+  }
   A->group = v.rows;
   A->nitems = (int32_t)items_for(v, A->nx, A->ny);
   A->per_xcd = (A->nitems + 7) / 8;

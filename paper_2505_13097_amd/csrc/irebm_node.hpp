@@ -41,6 +41,12 @@ __host__ __device__ constexpr double wt(int i) {
        : Q == 5 ? (i == 0 ? 1.0 / 3.0 : 1.0 / 6.0)
                 : (i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0));
 }
+// the first direction with the weight of direction i: equal weights give
+// equal w_i/tau and w_i/Ste, so kernels read one value per weight class
+template <int Q>
+__host__ __device__ constexpr int wclass(int i) {
+  return i == 0 ? 0 : (Q == 9 && i >= 5 ? 5 : 1);
+}
 template <int Q>
 __host__ __device__ constexpr int opp(int i) {
   return Q == 3 ? (i == 0 ? 0 : 3 - i)
@@ -433,7 +439,8 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
       st.max_it = it > st.max_it ? it : st.max_it;
       st.nonconv += (one || A.max_it >= 2) ? 0 : 1;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v[i] = (S)(A.a * q[i] + A.wtau[i] * m0);
+      for (int i = 0; i < Q; ++i)
+        v[i] = (S)(A.a * q[i] + A.wtau[wclass<Q>(i)] * m0);
       return;
     }
   }
@@ -447,11 +454,12 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   double tsum = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    f[i] = q[i] + A.wste[i] * dphi_s;
+    f[i] = q[i] + A.wste[wclass<Q>(i)] * dphi_s;
     tsum += f[i];
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v[i] = (S)(A.a * f[i] + A.wtau[i] * tsum);
+  for (int i = 0; i < Q; ++i)
+    v[i] = (S)(A.a * f[i] + A.wtau[wclass<Q>(i)] * tsum);
   const double res = fabs(tn + pnew * A.inv_ste - (m0 + pth * A.inv_ste));
   st.max_it = it > st.max_it ? it : st.max_it;
   st.nonconv += conv ? 0 : 1;

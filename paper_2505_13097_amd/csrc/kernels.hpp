@@ -239,29 +239,26 @@ __device__ __forceinline__ void ring_update(const StepArgs &A,
   }
 }
 
-// Blocks are numbered strip-fastest within a segment of rows, and each
-// XCD takes one contiguous chunk of that order, so neighbouring strips run
-// on the same XCD and share the halo lines (and the cache lines that
-// straddle two strips) in its L2.
+// One block: strip `strip` of segment `seg` (seg_rows rows) of the lattice
+// described by A, from state src to state dst, two steps (two = true) or
+// one (the rows of step n + 1 are then written out directly).
 template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
-__global__ __launch_bounds__(WIN * BY) __attribute__((amdgpu_waves_per_eu(4)))
-void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
-                  int32_t nitems) {
+__device__ __forceinline__ void step2_body(const StepArgs &A,
+                                           const S *__restrict__ src,
+                                           S *__restrict__ dst, int strip,
+                                           int seg, int seg_rows, bool two,
+                                           StatSlot *slot) {
   constexpr int RING = BY + 2;
   __shared__ S l0[RING][Q][WIN];
   __shared__ S l1[RING][Q][WIN];
-  const int per_xcd = (nitems + 7) >> 3;
-  const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
-  if (item >= nitems) return;
   // a wave lies in one row of threads (WIN is a multiple of 64)
   const int t = (int)threadIdx.x;
   const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-  const int strip = item % nstrips;
-  const int seg = item / nstrips;
   const int s0 = seg * seg_rows;
   const int s1 = min(s0 + seg_rows, A.ny);       // output rows [s0, s1)
   const int x = strip * (WIN - 4) - 2 + t;        // window column
   const int nx = A.nx, ny = A.ny;
+  const int64_t P = A.plane;
   const bool px = A.periodic_x != 0, py = A.periodic_y != 0;
   // lattice column of this window column (wrapped on a periodic axis)
   int gx = x;
@@ -276,8 +273,6 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
   // ring slots: (row - base) % RING with base a multiple of RING below
   // every row touched (rows >= s0 - 4)
   const int base = s0 - 12;
-  const S *src = (const S *)A.src;
-  S *dst = (S *)A.dst;
   // lattice row of row r (wrapped on a periodic axis), or -1
   auto lrow = [&](int r) -> int {
     if (r >= 0 && r < ny) return r;
@@ -289,9 +284,9 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
     const int gr = lrow(s0 - 2 + ty);
     const int64_t o = (int64_t)(gr < 0 ? 0 : gr) * nx + (col ? gx : 0);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) pf[j] = src[j * A.plane + o];
+    for (int j = 0; j < Q; ++j) pf[j] = src[j * P + o];
   }
-  S w[Q];            // a row of step n + 2 waiting to be stored
+  S w[Q];            // a row of output waiting to be stored
   int64_t wo = -1;   // its offset, or -1
   NodeStats st;
   for (int i = 0; i < iters; ++i) {
@@ -307,8 +302,8 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
     if (wo >= 0) {
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        if (NT) __builtin_nontemporal_store(w[j], dst + j * Ai.plane + wo);
-        else dst[j * Ai.plane + wo] = w[j];
+        if (NT) __builtin_nontemporal_store(w[j], dst + j * P + wo);
+        else dst[j * P + wo] = w[j];
       }
       wo = -1;
     }
@@ -316,11 +311,20 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
       const int gr = lrow(a + BY + ty);
       const int64_t o = (int64_t)(gr < 0 ? 0 : gr) * nx + (col ? gx : 0);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) pf[j] = src[j * Ai.plane + o];
+      for (int j = 0; j < Q; ++j) pf[j] = src[j * P + o];
     }
     __syncthreads();
-    // step n + 1 at row b (needed rows s0 - 1 .. s1)
-    {
+    // step n + 1 at row b (needed rows s0 - 1 .. s1; for one step only
+    // the block's own rows, stored in the next pass)
+    if (!two) {
+      const int b = a - 1 + ty;
+      if (own_col && b >= s0 && b < s1) {
+        const bool inner = inner_x && (py || (b >= 1 && b <= ny - 2));
+        ring_update<Q, S, PLAIN, RING, WIN>(Ai, l0, x, b, t, b, base, inner,
+                                            st, w);
+        wo = (int64_t)b * nx + x;
+      }
+    } else {
       const int b = a - 1 + ty;
       const int gb = lrow(b);
       if (t >= 1 && t < WIN - 1 && col && gb >= 0 && b >= s0 - 1 && b <= s1) {
@@ -342,7 +346,7 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
     }
     __syncthreads();
     // step n + 2 at row c (stored in the next pass)
-    {
+    if (two) {
       const int c = a - 2 + ty;
       if (own_col && c >= s0 && c < s1) {
         const bool inner = inner_x && (py || (c >= 1 && c <= ny - 2));
@@ -355,13 +359,32 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
   if (wo >= 0) {
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      if (NT) __builtin_nontemporal_store(w[j], dst + j * A.plane + wo);
-      else dst[j * A.plane + wo] = w[j];
+      if (NT) __builtin_nontemporal_store(w[j], dst + j * P + wo);
+      else dst[j * P + wo] = w[j];
     }
   }
   StatSlot pre{};
-  if (t == 0 && ty == 0) pre = A.slots[item];
-  block_stats_to_slot<false>(st, false, pre, A.slots + item);
+  if (t == 0 && ty == 0) pre = *slot;
+  block_stats_to_slot<false>(st, false, pre, slot);
+}
+
+// Blocks are numbered strip-fastest within a segment of rows, and each
+// XCD takes one contiguous chunk of that order, so neighbouring strips run
+// on the same XCD and share the halo lines (and the cache lines that
+// straddle two strips) in its L2.
+template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
+// FP32 states: at most 128 VGPRs (4 waves per SIMD); FP64 rings fill the
+// LDS first
+__global__ __launch_bounds__(WIN * BY)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 4 : 1)))
+void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
+                  int32_t nitems, int32_t two) {
+  const int per_xcd = (nitems + 7) >> 3;
+  const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (item >= nitems) return;
+  step2_body<Q, S, PLAIN, NT, BY, WIN>(A, (const S *)A.src, (S *)A.dst,
+                                       item % nstrips, item / nstrips,
+                                       seg_rows, two != 0, A.slots + item);
 }
 
 // ---------------------------------------------------------------------

@@ -186,14 +186,14 @@ namespace {
 // two steps src -> dst in one launch (variant v has tb set)
 template <int Q, typename S>
 hipError_t launch_step2_t(const lbm_stefan_t *h, const StepArgs &A,
-                          const Variant &v, bool plain) {
+                          const Variant &v, bool plain, bool two) {
   const int32_t nstrips = (int32_t)((h->p.nx + v.bx - 5) / (v.bx - 4));
   const int64_t nseg = (h->p.ny + v.rows - 1) / v.rows;
   const int32_t nitems = (int32_t)(nstrips * nseg);
   dim3 grid((unsigned)(8 * ((nitems + 7) / 8))), block(v.bx, v.by);
 #define LAUNCH2(PL, BY, WIN)                                            \
   step2_kernel<Q, S, PL, true, BY, WIN><<<grid, block, 0, h->stream>>>( \
-      A, nstrips, v.rows, nitems)
+      A, nstrips, v.rows, nitems, two ? 1 : 0)
 #define LAUNCH2_SHAPE(PL)                            \
   do {                                               \
     if (v.bx == 256) {                               \
@@ -218,7 +218,7 @@ bool irebm::two_step_variant(const lbm_stefan_t *h) {
 }
 
 hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
-                               void *dst) {
+                               void *dst, bool two) {
   StepArgs A;
   fill_step_args(h, &A);
   A.src = src;
@@ -227,16 +227,19 @@ hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
   const Variant &v = variants(h->p.q, &nv)[h->variant];
   const bool plain = h->p.newton_mode == LBM_NEWTON_PLAIN;
   if (h->p.q == 5)
-    return h->p.storage == LBM_STORE_F32 ? launch_step2_t<5, float>(h, A, v, plain)
-                                         : launch_step2_t<5, double>(h, A, v, plain);
-  return h->p.storage == LBM_STORE_F32 ? launch_step2_t<9, float>(h, A, v, plain)
-                                       : launch_step2_t<9, double>(h, A, v, plain);
+    return h->p.storage == LBM_STORE_F32
+               ? launch_step2_t<5, float>(h, A, v, plain, two)
+               : launch_step2_t<5, double>(h, A, v, plain, two);
+  return h->p.storage == LBM_STORE_F32
+             ? launch_step2_t<9, float>(h, A, v, plain, two)
+             : launch_step2_t<9, double>(h, A, v, plain, two);
 }
 
 hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
   if (two_step_variant(h)) {
     for (; nsteps >= 2; nsteps -= 2) {
-      const hipError_t e = launch_step2(h, h->buf[h->cur], h->buf[h->cur ^ 1]);
+      const hipError_t e =
+          launch_step2(h, h->buf[h->cur], h->buf[h->cur ^ 1], true);
       if (e != hipSuccess) return e;
       h->cur ^= 1;
       h->steps += 2;

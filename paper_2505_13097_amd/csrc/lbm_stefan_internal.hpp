@@ -64,8 +64,10 @@ void fill_args(const lbm_stefan_params &p, double *const prof[4],
                StepArgs *A);
 void fill_step_args(const lbm_stefan_t *h, StepArgs *A);
 hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst);
-// two steps in one launch (the handle's variant is a two-step variant)
-hipError_t launch_step2(const lbm_stefan_t *h, const void *src, void *dst);
+// two steps (or one, two = false) in one launch of the two-step kernel
+// (the handle's variant is a two-step variant)
+hipError_t launch_step2(const lbm_stefan_t *h, const void *src, void *dst,
+                        bool two);
 bool two_step_variant(const lbm_stefan_t *h);
 // advance the handle nsteps (pairs of steps in one launch under a two-step
 // variant); updates cur and steps
