@@ -26,17 +26,17 @@ struct Variant {
 };
 
 inline const Variant *variants(int q, int *n) {
-  static const Variant v1[] = {{256, 1, 1, 0, 0, 1}, {128, 1, 1, 0, 0, 1},
-                               {64, 1, 1, 0, 0, 1},  {256, 1, 2, 0, 0, 1}};
+  static const Variant v1[] = {{256, 1, 1, 0, 0, 1, 0}, {128, 1, 1, 0, 0, 1, 0},
+                               {64, 1, 1, 0, 0, 1, 0},  {256, 1, 2, 0, 0, 1, 0}};
   static const Variant v2[] = {
-      {64, 4, 1, 0, 0, 1}, {256, 1, 1, 0, 0, 1}, {128, 2, 1, 0, 0, 1},
-      {64, 4, 2, 0, 0, 1}, {128, 2, 2, 0, 0, 1}, {256, 1, 2, 0, 0, 1},
-      {64, 2, 2, 0, 0, 1}, {64, 4, 4, 0, 0, 1},  {64, 4, 2, 1, 0, 1},
-      {64, 4, 2, 0, 1, 1}, {64, 4, 2, 1, 1, 1},  {128, 2, 2, 0, 1, 1},
-      {64, 4, 2, 1, 0, 2}, {64, 4, 2, 1, 0, 4},  {64, 4, 2, 1, 0, 8},
-      {64, 4, 2, 0, 0, 4}, {64, 4, 1, 1, 0, 4},  {64, 4, 2, 1, 1, 4},
-      {128, 2, 2, 1, 0, 4}, {64, 4, 2, 1, 0, 16}, {64, 1, 1, 0, 0, 1},
-      {64, 2, 1, 0, 0, 1},
+      {64, 4, 1, 0, 0, 1, 0}, {256, 1, 1, 0, 0, 1, 0}, {128, 2, 1, 0, 0, 1, 0},
+      {64, 4, 2, 0, 0, 1, 0}, {128, 2, 2, 0, 0, 1, 0}, {256, 1, 2, 0, 0, 1, 0},
+      {64, 2, 2, 0, 0, 1, 0}, {64, 4, 4, 0, 0, 1, 0},  {64, 4, 2, 1, 0, 1, 0},
+      {64, 4, 2, 0, 1, 1, 0}, {64, 4, 2, 1, 1, 1, 0},  {128, 2, 2, 0, 1, 1, 0},
+      {64, 4, 2, 1, 0, 2, 0}, {64, 4, 2, 1, 0, 4, 0},  {64, 4, 2, 1, 0, 8, 0},
+      {64, 4, 2, 0, 0, 4, 0}, {64, 4, 1, 1, 0, 4, 0},  {64, 4, 2, 1, 1, 4, 0},
+      {128, 2, 2, 1, 0, 4, 0}, {64, 4, 2, 1, 0, 16, 0}, {64, 1, 1, 0, 0, 1, 0},
+      {64, 2, 1, 0, 0, 1, 0},
       {256, 2, 1, 1, 0, 32, 1},  {256, 2, 1, 1, 0, 64, 1},
       {128, 2, 1, 1, 0, 16, 1},  {128, 2, 1, 1, 0, 24, 1},
       {128, 2, 1, 1, 0, 32, 1},  {128, 2, 1, 1, 0, 64, 1},
