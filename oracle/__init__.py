@@ -4,7 +4,9 @@ This package is the plain, slow, obviously correct statement of what the
 GPU path computes: the implicit regularized enthalpy lattice Boltzmann
 step of Luddens, Lothode and Danaila (arXiv 2505.13097), Algorithm 3
 (Section 4.1), with the boundary closures of Section 4.2, the Neumann
-similarity solution of Section 2 and a reverse mode of the step.
+similarity solution of Section 2 and a reverse mode of the step; and the
+explicit enthalpy based method the paper compares with (Algorithm 2),
+selected by ``prob.scheme == "eebm"``.
 
 Only the tests, the smoke check and the CPU-baseline leg of the bench may
 import it.  It shares no code with the GPU library: the C sources in this
@@ -19,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ("irebm.c", "irebm_cs.c")
+SOURCES = ("irebm.c", "irebm_cs.c", "eebm.c")
 
 DIRICHLET, BOUNCEBACK, PERIODIC = 0, 1, 2
 SAFEGUARDED, PLAIN = 0, 1
@@ -98,12 +100,19 @@ def lib():
                             dp, dp],
             "orc_cs_front_loss": [P, dp, ctypes.c_long, dp, ctypes.c_double,
                                   ctypes.c_double, dp, dp, dp],
+            "orc_eebm_init": [P, dp, dp],
+            "orc_eebm_step": [P, dp, dp, S],
+            "orc_eebm_run": [P, dp, ctypes.c_long, S, dp, dp],
+            "orc_eebm_temperature": [P, dp, dp],
+            "orc_eebm_energy": [P, dp, dp],
+            "orc_eebm_front": [P, dp, ctypes.c_int, dp],
+            "orc_eebm_collide": [P, dp, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
-        for name in ("orc_phi", "orc_dphi"):
+        for name in ("orc_phi", "orc_dphi", "orc_eebm_theta"):
             fn = getattr(L, name)
             fn.argtypes = [ctypes.c_double] * 3
             fn.restype = ctypes.c_double
@@ -191,11 +200,33 @@ def newton(m0, theta, ste, tm, delta, tol=1e-12, max_it=20,
     return out.value, it.value, bool(conv.value)
 
 
+def _fn(prob, name):
+    """orc_<name>, or orc_eebm_<name> for the explicit scheme."""
+    if getattr(prob, "scheme", "irebm") == "eebm":
+        return getattr(lib(), "orc_eebm_" + name)
+    return getattr(lib(), "orc_" + name)
+
+
+def eebm_theta(H, ste, tm):
+    """Temperature of enthalpy H in the explicit scheme (Section 3.4)."""
+    return lib().orc_eebm_theta(H, ste, tm)
+
+
+def eebm_collide(prob, f):
+    """Post-collision populations of the explicit scheme's state f
+    (Algorithm 2 up to streaming)."""
+    s = Setup(prob)
+    f = _f64(f)
+    out = np.empty_like(f)
+    _check(lib().orc_eebm_collide(s.ref(), _dp(f), _dp(out)), "eebm_collide")
+    return out
+
+
 def init(prob, T0=None):
     s = Setup(prob)
     f = np.zeros(s.shape)
     T0a = None if T0 is None else _f64(np.broadcast_to(T0, (s.ny, s.nx)))
-    _check(lib().orc_init(s.ref(), _dp(T0a), _dp(f)), "orc_init")
+    _check(_fn(prob, "init")(s.ref(), _dp(T0a), _dp(f)), "init")
     return f
 
 
@@ -204,8 +235,8 @@ def step(prob, f):
     f = _f64(f)
     out = np.empty_like(f)
     st = Stats()
-    _check(lib().orc_step(s.ref(), _dp(f), _dp(out), ctypes.byref(st)),
-           "orc_step")
+    _check(_fn(prob, "step")(s.ref(), _dp(f), _dp(out), ctypes.byref(st)),
+           "step")
     return out, st.as_dict()
 
 
@@ -216,8 +247,8 @@ def run(prob, f, nsteps, trace=False):
     st = Stats()
     et = np.empty(nsteps + 1) if trace else None
     ft = np.empty((nsteps, 2)) if trace else None
-    _check(lib().orc_run(s.ref(), _dp(f), nsteps, ctypes.byref(st), _dp(et),
-                         _dp(ft)), "orc_run")
+    _check(_fn(prob, "run")(s.ref(), _dp(f), nsteps, ctypes.byref(st),
+                            _dp(et), _dp(ft)), "run")
     if trace:
         return f, st.as_dict(), et, ft
     return f, st.as_dict()
@@ -226,23 +257,23 @@ def run(prob, f, nsteps, trace=False):
 def temperature(prob, f):
     s = Setup(prob)
     T = np.empty((s.ny, s.nx))
-    _check(lib().orc_temperature(s.ref(), _dp(_f64(f)), _dp(T)),
-           "orc_temperature")
+    _check(_fn(prob, "temperature")(s.ref(), _dp(_f64(f)), _dp(T)),
+           "temperature")
     return T
 
 
 def energy(prob, f):
     s = Setup(prob)
     E = ctypes.c_double()
-    _check(lib().orc_energy(s.ref(), _dp(_f64(f)), ctypes.byref(E)),
-           "orc_energy")
+    _check(_fn(prob, "energy")(s.ref(), _dp(_f64(f)), ctypes.byref(E)),
+           "energy")
     return E.value
 
 
 def front(prob, f, mode=FRONT_INTEGRAL):
     s = Setup(prob)
     xf = np.empty(s.ny)
-    _check(lib().orc_front(s.ref(), _dp(_f64(f)), mode, _dp(xf)), "orc_front")
+    _check(_fn(prob, "front")(s.ref(), _dp(_f64(f)), mode, _dp(xf)), "front")
     return xf
 
 

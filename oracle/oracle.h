@@ -108,6 +108,23 @@ int orc_cs_front_loss(const orc_params *p, const double *T0, long nsteps,
                       const double *wall_im, double *loss_re,
                       double *loss_im);
 
+/* The explicit enthalpy based method (Algorithm 2): state f with
+   M0(f) = H; same parameters (delta, tol, max_it, newton_mode unused),
+   same boundary conditions (eebm.c states the closures). */
+double orc_eebm_theta(double H, double ste, double tm);
+int orc_eebm_init(const orc_params *p, const double *T0, double *f);
+int orc_eebm_step(const orc_params *p, const double *f, double *fout,
+                  orc_stats *st);
+int orc_eebm_run(const orc_params *p, double *f, long nsteps, orc_stats *st,
+                 double *energy_trace, double *flux_trace);
+int orc_eebm_temperature(const orc_params *p, const double *f, double *T);
+int orc_eebm_energy(const orc_params *p, const double *f, double *E);
+int orc_eebm_front(const orc_params *p, const double *f, int mode,
+                   double *xf);
+/* the collision half of a step (moments, equilibrium, BGK) at every node:
+   the post-collision populations, whose pull streaming gives the next f */
+int orc_eebm_collide(const orc_params *p, const double *f, double *omega);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,7 @@ class Problem:
     nsteps: int = 0
     name: str = ""
     dx: float = field(default=None)
+    scheme: str = "irebm"  # "irebm" (Algorithm 3) or "eebm" (Algorithm 2)
 
     def __post_init__(self):
         if self.dx is None:
