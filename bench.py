@@ -43,7 +43,7 @@ def workload(name):
 
 
 KERNEL_SOURCES = ("irebm_node.hpp", "kernels.hpp", "host_util.hpp",
-                  "lbm_stefan.hip")
+                  "launch.hpp", "k_step_safeguarded.hip")
 
 
 def kernel_source_hash():
@@ -153,6 +153,30 @@ def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
         "graph_steps": graph_steps, "autotune": tuned,
         "nonconverged": int(sum(s["nonconverged"] for s in st)),
         "max_newton_it": int(max(s["max_newton_it"] for s in st)),
+    }
+
+
+def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step):
+    """The explicit enthalpy based method (Algorithm 2) on the same
+    lattice, same kernels and state layout, no Newton solve; the paper's
+    timing tables report the IREBM/EEBM time ratio."""
+    from paper_2505_13097_amd import variant_names
+    pe = prob.with_(scheme="eebm", name=prob.name + "_eebm")
+    r = time_plain(pe, steps, warmup, -1, autotune=autotune)
+    v = r["variant"] if r["variant"] >= 0 else (0 if pe.q == 3 else 3)
+    vname = variant_names(pe.q, pe.storage)[v]
+    spl = steps_per_launch(vname)
+    launch_ms = r["gpu_ms"] / (steps // spl)
+    gbps = pe.nodes * bytes_per_node(pe) * spl / (launch_ms * 1e-3) / 1e9
+    ms = r["wall_s"] * 1e3 / steps
+    return {
+        "workload": pe.name, "steps": steps,
+        "value": round(pe.nodes * steps / r["wall_s"] / 1e6, 1),
+        "unit": "MLUPS", "ms_per_step": round(ms, 4),
+        "kernel_variant": vname,
+        "hbm_gbps_algorithmic": round(gbps, 1),
+        "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
+        "time_ratio_irebm_to_eebm": round(irebm_ms_per_step / ms, 3),
     }
 
 
@@ -426,8 +450,9 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,adjoint",
-                    help="comma list of extra forms to time: batched, adjoint")
+    ap.add_argument("--forms", default="plain,batched,adjoint,eebm",
+                    help="comma list of extra forms to time: batched, "
+                         "adjoint, eebm")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-variant", type=int, default=-1)
@@ -561,6 +586,11 @@ def main():
         # every state kept (no recompute): 4097 states of 5.2 MB fit in HBM
         forms["adjoint_all_states"] = time_adjoint(adj, 1, not args.no_autotune)
         print("[bench] adjoint done", file=sys.stderr, flush=True)
+    if "eebm" in args.forms.split(","):
+        print("[bench] eebm form", file=sys.stderr, flush=True)
+        forms["eebm"] = time_eebm(prob, args.steps, args.warmup,
+                                  not args.no_autotune, ms_per_step)
+        print("[bench] eebm done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

@@ -12,6 +12,14 @@
  * and the update, with the boundary closures on the pulled populations of
  * Section 4.2 (Dirichlet, bounce-back) or periodic axes.
  *
+ * The same handles also run the explicit enthalpy based method the paper
+ * compares with (EEBM, Section 3.4, Algorithm 2; params.scheme =
+ * LBM_SCHEME_EEBM): H = M0(f), theta = Theta(H) in closed form (H below
+ * T_m, T_m for T_m <= H <= T_m + 1/Ste, H - 1/Ste above), equilibrium
+ * w_i theta (i != 0) and H - (1 - w_0) theta (rest), BGK collision and
+ * pull streaming, with the same closures (Dirichlet target: the wall
+ * enthalpy T_D + l(T_D)/Ste, l = 1 above T_m and 0 otherwise).
+ *
  * Conventions
  *   - All entry points return LBM_STEFAN_OK (0) or a negative error code;
  *     the text of the last error of a handle is lbm_stefan_last_error(h)
@@ -29,7 +37,10 @@
  *     Omega_i = (1 - 1/tau) f_i + (w_i/tau) T  (eq. def_qi_omegai) at the
  *     current time, stored as q planes [q][ny][nx] (x fastest) in the
  *     storage type (double or float).  T = sum_i Omega_i = sum_i f_i.
- *     Per-node arithmetic is always double precision.
+ *     EEBM: Omega_i = f_i - (f_i - f_i^eq)/tau, the populations after the
+ *     collision of Algorithm 2 and before its streaming; sum_i Omega_i =
+ *     sum_i f_i = H and T = Theta(H).  Per-node arithmetic is always
+ *     double precision.
  *   - nx nodes span x in [0, 1] unless dx says otherwise; wall nodes are
  *     lattice nodes ("wet" walls).
  *   - A handle enqueues all GPU work on the stream it was created with and
@@ -68,9 +79,17 @@ extern "C" {
 #define LBM_NEWTON_PLAIN 1       /* the update of Algorithm 3 as printed */
 
 /* front position of each row y (Section 6: "position of the interface") */
-#define LBM_FRONT_LIQUID_INTEGRAL 0 /* dx * trapezoid sum_x phi(T(x, y)) */
+#define LBM_FRONT_LIQUID_INTEGRAL 0 /* dx * trapezoid sum_x phi(T(x, y));
+                                       EEBM: of l(H) = clamp(Ste (H - T_m),
+                                       0, 1) */
 #define LBM_FRONT_ZERO_CROSSING 1   /* first x where T - T_m goes from > 0
                                        to <= 0, linearly interpolated */
+
+/* time-step scheme */
+#define LBM_SCHEME_IREBM 0 /* Algorithm 3 (Section 4.1), default */
+#define LBM_SCHEME_EEBM 1  /* Algorithm 2 (Section 3.4): no Newton solve;
+                              delta, newton_* and newton_mode are unused
+                              but still validated; no reverse mode */
 
 /* fields for lbm_stefan_get_field */
 #define LBM_FIELD_T 0     /* temperature, double [ny][nx] */
@@ -104,6 +123,7 @@ typedef struct lbm_stefan_params {
   int32_t variant;       /* kernel variant (lbm_stefan_variant_name); -1
                             picks the library default for the lattice */
   int32_t flags;         /* LBM_FLAG_* */
+  int32_t scheme;        /* LBM_SCHEME_*; 0 (zeroed params) is IREBM */
 } lbm_stefan_params;
 
 #define LBM_FLAG_ADJOINT 1 /* reserve workspace for the reverse mode */
@@ -111,12 +131,14 @@ typedef struct lbm_stefan_params {
 typedef struct lbm_stefan_stats {
   int64_t steps;         /* steps taken since init */
   int32_t max_newton_it; /* largest Newton iteration count since the last
-                            lbm_stefan_reset_stats (or init) */
+                            lbm_stefan_reset_stats (or init); EEBM: 0, as
+                            are nonconverged and max_residual */
   int32_t reserved;
   int64_t nonconverged;  /* node-steps that reached the cap, same window */
   double max_residual;   /* largest |T~ + phi(T~)/Ste - M0(q) - phi(T)/Ste| */
   double energy;         /* E = sum_x [T + phi(T)/Ste] of the current state
-                            (eq. eq-H), FP64 in a fixed summation order */
+                            (eq. eq-H; EEBM: sum_x H), FP64 in a fixed
+                            summation order */
   double flux_in;        /* sum of populations set by boundary closures */
   double flux_out;       /* sum of post-collision populations leaving the
                             lattice; E(n) - E(0) = flux_in - flux_out up to
@@ -154,7 +176,8 @@ int lbm_stefan_workspace_bytes(const lbm_stefan_params *p, size_t *bytes);
  * tau <= 1/2, Ste <= 0, delta <= 0, tol <= 0, max_it outside 1..1000,
  * nx < 3, ny < 3 in 2D or != 1 in 1D, lattice/dim mismatch, a periodic
  * axis with one non-periodic wall, workspace too small or misaligned,
- * unknown variant), EDEVICE.
+ * unknown variant or scheme, LBM_FLAG_ADJOINT with LBM_SCHEME_EEBM),
+ * EDEVICE.
  */
 int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
                     void *workspace, size_t bytes, void *stream,
@@ -328,7 +351,8 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
 typedef struct lbm_stefan_batch lbm_stefan_batch_t;
 
 /* Workspace for `count` instances (params array of length count).
-   Errors: EINVAL (an invalid instance, mixed q/storage/newton_mode). */
+   Errors: EINVAL (an invalid instance, mixed q/storage/newton_mode/
+   scheme). */
 int lbm_stefan_batch_workspace_bytes(const lbm_stefan_params *params,
                                      int32_t count, size_t *bytes);
 

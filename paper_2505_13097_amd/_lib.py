@@ -19,6 +19,7 @@ NEWTON_SAFEGUARDED, NEWTON_PLAIN = 0, 1
 FRONT_LIQUID_INTEGRAL, FRONT_ZERO_CROSSING = 0, 1
 FIELD_T, FIELD_STATE = 0, 1
 FLAG_ADJOINT = 1
+SCHEME_IREBM, SCHEME_EEBM = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -35,6 +36,7 @@ class Params(ctypes.Structure):
         ("dx", ctypes.c_double), ("newton_tol", ctypes.c_double),
         ("newton_max_it", ctypes.c_int32), ("strict", ctypes.c_int32),
         ("variant", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
     ]
 
 

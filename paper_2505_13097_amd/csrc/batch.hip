@@ -10,8 +10,10 @@
 // XCD (block b runs on XCD b mod 8), so neighbouring tiles of an instance
 // are swept by the same XCD and share its L2.  The node update is the one of
 // the single-lattice step (step_item), so a batch member evolves exactly
-// as the same lattice run alone.  Steps can be captured in a hipGraph;
-// the autotuner picks the tile variant and the grid size.
+// as the same lattice run alone, IREBM or EEBM alike.  Steps can be
+// captured in a hipGraph; the autotuner picks the tile variant and the
+// grid size.  This unit is the host side; the kernels and their launches
+// are in launch.hpp (instantiated by k_batch_<mode>.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,79 +30,10 @@
 
 using namespace irebm;
 
-namespace {
-
-// one work item of the table: items[t] = (instance, item index within
-// it); the descriptor is block-uniform and read in place with scalar loads
-template <int Q, typename S, int NPT, bool PLAIN, bool NT, bool LOOP>
-__device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
-                                           const int2 *__restrict__ items,
-                                           int t, int parity) {
-  const int2 e = items[t];
-  const int inst = __builtin_amdgcn_readfirstlane(e.x);
-  const int item = __builtin_amdgcn_readfirstlane(e.y);
-  const StepArgs &A = descs[inst];
-  const S *src = (const S *)(parity ? A.dst : A.src);
-  S *dst = (S *)(parity ? A.src : A.dst);
-  step_item<Q, S, NPT, PLAIN, NT, LOOP>(A, src, dst, item, A.slots + item);
-}
-
-// one block per work item, the blocks of XCD k taking the k-th contiguous
-// chunk of the table
-template <int Q, typename S, int NPT, bool PLAIN, bool NT>
-__global__ __launch_bounds__(256) void batch_step_kernel(
-    const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
-    int32_t nitems, int32_t parity, int32_t reverse) {
-  const int chunk = (nitems + 7) >> 3;
-  const int b = (int)blockIdx.x;
-  if ((b & 7) * chunk + (b >> 3) >= nitems) return;
-  batch_item<Q, S, NPT, PLAIN, NT, false>(
-      descs, items, xcd_item(b, chunk, nitems, reverse), parity);
-}
-
-// persistent grid sized to the machine: each block walks its XCD's chunk
-// of the table with a stride
-template <int Q, typename S, int NPT, bool PLAIN, bool NT>
-__global__ __launch_bounds__(256) void batch_persistent_kernel(
-    const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
-    int32_t nitems, int32_t parity, int32_t reverse) {
-  const int chunk = (nitems + 7) >> 3;
-  const int per_xcd_blocks = (int)(gridDim.x >> 3);
-  const int xcd = (int)(blockIdx.x & 7), lane = (int)(blockIdx.x >> 3);
-  const int t_end = min(nitems, (xcd + 1) * chunk);
-  for (int t = xcd * chunk + lane; t < t_end; t += per_xcd_blocks)
-    batch_item<Q, S, NPT, PLAIN, NT, true>(descs, items,
-                                           reverse ? nitems - 1 - t : t, parity);
-}
-
-// two steps (or one) per launch: one block per item of the two-step
-// tiling (a strip of one segment of one instance), XCD-contiguous chunks
-template <int Q, typename S, bool PLAIN, int BY, int WIN>
-__global__ __launch_bounds__(WIN * BY)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 4 : 1)))
-void batch_step2_kernel(const StepArgs *__restrict__ descs,
-                        const int2 *__restrict__ items, int32_t nitems,
-                        int32_t parity, int32_t two) {
-  const int per_xcd = (nitems + 7) >> 3;
-  const int t = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
-  if (t >= nitems) return;
-  const int2 e = items[t];
-  const int inst = __builtin_amdgcn_readfirstlane(e.x);
-  const int item = __builtin_amdgcn_readfirstlane(e.y);
-  const StepArgs &A = descs[inst];
-  const S *src = (const S *)(parity ? A.dst : A.src);
-  S *dst = (S *)(parity ? A.src : A.dst);
-  step2_body<Q, S, PLAIN, true, BY, WIN>(A, src, dst, item % A.tiles_x,
-                                         item / A.tiles_x, A.group, two != 0,
-                                         A.slots + item);
-}
-
-}  // namespace
-
 struct lbm_stefan_batch {
   std::vector<lbm_stefan_params> ps;
   int count = 0, q = 0, storage = 0;
-  bool plain = false;
+  int mode = kSafeguarded;  // node-update mode shared by the instances
   int device = 0, cus = 0;
   hipStream_t stream = nullptr, cap_stream = nullptr;
   char *ws = nullptr;
@@ -151,8 +84,9 @@ std::string validate_batch(const lbm_stefan_params *ps, int32_t count) {
     const std::string e = validate_params(&ps[k]);
     if (!e.empty()) return "instance " + std::to_string(k) + ": " + e;
     if (ps[k].q != ps[0].q || ps[k].storage != ps[0].storage ||
-        ps[k].newton_mode != ps[0].newton_mode)
-      return "instances must share lattice, storage and newton_mode";
+        ps[k].newton_mode != ps[0].newton_mode ||
+        ps[k].scheme != ps[0].scheme)
+      return "instances must share lattice, storage, newton_mode and scheme";
   }
   return "";
 }
@@ -251,76 +185,21 @@ int build_schedule(lbm_stefan_batch_t *b) {
   return LBM_STEFAN_OK;
 }
 
-template <int Q, typename S>
-hipError_t launch_batch_t(const lbm_stefan_batch_t *b, hipStream_t stream,
-                          int parity, bool two) {
-  int nv;
-  const Variant &v = variants(Q, &nv)[b->variant];
-  const int64_t chunk = (b->nitems + 7) / 8;
-  if (v.tb) {
-    if constexpr (Q == 3) {
-      return hipErrorInvalidValue;
-    } else {
-      dim3 grid((unsigned)(8 * std::max<int64_t>(chunk, 1))), block(v.bx, v.by);
-      const int32_t nt = (int32_t)b->nitems, tw = two ? 1 : 0;
-#define B2LAUNCH(PL, BY, WIN)                                              \
-  batch_step2_kernel<Q, S, PL, BY, WIN><<<grid, block, 0, stream>>>(     \
-      b->descs, b->items, nt, parity, tw)
-#define B2LAUNCH_SHAPE(PL)                 \
-  do {                                     \
-    if (v.bx == 256) B2LAUNCH(PL, 2, 256); \
-    else if (v.by == 2) B2LAUNCH(PL, 2, 128); \
-    else B2LAUNCH(PL, 4, 128);             \
-  } while (0)
-      if (b->plain) B2LAUNCH_SHAPE(true);
-      else B2LAUNCH_SHAPE(false);
-#undef B2LAUNCH_SHAPE
-#undef B2LAUNCH
-      return hipGetLastError();
-    }
-  }
-  int64_t g8 = chunk;  // one block per item
-  if (b->blocks_per_cu > 0)
-    g8 = std::min<int64_t>(((int64_t)b->cus * b->blocks_per_cu + 7) / 8, chunk);
-  dim3 grid((unsigned)(8 * std::max<int64_t>(g8, 1))), block(v.bx, v.by);
-  const int32_t nt = (int32_t)b->nitems;
-  const int32_t rev = v.rev && parity;
-  const int32_t pers = b->blocks_per_cu > 0;
-#define BLAUNCH(NPT, PL, NTS)                                              \
-  do {                                                                     \
-    if (pers)                                                              \
-      batch_persistent_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>( \
-          b->descs, b->items, nt, parity, rev);                            \
-    else                                                                   \
-      batch_step_kernel<Q, S, NPT, PL, NTS><<<grid, block, 0, stream>>>(   \
-          b->descs, b->items, nt, parity, rev);                            \
-  } while (0)
-#define BLAUNCH_NPT(PL, NTS)                  \
-  do {                                        \
-    if (v.npt == 1) BLAUNCH(1, PL, NTS);      \
-    else if (v.npt == 2) BLAUNCH(2, PL, NTS); \
-    else BLAUNCH(4, PL, NTS);                 \
-  } while (0)
-  if (b->plain) {
-    if (v.nt) BLAUNCH_NPT(true, true);
-    else BLAUNCH_NPT(true, false);
-  } else {
-    if (v.nt) BLAUNCH_NPT(false, true);
-    else BLAUNCH_NPT(false, false);
-  }
-#undef BLAUNCH_NPT
-#undef BLAUNCH
-  return hipGetLastError();
-}
-
 // one launch from buffer `parity`: one step, or two under a two-step
 // variant (one if two = false)
 hipError_t launch_batch(const lbm_stefan_batch_t *b, hipStream_t stream,
                         int parity, bool two = true) {
-  return dispatch_qs(b->q, b->storage, [&](auto qt, auto tt) {
-    QS_TYPES(qt, tt);
-    return launch_batch_t<Q, S>(b, stream, parity, two);
-  });
+  int nv;
+  const Variant &v = variants(b->q, &nv)[b->variant];
+  BatchLaunch L;
+  L.descs = b->descs;
+  L.items = b->items;
+  L.nitems = b->nitems;
+  L.cus = b->cus;
+  L.blocks_per_cu = b->blocks_per_cu;
+  L.parity = parity;
+  L.two = two;
+  return batch_launch(b->mode, b->q, b->storage, L, v, stream);
 }
 
 // time steps one launch advances under the current variant
@@ -401,7 +280,7 @@ int lbm_stefan_batch_init(const lbm_stefan_params *ps, int32_t count,
   b->count = count;
   b->q = ps[0].q;
   b->storage = ps[0].storage;
-  b->plain = ps[0].newton_mode == LBM_NEWTON_PLAIN;
+  b->mode = mode_of(ps[0]);
   b->stream = (hipStream_t)stream;
   if (hipGetDevice(&b->device) != hipSuccess ||
       hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount,
@@ -532,8 +411,7 @@ int lbm_stefan_batch_stats(lbm_stefan_batch_t *b, lbm_stefan_stats *out) {
     stats_kernel<<<1, 256, 0, b->stream>>>(b->slots + b->first_item[k],
                                            b->nitems_inst[k], b->small + 16 * k);
     BCHK(b, hipGetLastError());
-    BCHK(b, energy_async(b->q, b->storage, b->state[b->cur] + b->off[k],
-                         p.nx * p.ny, p.t_m, p.delta, p.ste, b->partials,
+    BCHK(b, energy_async(p, b->state[b->cur] + b->off[k], b->partials,
                          b->small + 16 * k + 8, b->stream));
   }
   BCHK(b, hipMemcpyAsync(hs.data(), b->small, hs.size() * 8,
@@ -569,16 +447,14 @@ int lbm_stefan_batch_query_front(lbm_stefan_batch_t *b, int32_t inst,
   const char *src = b->state[b->cur] + b->off[inst];
   double *fr = b->small + 16 * (int64_t)b->count + 16;
   if (front) {
-    BCHK(b, front_async(b->q, b->storage, src, p.nx, p.ny, mode, p.t_m,
-                        p.delta, p.dx, fr, b->stream));
+    BCHK(b, front_async(p, src, mode, fr, b->stream));
     BCHK(b, hipMemcpyAsync(front, fr, p.ny * 8, hipMemcpyDeviceToHost,
                            b->stream));
   }
   double e = 0.0;
   if (energy) {
-    BCHK(b, energy_async(b->q, b->storage, src, p.nx * p.ny, p.t_m, p.delta,
-                         p.ste, b->partials, b->small + 16 * (int64_t)b->count,
-                         b->stream));
+    BCHK(b, energy_async(p, src, b->partials,
+                         b->small + 16 * (int64_t)b->count, b->stream));
     BCHK(b, hipMemcpyAsync(&e, b->small + 16 * (int64_t)b->count, 8,
                            hipMemcpyDeviceToHost, b->stream));
   }
@@ -606,7 +482,7 @@ int lbm_stefan_batch_get_field(lbm_stefan_batch_t *b, int32_t inst,
   } else if (what == LBM_FIELD_T) {
     // the instance's idle buffer holds >= 12 n bytes
     double *T = (double *)(b->state[b->cur ^ 1] + b->off[inst]);
-    BCHK(b, temperature_async(b->q, b->storage, src, n, T, b->stream));
+    BCHK(b, temperature_async(p, src, T, b->stream));
     BCHK(b, hipMemcpyAsync(host, T, n * 8, hipMemcpyDeviceToHost, b->stream));
   } else {
     return bfail(b, LBM_STEFAN_EINVAL, "unknown field");

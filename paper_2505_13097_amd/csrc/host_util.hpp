@@ -130,45 +130,53 @@ inline hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-// E = sum [T + phi(T)/Ste] of n nodes of state `src` into *out (device),
-// using `partials` (>= ceil(n / kEnergyChunk) doubles) as scratch
-inline hipError_t energy_async(int q, int storage, const void *src, int64_t n,
-                               double tm, double delta, double ste,
+// E = sum [T + phi(T)/Ste] (EEBM: sum H) of the state `src` of a lattice
+// with params p into *out (device), using `partials` (>= ceil(nodes /
+// kEnergyChunk) doubles) as scratch
+inline hipError_t energy_async(const lbm_stefan_params &p, const void *src,
                                double *partials, double *out,
                                hipStream_t stream) {
-  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+  const int64_t n = p.nx * p.ny;
+  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     const int64_t parts = (n + kEnergyChunk - 1) / kEnergyChunk;
     energy_partial_kernel<Q, S><<<(unsigned)parts, 256, 0, stream>>>(
-        (const S *)src, n, tm, 1.0 / delta, 1.0 / ste, partials);
+        (const S *)src, n, p.scheme == LBM_SCHEME_EEBM, p.t_m, 1.0 / p.delta,
+        1.0 / p.ste, partials);
     sum_kernel<<<1, 256, 0, stream>>>(partials, parts, out);
     return hipGetLastError();
   });
 }
 
-// per-row front of an nx x ny state into out[0..ny) (device)
-inline hipError_t front_async(int q, int storage, const void *src, int64_t nx,
-                              int64_t ny, int mode, double tm, double delta,
-                              double dx, double *out, hipStream_t stream) {
-  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+// per-row front of the state `src` of a lattice with params p (p.dx > 0)
+// into out[0..ny) (device)
+inline hipError_t front_async(const lbm_stefan_params &p, const void *src,
+                              int mode, double *out, hipStream_t stream) {
+  const int eebm = p.scheme == LBM_SCHEME_EEBM;
+  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     if (mode == LBM_FRONT_LIQUID_INTEGRAL)
-      front_integral_kernel<Q, S><<<(unsigned)ny, 256, 0, stream>>>(
-          (const S *)src, nx * ny, (int)nx, tm, 1.0 / delta, dx, out);
+      front_integral_kernel<Q, S><<<(unsigned)p.ny, 256, 0, stream>>>(
+          (const S *)src, p.nx * p.ny, (int)p.nx, eebm, p.t_m, 1.0 / p.delta,
+          p.ste, p.dx, out);
     else
-      front_crossing_kernel<Q, S><<<(unsigned)ny, 256, 0, stream>>>(
-          (const S *)src, nx * ny, (int)nx, tm, dx, out);
+      front_crossing_kernel<Q, S><<<(unsigned)p.ny, 256, 0, stream>>>(
+          (const S *)src, p.nx * p.ny, (int)p.nx, eebm, p.t_m, 1.0 / p.ste,
+          p.dx, out);
     return hipGetLastError();
   });
 }
 
-// T = sum_i Omega_i of n nodes into T (device doubles)
-inline hipError_t temperature_async(int q, int storage, const void *src,
-                                    int64_t n, double *T, hipStream_t stream) {
-  return dispatch_qs(q, storage, [&](auto qt, auto tt) {
+// temperature of every node of the state `src` into T (device doubles)
+inline hipError_t temperature_async(const lbm_stefan_params &p,
+                                    const void *src, double *T,
+                                    hipStream_t stream) {
+  const int64_t n = p.nx * p.ny;
+  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     temp_kernel<Q, S><<<blocks_for(n, 256), 256, 0, stream>>>(
-        (const S *)src, n, T);
+        (const S *)src, n, p.scheme == LBM_SCHEME_EEBM, p.t_m, 1.0 / p.ste,
+        T);
     return hipGetLastError();
   });
 }

@@ -14,6 +14,13 @@
 // and writes the next state Omega'_i = (1 - 1/tau) f~_i + (w_i/tau) M0(f~).
 // Storing Omega instead of f makes the pull read one direction per
 // neighbour, so a step moves the minimum 2 q s bytes per node.
+//
+// The same kernels run the explicit enthalpy based method (EEBM, Section
+// 3.4, Algorithm 2) on the same post-collision state: the pulled q_i are
+// the streamed f~_i, H = M0(f~) is the enthalpy, theta = Theta(H) its
+// temperature, and the next state is the BGK collision
+//   Omega'_i = (1 - 1/tau) f~_i + f_i^eq / tau,
+//   f_i^eq = w_i theta (i != 0),  f_0^eq = H - (1 - w_0) theta.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,6 +64,11 @@ __host__ __device__ constexpr int opp(int i) {
 
 enum { BC_DIRICHLET = 0, BC_BOUNCEBACK = 1, BC_PERIODIC = 2 };
 
+// node update of a kernel instance: IREBM with the safeguarded or the
+// printed Newton update (Algorithm 3), or the explicit scheme (Algorithm 2)
+enum Mode : int { kSafeguarded = 0, kPlain = 1, kEebm = 2 };
+enum { SCHEME_IREBM = 0, SCHEME_EEBM = 1 };
+
 // Per-tile statistics slot, accumulated across steps by the one block
 // that owns the tile (no atomics; deterministic).
 struct StatSlot {
@@ -78,7 +90,9 @@ struct StepArgs {
   int32_t nitems, per_xcd;   // work items; items per XCD chunk
   int32_t reverse;      // sweep the tiles in reverse order
   int32_t periodic_x, periodic_y;
+  int32_t scheme;       // SCHEME_IREBM or SCHEME_EEBM
   double a;             // 1 - 1/tau
+  double inv_tau;       // 1/tau
   double wtau[9];       // w_i / tau
   double wste[9];       // w_i / Ste
   double inv_ste, tm, inv_delta, tol;
@@ -116,6 +130,19 @@ __device__ __forceinline__ double phi_only(double t, double tm, double inv_delta
   if (u > 20.0) return 1.0;
   if (u < -20.0) return 0.0;
   return 1.0 / (1.0 + exp(-2.0 * u));
+}
+
+// ---- temperature of an enthalpy in the explicit scheme (Section 3.4):
+// H below T_m, T_m on the band [T_m, T_m + 1/Ste], H - 1/Ste above it
+__host__ __device__ __forceinline__ double eebm_theta(double H, double tm,
+                                                      double inv_ste) {
+  return H < tm ? H : (H <= tm + inv_ste ? tm : H - inv_ste);
+}
+// its sharp liquid fraction l(H) = clamp(Ste (H - T_m), 0, 1)
+__host__ __device__ __forceinline__ double eebm_lf(double H, double tm,
+                                                   double ste) {
+  const double l = ste * (H - tm);
+  return l < 0.0 ? 0.0 : (l > 1.0 ? 1.0 : l);
 }
 
 // ---- local Newton solve of eq. rhs_fl_2:
@@ -308,7 +335,8 @@ __device__ __forceinline__ double wall_value(const StepArgs &A, int wall, int x,
 // 2. on a Dirichlet node, the zeroth moment is fixed to
 //    T_D + (phi(T_D) - phi(T))/Ste (eq. Dir_on_q), so that the new
 //    temperature is T_D; the deficit is shared by weight among the
-//    remaining unknowns;
+//    remaining unknowns.  EEBM: the zeroth moment is the wall enthalpy
+//    T_D + l(T_D)/Ste (l = 1 above T_m, else 0), whose Theta is T_D;
 // 3. anything left (corner of two bounce-back walls): own Omega_opp(i).
 // Masks of how each unknown was closed (for the reverse mode).
 struct CloseInfo {
@@ -319,7 +347,7 @@ struct CloseInfo {
   double TD = 0.0, wu = 0.0;
 };
 
-template <int Q>
+template <int Q, bool EEBM = false>
 __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
                                     double th, const double *om, double *q,
                                     uint32_t known, CloseInfo *ci = nullptr) {
@@ -340,8 +368,9 @@ __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
   if (ci) ci->wall = wall;
   if (wall >= 0) {
     const double TD = wall_value(A, wall, x, y);
-    double D = TD + (phi_only(TD, A.tm, A.inv_delta) -
-                     phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
+    double D = EEBM ? TD + (TD > A.tm ? A.inv_ste : 0.0)
+                    : TD + (phi_only(TD, A.tm, A.inv_delta) -
+                            phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
     double wu = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -397,10 +426,12 @@ __device__ __forceinline__ void node_masks(const StepArgs &A, int x, int y,
 
 // The update of one node from its loads: the next state's populations
 // into v (rounded to the storage type).
-template <int Q, typename S, bool PLAIN, bool FAST>
+template <int Q, typename S, int MODE, bool FAST>
 __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
                                               const NodeLoad<Q, S> &L,
                                               NodeStats &st, S v[Q]) {
+  constexpr bool PLAIN = MODE == kPlain;
+  constexpr bool EEBM = MODE == kEebm;
   double om[Q], q[Q];
   double th = 0.0;
 #pragma unroll
@@ -412,7 +443,7 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
   if (!FAST) {
     if (L.known != (1u << Q) - 1u)
-      st.flux_in += close_node<Q>(A, x, y, th, om, q, L.known);
+      st.flux_in += close_node<Q, EEBM>(A, x, y, th, om, q, L.known);
     if (L.out) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
@@ -422,6 +453,15 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   double m0 = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) m0 += q[i];
+  if constexpr (EEBM) {
+    // Algorithm 2: H = m0, explicit temperature, BGK collision
+    const double tq = eebm_theta(m0, A.tm, A.inv_ste);
+    v[0] = (S)(A.a * q[0] + A.inv_tau * (m0 - (1.0 - wt<Q>(0)) * tq));
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      v[i] = (S)(A.a * q[i] + A.wtau[wclass<Q>(i)] * tq);
+    return;
+  }
   // Quiet node: far below the melting band before and after (phi = 0 and
   // phi' = 0 exactly) and the Newton solve is the closed form of newton()
   // (T~ = m0, same iteration count).  Then f~ = q exactly and M0(f~) = m0
@@ -467,12 +507,12 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
 }
 
 // The update of one node from its loads; writes the next state.
-template <int Q, typename S, bool PLAIN, bool FAST, bool NT = false>
+template <int Q, typename S, int MODE, bool FAST, bool NT = false>
 __device__ __forceinline__ void update_node(const StepArgs &A, S *__restrict__ dst,
                                    int x, int y, const NodeLoad<Q, S> &L,
                                    NodeStats &st) {
   S v[Q];
-  update_values<Q, S, PLAIN, FAST>(A, x, y, L, st, v);
+  update_values<Q, S, MODE, FAST>(A, x, y, L, st, v);
   S *row = dst + (int64_t)y * A.nx;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {

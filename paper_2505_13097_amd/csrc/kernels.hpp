@@ -11,8 +11,9 @@
 //                    checks.  Per-item Newton and flux statistics are
 //                    accumulated by the owning block (no atomics).
 //   init_kernel      equilibrium state from a temperature field.
-//   temp_kernel      T = sum_i Omega_i.
-//   energy_*         E = sum [T + phi(T)/Ste], two fixed-order passes.
+//   temp_kernel      T = sum_i Omega_i (EEBM: Theta of that enthalpy).
+//   energy_*         E = sum [T + phi(T)/Ste] (EEBM: sum H), two
+//                    fixed-order passes.
 //   front_*          per-row front position.
 //   stats_kernel     fixed-order reduction of per-item slots.
 #pragma once
@@ -84,7 +85,7 @@ __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
 // state dst: on interior tiles all loads of the thread's nodes first
 // (memory-level parallelism), then the updates.  Statistics go into st;
 // returns whether the tile took the interior path.
-template <int Q, typename S, int NPT, bool PLAIN, bool NT>
+template <int Q, typename S, int NPT, int MODE, bool NT>
 __device__ __forceinline__ bool step_tile(const StepArgs &A,
                                           const S *__restrict__ src,
                                           S *__restrict__ dst, int tx, int ty,
@@ -103,7 +104,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
       load_node<Q, S, true>(A, src, x0 + (int)threadIdx.x + k * bx, y, L[k]);
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
-      update_node<Q, S, PLAIN, true, NT>(A, dst, x0 + (int)threadIdx.x + k * bx,
+      update_node<Q, S, MODE, true, NT>(A, dst, x0 + (int)threadIdx.x + k * bx,
                                          y, L[k], st);
   } else {
     // boundary tiles: one node at a time keeps the register count of the
@@ -114,7 +115,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
       if (x < A.nx && y < A.ny) {
         NodeLoad<Q, S> L;
         load_node<Q, S, false>(A, src, x, y, L);
-        update_node<Q, S, PLAIN, false, NT>(A, dst, x, y, L, st);
+        update_node<Q, S, MODE, false, NT>(A, dst, x, y, L, st);
       }
     }
   }
@@ -126,7 +127,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
 // rows a tile pulls from below were just read by the same block, and the
 // block's start-up (descriptor and slot reads) and statistics reduction
 // are paid once per item.  One statistics slot per item.
-template <int Q, typename S, int NPT, bool PLAIN, bool NT = false,
+template <int Q, typename S, int NPT, int MODE, bool NT = false,
           bool LOOP = false>
 __device__ __forceinline__ void step_item(const StepArgs &A,
                                           const S *__restrict__ src,
@@ -144,7 +145,7 @@ __device__ __forceinline__ void step_item(const StepArgs &A,
     // spill them into vector registers (lower occupancy).
     int z = 0;
     asm volatile("" : "+s"(z));
-    fast &= step_tile<Q, S, NPT, PLAIN, NT>((&A)[z], src, dst, tx, ty0 + r,
+    fast &= step_tile<Q, S, NPT, MODE, NT>((&A)[z], src, dst, tx, ty0 + r,
                                            st);
   }
   // read after the loop: a prefetched slot would stay live across it
@@ -165,12 +166,12 @@ namespace {
 
 
 // one time step of one lattice, one block per work item (XCD-aware order)
-template <int Q, typename S, int NPT, bool PLAIN, bool NT>
+template <int Q, typename S, int NPT, int MODE, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int b = blockIdx.x;
   if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
   const int t = xcd_item(b, A.per_xcd, A.nitems, A.reverse);
-  step_item<Q, S, NPT, PLAIN, NT>(A, (const S *)A.src, (S *)A.dst, t,
+  step_item<Q, S, NPT, MODE, NT>(A, (const S *)A.src, (S *)A.dst, t,
                                   A.slots + t);
 }
 
@@ -224,7 +225,7 @@ __device__ __forceinline__ void load_ring(const StepArgs &A,
 
 // the update of node (x, y) of a window from a ring: the interior form
 // (no masks, no closures) when every neighbour is a lattice node
-template <int Q, typename S, bool PLAIN, int RING, int WIN>
+template <int Q, typename S, int MODE, int RING, int WIN>
 __device__ __forceinline__ void ring_update(const StepArgs &A,
                                             const S (*ring)[Q][WIN], int x,
                                             int y, int t, int r, int base,
@@ -232,17 +233,17 @@ __device__ __forceinline__ void ring_update(const StepArgs &A,
   NodeLoad<Q, S> L;
   if (inner) {
     load_ring<Q, S, RING, WIN, true>(A, ring, x, y, t, r, base, L);
-    update_values<Q, S, PLAIN, true>(A, x, y, L, st, v);
+    update_values<Q, S, MODE, true>(A, x, y, L, st, v);
   } else {
     load_ring<Q, S, RING, WIN, false>(A, ring, x, y, t, r, base, L);
-    update_values<Q, S, PLAIN, false>(A, x, y, L, st, v);
+    update_values<Q, S, MODE, false>(A, x, y, L, st, v);
   }
 }
 
 // One block: strip `strip` of segment `seg` (seg_rows rows) of the lattice
 // described by A, from state src to state dst, two steps (two = true) or
 // one (the rows of step n + 1 are then written out directly).
-template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
+template <int Q, typename S, int MODE, bool NT, int BY, int WIN>
 __device__ __forceinline__ void step2_body(const StepArgs &A,
                                            const S *__restrict__ src,
                                            S *__restrict__ dst, int strip,
@@ -320,7 +321,7 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
       const int b = a - 1 + ty;
       if (own_col && b >= s0 && b < s1) {
         const bool inner = inner_x && (py || (b >= 1 && b <= ny - 2));
-        ring_update<Q, S, PLAIN, RING, WIN>(Ai, l0, x, b, t, b, base, inner,
+        ring_update<Q, S, MODE, RING, WIN>(Ai, l0, x, b, t, b, base, inner,
                                             st, w);
         wo = (int64_t)b * nx + x;
       }
@@ -331,7 +332,7 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
         S v[Q];
         NodeStats one;
         const bool inner = inner_x && (py || (gb >= 1 && gb <= ny - 2));
-        ring_update<Q, S, PLAIN, RING, WIN>(Ai, l0, gx, gb, t, b, base, inner,
+        ring_update<Q, S, MODE, RING, WIN>(Ai, l0, gx, gb, t, b, base, inner,
                                             one, v);
         if (own_col && b >= s0 && b < s1) {
           st.max_it = max(st.max_it, one.max_it);
@@ -350,7 +351,7 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
       const int c = a - 2 + ty;
       if (own_col && c >= s0 && c < s1) {
         const bool inner = inner_x && (py || (c >= 1 && c <= ny - 2));
-        ring_update<Q, S, PLAIN, RING, WIN>(Ai, l1, x, c, t, c, base, inner,
+        ring_update<Q, S, MODE, RING, WIN>(Ai, l1, x, c, t, c, base, inner,
                                             st, w);
         wo = (int64_t)c * nx + x;
       }
@@ -372,7 +373,7 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
 // XCD takes one contiguous chunk of that order, so neighbouring strips run
 // on the same XCD and share the halo lines (and the cache lines that
 // straddle two strips) in its L2.
-template <int Q, typename S, bool PLAIN, bool NT, int BY, int WIN>
+template <int Q, typename S, int MODE, bool NT, int BY, int WIN>
 // FP32 states: at most 128 VGPRs (4 waves per SIMD); FP64 rings fill the
 // LDS first
 __global__ __launch_bounds__(WIN * BY)
@@ -382,7 +383,7 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
   const int per_xcd = (nitems + 7) >> 3;
   const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (item >= nitems) return;
-  step2_body<Q, S, PLAIN, NT, BY, WIN>(A, (const S *)A.src, (S *)A.dst,
+  step2_body<Q, S, MODE, NT, BY, WIN>(A, (const S *)A.src, (S *)A.dst,
                                        item % nstrips, item / nstrips,
                                        seg_rows, two != 0, A.slots + item);
 }
@@ -390,6 +391,8 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
 // ---------------------------------------------------------------------
 // init, temperature, zero fill
 
+// IREBM: Omega_i = w_i T.  EEBM: the equilibrium of the enthalpy
+// H = T + l(T)/Ste (l = 1 above T_m, else 0), which collision keeps.
 template <int Q, typename S>
 __global__ void init_kernel(StepArgs A, const double *T0) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -398,18 +401,27 @@ __global__ void init_kernel(StepArgs A, const double *T0) {
   const int wall = dirichlet_wall<Q>(A, x, y);
   const double T = wall >= 0 ? wall_value(A, wall, x, y) : (T0 ? T0[k] : 0.0);
   S *dst = (S *)A.dst;
+  if (A.scheme == SCHEME_EEBM) {
+    const double H = T + (T > A.tm ? A.inv_ste : 0.0);
+    const double th = eebm_theta(H, A.tm, A.inv_ste);
+    dst[k] = (S)(H - (1.0 - wt<Q>(0)) * th);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) dst[i * A.plane + k] = (S)(wt<Q>(i) * th);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) dst[i * A.plane + k] = (S)(wt<Q>(i) * T);
 }
 
 template <int Q, typename S>
-__global__ void temp_kernel(const S *src, int64_t plane, double *T) {
+__global__ void temp_kernel(const S *src, int64_t plane, int eebm, double tm,
+                            double inv_ste, double *T) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= plane) return;
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) s += (double)src[j * plane + k];
-  T[k] = s;
+  T[k] = eebm ? eebm_theta(s, tm, inv_ste) : s;
 }
 
 __global__ void zero_kernel(uint64_t *p, int64_t n) {
@@ -431,11 +443,12 @@ __device__ __forceinline__ double block_sum_256(double v) {
   return r;
 }
 
-// partial[b] = sum over nodes [b*chunk, (b+1)*chunk) of T + phi(T)/Ste
+// partial[b] = sum over nodes [b*chunk, (b+1)*chunk) of T + phi(T)/Ste,
+// or of the enthalpy M0 itself (eebm)
 template <int Q, typename S>
 __global__ __launch_bounds__(256) void energy_partial_kernel(
-    const S *src, int64_t plane, double tm, double inv_delta, double inv_ste,
-    double *partial) {
+    const S *src, int64_t plane, int eebm, double tm, double inv_delta,
+    double inv_ste, double *partial) {
   const int64_t base = (int64_t)blockIdx.x * kEnergyChunk;
   double acc = 0.0;
   for (int j = 0; j < kEnergyChunk / 256; ++j) {
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(256) void energy_partial_kernel(
       double T = 0.0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
-      acc += T + phi_only(T, tm, inv_delta) * inv_ste;
+      acc += eebm ? T : T + phi_only(T, tm, inv_delta) * inv_ste;
     }
   }
   const double s = block_sum_256(acc);
@@ -492,43 +505,51 @@ __global__ __launch_bounds__(256) void stats_kernel(const StatSlot *slots,
   }
 }
 
-// front of row blockIdx.x: dx * trapezoid sum of phi(T)
+// front of row blockIdx.x: dx * trapezoid sum of phi(T), or of the sharp
+// liquid fraction l(H) (eebm)
 template <int Q, typename S>
 __global__ __launch_bounds__(256) void front_integral_kernel(
-    const S *src, int64_t plane, int nx, double tm, double inv_delta,
-    double dx, double *out) {
+    const S *src, int64_t plane, int nx, int eebm, double tm, double inv_delta,
+    double ste, double dx, double *out) {
   const int64_t row = (int64_t)blockIdx.x * nx;
   double acc = 0.0;
   for (int x = threadIdx.x; x < nx; x += 256) {
     double T = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) T += (double)src[i * plane + row + x];
-    const double ph = phi_only(T, tm, inv_delta);
+    const double ph = eebm ? eebm_lf(T, tm, ste) : phi_only(T, tm, inv_delta);
     acc += (x == 0 || x == nx - 1) ? 0.5 * ph : ph;
   }
   const double s = block_sum_256(acc);
   if (threadIdx.x == 0) out[blockIdx.x] = dx * s;
 }
 
+// temperature of node k: M0 of the state, or Theta of it (eebm)
 template <int Q, typename S>
-__device__ __forceinline__ double temp_at(const S *src, int64_t plane, int64_t k) {
+__device__ __forceinline__ double temp_at(const S *src, int64_t plane,
+                                          int64_t k, int eebm, double tm,
+                                          double inv_ste) {
   double T = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
-  return T;
+  return eebm ? eebm_theta(T, tm, inv_ste) : T;
 }
 
 // first x (from x = 0) with T(x) - tm > 0 >= T(x+1) - tm, interpolated
 template <int Q, typename S>
 __global__ __launch_bounds__(256) void front_crossing_kernel(
-    const S *src, int64_t plane, int nx, double tm, double dx, double *out) {
+    const S *src, int64_t plane, int nx, int eebm, double tm, double inv_ste,
+    double dx, double *out) {
   const int64_t row = (int64_t)blockIdx.x * nx;
+  auto rel = [&](int64_t k) {
+    return temp_at<Q, S>(src, plane, k, eebm, tm, inv_ste) - tm;
+  };
   const int chunk = (nx + 255) / 256;
   const int xa = threadIdx.x * chunk;
   int first = INT32_MAX;
   for (int x = xa; x < xa + chunk && x + 1 < nx; ++x) {
-    const double t0 = temp_at<Q, S>(src, plane, row + x) - tm;
-    const double t1 = temp_at<Q, S>(src, plane, row + x + 1) - tm;
+    const double t0 = rel(row + x);
+    const double t1 = rel(row + x + 1);
     if (t0 > 0.0 && t1 <= 0.0) {
       first = x;
       break;
@@ -542,15 +563,15 @@ __global__ __launch_bounds__(256) void front_crossing_kernel(
   __syncthreads();
   if (threadIdx.x == 0) {
     m = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
-    const double T0 = temp_at<Q, S>(src, plane, row) - tm;
+    const double T0 = rel(row);
     double pos;
     if (T0 <= 0.0) {
       pos = 0.0;
     } else if (m == INT32_MAX) {
       pos = (nx - 1) * dx;
     } else {
-      const double t0 = temp_at<Q, S>(src, plane, row + m) - tm;
-      const double t1 = temp_at<Q, S>(src, plane, row + m + 1) - tm;
+      const double t0 = rel(row + m);
+      const double t1 = rel(row + m + 1);
       pos = dx * (m + t0 / (t0 - t1));
     }
     out[blockIdx.x] = pos;

@@ -48,6 +48,10 @@ std::string irebm::validate_params(const lbm_stefan_params *p) {
   if (p->newton_mode != LBM_NEWTON_SAFEGUARDED &&
       p->newton_mode != LBM_NEWTON_PLAIN)
     return "unknown newton_mode";
+  if (p->scheme != LBM_SCHEME_IREBM && p->scheme != LBM_SCHEME_EEBM)
+    return "unknown scheme";
+  if (p->scheme == LBM_SCHEME_EEBM && (p->flags & LBM_FLAG_ADJOINT))
+    return "the reverse mode is for the IREBM scheme only";
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return "tau must be > 1/2";
   if (!(p->ste > 0.0) || !std::isfinite(p->ste)) return "ste must be > 0";
   if (!(p->delta > 0.0) || !std::isfinite(p->delta))
@@ -125,7 +129,9 @@ void irebm::fill_args(const lbm_stefan_params &p, double *const prof[4],
   A->plane = p.nx * p.ny;
   A->periodic_x = p.bc[0] == LBM_BC_PERIODIC;
   A->periodic_y = p.dim == 2 && p.bc[2] == LBM_BC_PERIODIC;
+  A->scheme = p.scheme;
   A->a = 1.0 - 1.0 / p.tau;
+  A->inv_tau = 1.0 / p.tau;
   for (int i = 0; i < p.q; ++i) {
     const double w = p.q == 3 ? wt<3>(i) : (p.q == 5 ? wt<5>(i) : wt<9>(i));
     A->wtau[i] = w / p.tau;
@@ -150,68 +156,6 @@ void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
   A->slots = h->slots;
 }
 
-namespace {
-
-template <int Q, typename S>
-hipError_t launch_step_t(const lbm_stefan_t *h, const StepArgs &A,
-                         const Variant &v, bool plain) {
-  StepArgs B = A;
-  set_tiling(&B, v);
-  B.reverse = v.rev && (h->steps & 1);
-  dim3 grid(8 * B.per_xcd), block(v.bx, v.by);
-#define LAUNCH(NPT, PL, NT) \
-  step_kernel<Q, S, NPT, PL, NT><<<grid, block, 0, h->stream>>>(B)
-#define LAUNCH_NPT(PL, NT)                 \
-  do {                                     \
-    if (v.npt == 1) LAUNCH(1, PL, NT);     \
-    else if (v.npt == 2) LAUNCH(2, PL, NT); \
-    else LAUNCH(4, PL, NT);                \
-  } while (0)
-  if (plain) {
-    if (v.nt) LAUNCH_NPT(true, true);
-    else LAUNCH_NPT(true, false);
-  } else {
-    if (v.nt) LAUNCH_NPT(false, true);
-    else LAUNCH_NPT(false, false);
-  }
-#undef LAUNCH_NPT
-#undef LAUNCH
-  return hipGetLastError();
-}
-
-}  // namespace
-
-namespace {
-
-// two steps src -> dst in one launch (variant v has tb set)
-template <int Q, typename S>
-hipError_t launch_step2_t(const lbm_stefan_t *h, const StepArgs &A,
-                          const Variant &v, bool plain, bool two) {
-  const int32_t nstrips = (int32_t)((h->p.nx + v.bx - 5) / (v.bx - 4));
-  const int64_t nseg = (h->p.ny + v.rows - 1) / v.rows;
-  const int32_t nitems = (int32_t)(nstrips * nseg);
-  dim3 grid((unsigned)(8 * ((nitems + 7) / 8))), block(v.bx, v.by);
-#define LAUNCH2(PL, BY, WIN)                                            \
-  step2_kernel<Q, S, PL, true, BY, WIN><<<grid, block, 0, h->stream>>>( \
-      A, nstrips, v.rows, nitems, two ? 1 : 0)
-#define LAUNCH2_SHAPE(PL)                            \
-  do {                                               \
-    if (v.bx == 256) {                               \
-      LAUNCH2(PL, 2, 256);                           \
-    } else {                                         \
-      if (v.by == 2) LAUNCH2(PL, 2, 128);            \
-      else LAUNCH2(PL, 4, 128);                      \
-    }                                                \
-  } while (0)
-  if (plain) LAUNCH2_SHAPE(true);
-  else LAUNCH2_SHAPE(false);
-#undef LAUNCH2_SHAPE
-#undef LAUNCH2
-  return hipGetLastError();
-}
-
-}  // namespace
-
 bool irebm::two_step_variant(const lbm_stefan_t *h) {
   int nv;
   return variants(h->p.q, &nv)[h->variant].tb != 0;
@@ -225,14 +169,8 @@ hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
   A.dst = dst;
   int nv;
   const Variant &v = variants(h->p.q, &nv)[h->variant];
-  const bool plain = h->p.newton_mode == LBM_NEWTON_PLAIN;
-  if (h->p.q == 5)
-    return h->p.storage == LBM_STORE_F32
-               ? launch_step2_t<5, float>(h, A, v, plain, two)
-               : launch_step2_t<5, double>(h, A, v, plain, two);
-  return h->p.storage == LBM_STORE_F32
-             ? launch_step2_t<9, float>(h, A, v, plain, two)
-             : launch_step2_t<9, double>(h, A, v, plain, two);
+  return step2_launch(mode_of(h->p), h->p.q, h->p.storage, A, v, two,
+                      h->stream);
 }
 
 hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
@@ -264,28 +202,16 @@ hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
   const Variant *vt = variants(h->p.q, &nv);
   // a single step under a two-step variant takes the default tiling
   const Variant &v = vt[vt[h->variant].tb ? kDefaultVariant2D : h->variant];
-  const bool plain = h->p.newton_mode == LBM_NEWTON_PLAIN;
-  const bool f32 = h->p.storage == LBM_STORE_F32;
-  switch (h->p.q) {
-    case 3:
-      return f32 ? launch_step_t<3, float>(h, A, v, plain)
-                 : launch_step_t<3, double>(h, A, v, plain);
-    case 5:
-      return f32 ? launch_step_t<5, float>(h, A, v, plain)
-                 : launch_step_t<5, double>(h, A, v, plain);
-    default:
-      return f32 ? launch_step_t<9, float>(h, A, v, plain)
-                 : launch_step_t<9, double>(h, A, v, plain);
-  }
+  return step_launch(mode_of(h->p), h->p.q, h->p.storage, A, v,
+                     v.rev && (h->steps & 1), h->stream);
 }
 
 namespace {
 
 // energy of the state `src` into h->small[kSmallEnergy] (device)
 hipError_t handle_energy_async(const lbm_stefan_t *h, const void *src) {
-  return irebm::energy_async(h->p.q, h->p.storage, src, h->p.nx * h->p.ny,
-                             h->p.t_m, h->p.delta, h->p.ste, h->partials,
-                             h->small + kSmallEnergy, h->stream);
+  return irebm::energy_async(h->p, src, h->partials, h->small + kSmallEnergy,
+                             h->stream);
 }
 
 }  // namespace
@@ -445,18 +371,7 @@ int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
   const lbm_stefan_params &p = h->p;
   double *fr = h->small + kSmallFront;
   if (front) {
-    auto r = [&](auto qt, auto tt) {
-      QS_TYPES(qt, tt);
-      const S *src = (const S *)h->buf[h->cur];
-      if (mode == LBM_FRONT_LIQUID_INTEGRAL)
-        front_integral_kernel<Q, S><<<(unsigned)p.ny, 256, 0, h->stream>>>(
-            src, p.nx * p.ny, (int)p.nx, p.t_m, 1.0 / p.delta, p.dx, fr);
-      else
-        front_crossing_kernel<Q, S><<<(unsigned)p.ny, 256, 0, h->stream>>>(
-            src, p.nx * p.ny, (int)p.nx, p.t_m, p.dx, fr);
-      return hipGetLastError();
-    };
-    HIPCHK(h, dispatch_qs(p.q, p.storage, r));
+    HIPCHK(h, front_async(p, h->buf[h->cur], mode, fr, h->stream));
     HIPCHK(h, hipMemcpyAsync(front, fr, p.ny * 8, hipMemcpyDeviceToHost,
                              h->stream));
   }
@@ -487,13 +402,7 @@ int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host) {
   } else if (what == LBM_FIELD_T) {
     // the other population buffer is free between steps (>= 12 n bytes)
     double *T = (double *)h->buf[h->cur ^ 1];
-    auto r = [&](auto qt, auto tt) {
-      QS_TYPES(qt, tt);
-      temp_kernel<Q, S><<<blocks_for(n, 256), 256, 0, h->stream>>>(
-          (const S *)h->buf[h->cur], n, T);
-      return hipGetLastError();
-    };
-    HIPCHK(h, dispatch_qs(p.q, p.storage, r));
+    HIPCHK(h, temperature_async(p, h->buf[h->cur], T, h->stream));
     HIPCHK(h, hipMemcpyAsync(host, T, n * 8, hipMemcpyDeviceToHost, h->stream));
   } else {
     return fail(h, LBM_STEFAN_EINVAL, "unknown field");

@@ -75,4 +75,79 @@ hipError_t advance(lbm_stefan_t *h, int64_t nsteps);
 hipError_t zero_stats_async(lbm_stefan_t *h);
 int read_stats(lbm_stefan_t *h, lbm_stefan_stats *st);
 
+// ---- kernel launches by node-update mode (launch.hpp; one translation
+// unit per mode instantiates them)
+
+struct Variant;
+
+// one launch over a batch's table of work items
+struct BatchLaunch {
+  const StepArgs *descs;  // device: one descriptor per instance
+  const int2 *items;      // device: (instance, item) per work item
+  int64_t nitems;
+  int cus, blocks_per_cu; // persistent grid of cus * blocks_per_cu blocks
+                          // when blocks_per_cu > 0, else one per item
+  int parity;             // 0: src -> dst of each descriptor, 1: dst -> src
+  bool two;               // two steps under a two-step variant (else one)
+};
+
+template <int MODE>
+hipError_t step_launch_mode(int q, int storage, const StepArgs &A,
+                            const Variant &v, bool reverse,
+                            hipStream_t stream);
+template <int MODE>
+hipError_t step2_launch_mode(int q, int storage, const StepArgs &A,
+                             const Variant &v, bool two, hipStream_t stream);
+template <int MODE>
+hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
+                             const Variant &v, hipStream_t stream);
+
+#define IREBM_DECLARE_MODE(M)                                              \
+  extern template hipError_t step_launch_mode<M>(                          \
+      int, int, const StepArgs &, const Variant &, bool, hipStream_t);     \
+  extern template hipError_t step2_launch_mode<M>(                         \
+      int, int, const StepArgs &, const Variant &, bool, hipStream_t);     \
+  extern template hipError_t batch_launch_mode<M>(                         \
+      int, int, const BatchLaunch &, const Variant &, hipStream_t)
+IREBM_DECLARE_MODE(kSafeguarded);
+IREBM_DECLARE_MODE(kPlain);
+IREBM_DECLARE_MODE(kEebm);
+#undef IREBM_DECLARE_MODE
+
+// node-update mode of a lattice
+inline int mode_of(const lbm_stefan_params &p) {
+  if (p.scheme == LBM_SCHEME_EEBM) return kEebm;
+  return p.newton_mode == LBM_NEWTON_PLAIN ? kPlain : kSafeguarded;
+}
+
+// one step of one lattice (one-step variant v)
+inline hipError_t step_launch(int mode, int q, int storage, const StepArgs &A,
+                              const Variant &v, bool reverse,
+                              hipStream_t stream) {
+  if (mode == kEebm)
+    return step_launch_mode<kEebm>(q, storage, A, v, reverse, stream);
+  if (mode == kPlain)
+    return step_launch_mode<kPlain>(q, storage, A, v, reverse, stream);
+  return step_launch_mode<kSafeguarded>(q, storage, A, v, reverse, stream);
+}
+
+// two steps (one if two = false) of one 2D lattice (two-step variant v)
+inline hipError_t step2_launch(int mode, int q, int storage,
+                               const StepArgs &A, const Variant &v, bool two,
+                               hipStream_t stream) {
+  if (mode == kEebm)
+    return step2_launch_mode<kEebm>(q, storage, A, v, two, stream);
+  if (mode == kPlain)
+    return step2_launch_mode<kPlain>(q, storage, A, v, two, stream);
+  return step2_launch_mode<kSafeguarded>(q, storage, A, v, two, stream);
+}
+
+inline hipError_t batch_launch(int mode, int q, int storage,
+                               const BatchLaunch &b, const Variant &v,
+                               hipStream_t stream) {
+  if (mode == kEebm) return batch_launch_mode<kEebm>(q, storage, b, v, stream);
+  if (mode == kPlain) return batch_launch_mode<kPlain>(q, storage, b, v, stream);
+  return batch_launch_mode<kSafeguarded>(q, storage, b, v, stream);
+}
+
 }  // namespace irebm

@@ -15,6 +15,7 @@ _BC = {"dirichlet": C.BC_DIRICHLET, "bounceback": C.BC_BOUNCEBACK,
        "periodic": C.BC_PERIODIC}
 _STORE = {"f64": C.STORE_F64, "f32": C.STORE_F32}
 _NEWTON = {"safeguarded": C.NEWTON_SAFEGUARDED, "plain": C.NEWTON_PLAIN}
+_SCHEME = {"irebm": C.SCHEME_IREBM, "eebm": C.SCHEME_EEBM}
 _FRONT = {"integral": C.FRONT_LIQUID_INTEGRAL,
           "crossing": C.FRONT_ZERO_CROSSING}
 
@@ -45,6 +46,8 @@ def make_params(prob, variant=-1, flags=0, strict=False):
     p.strict = 1 if strict else 0
     p.variant = variant
     p.flags = flags
+    sc = getattr(prob, "scheme", "irebm")
+    p.scheme = _SCHEME[sc] if isinstance(sc, str) else int(sc)
     return p, keep
 
 

@@ -4,6 +4,7 @@ paths return before any HIP call)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -62,6 +63,7 @@ def _ws(L, p):
     ("newton_tol", 0.0), ("newton_max_it", 0), ("newton_max_it", 1001),
     ("nx", 2), ("ny", 2), ("q", 4), ("dim", 3), ("storage", 7),
     ("newton_mode", 5), ("variant", 99), ("tau", float("nan")),
+    ("scheme", 2), ("scheme", -1),
 ])
 def test_invalid_params_rejected(L, field, value):
     p, keep = _params(L, synth.planar_2d(n=32, ny=16))
@@ -143,3 +145,49 @@ def test_batch_rejects_mixed_lattices(L):
     arr = (L.Params * 2)(a, a)
     assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.OK
     assert n.value >= 2 * 2 * 5 * 64 * 32 * 4
+
+
+def test_eebm_rejects_reverse_mode(L):
+    p, _ = _params(L, synth.planar_2d(n=32, ny=16), scheme=L.SCHEME_EEBM)
+    assert _ws(L, p)[0] == L.OK
+    p.flags = L.FLAG_ADJOINT
+    assert _ws(L, p)[0] == L.EINVAL
+    assert b"IREBM" in L.lib().lbm_stefan_last_error(None)
+
+
+def test_batch_rejects_mixed_schemes(L):
+    from paper_2505_13097_amd.stefan import make_params
+    a, _ = make_params(synth.planar_2d(n=64, ny=32))
+    b, _ = make_params(synth.planar_2d(n=64, ny=32).with_(scheme="eebm"))
+    assert b.scheme == L.SCHEME_EEBM
+    n = ctypes.c_size_t()
+    arr = (L.Params * 2)(a, b)
+    assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.EINVAL
+    arr = (L.Params * 2)(b, b)
+    assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.OK
+
+
+def test_ctypes_structs_match_header(L, tmp_path):
+    """Size and field offsets of the binding's structs equal the C ones."""
+    fields = [f for f, _ in L.Params._fields_]
+    sfields = [f for f, _ in L.Stats._fields_]
+    src = ["#include <stddef.h>", "#include <stdio.h>",
+           '#include "lbm_stefan.h"', "int main(void) {",
+           '  printf("%zu\\n", sizeof(lbm_stefan_params));',
+           '  printf("%zu\\n", sizeof(lbm_stefan_stats));']
+    src += [f'  printf("%zu\\n", offsetof(lbm_stefan_params, {f}));'
+            for f in fields]
+    src += [f'  printf("%zu\\n", offsetof(lbm_stefan_stats, {f}));'
+            for f in sfields]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o",
+                    str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True,
+                                          text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(L.Params), ctypes.sizeof(L.Stats)]
+    want += [getattr(L.Params, f).offset for f in fields]
+    want += [getattr(L.Stats, f).offset for f in sfields]
+    assert out == want
