@@ -23,10 +23,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SOURCES = ("irebm.c", "irebm_cs.c", "eebm.c")
 
-DIRICHLET, BOUNCEBACK, PERIODIC = 0, 1, 2
+DIRICHLET, BOUNCEBACK, PERIODIC, NEUMANN = 0, 1, 2, 3
 SAFEGUARDED, PLAIN = 0, 1
 FRONT_INTEGRAL, FRONT_CROSSING = 0, 1
-_BC = {"dirichlet": DIRICHLET, "bounceback": BOUNCEBACK, "periodic": PERIODIC}
+_BC = {"dirichlet": DIRICHLET, "bounceback": BOUNCEBACK, "periodic": PERIODIC,
+       "neumann": NEUMANN}
 _NEWTON = {"safeguarded": SAFEGUARDED, "plain": PLAIN}
 
 

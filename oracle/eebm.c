@@ -16,7 +16,8 @@
  * collision towards f^eq followed by pull streaming, with the boundary
  * closures of the IREBM oracle applied to the streamed populations, the
  * Dirichlet target being the wall enthalpy T_D + l(T_D)/Ste (l = 1 above
- * T_m, 0 at or below it).
+ * T_m, 0 at or below it) and the Neumann target the enthalpy streamed
+ * into the mirror node.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -47,8 +48,15 @@ static int check(const orc_params *p, lat *L) {
   if (!p || !(p->tau > 0.5) || !(p->ste > 0)) return -1;
   if (p->nx < 3 || p->ny < 1 || (p->dim == 2 && p->ny < 3)) return -1;
   if (p->dim == 1 && p->ny != 1) return -1;
-  for (int k = 0; k < 4; k++)
-    if (p->bc[k] < ORC_DIRICHLET || p->bc[k] > ORC_PERIODIC) return -1;
+  int neu = 0, bb = 0;
+  for (int k = 0; k < 4; k++) {
+    if (p->bc[k] < ORC_DIRICHLET || p->bc[k] > ORC_NEUMANN) return -1;
+    if (p->dim == 2 || k < 2) {
+      neu |= p->bc[k] == ORC_NEUMANN;
+      bb |= p->bc[k] == ORC_BOUNCEBACK;
+    }
+  }
+  if (neu && bb) return -1;
   if ((p->bc[0] == ORC_PERIODIC) != (p->bc[1] == ORC_PERIODIC)) return -1;
   if (p->dim == 2 && (p->bc[2] == ORC_PERIODIC) != (p->bc[3] == ORC_PERIODIC))
     return -1;
@@ -66,6 +74,21 @@ static int dirichlet_wall(const orc_params *p, long x, long y) {
 static double wall_value(const orc_params *p, int wall, long x, long y) {
   if (p->wall_profile[wall]) return p->wall_profile[wall][wall < 2 ? y : x];
   return p->wall_T[wall];
+}
+
+/* the interior neighbour across the Neumann walls of node (x, y) (the
+   diagonal one at the corner of two); 0 when on no Neumann wall */
+static int neumann_mirror(const orc_params *p, long x, long y, long *mx,
+                          long *my) {
+  long dx = 0, dy = 0;
+  if (x == 0 && p->bc[0] == ORC_NEUMANN) dx = 1;
+  if (x == p->nx - 1 && p->bc[1] == ORC_NEUMANN) dx = -1;
+  if (p->dim == 2 && y == 0 && p->bc[2] == ORC_NEUMANN) dy = 1;
+  if (p->dim == 2 && y == p->ny - 1 && p->bc[3] == ORC_NEUMANN) dy = -1;
+  if (dx == 0 && dy == 0) return 0;
+  *mx = x + dx;
+  *my = y + dy;
+  return 1;
 }
 
 /* pull source x - e of node (x, y), wrapped on periodic axes; 0 outside */
@@ -171,6 +194,26 @@ static void step(const orc_params *p, const lat *L, const double *f,
         if (wall >= 0) {
           const double TD = wall_value(p, wall, x, y);
           double D = TD + lf_of_T(TD, p->tm) / p->ste, wu = 0.0;
+          for (int i = 0; i < p->q; i++) {
+            if (set[i]) D -= g[i];
+            else wu += L->w[i];
+          }
+          for (int i = 0; i < p->q; i++)
+            if (!set[i]) {
+              g[i] = D * (L->w[i] / wu);
+              set[i] = 1;
+              *fin += g[i];
+            }
+        }
+        long mx, my;
+        if (wall < 0 && neumann_mirror(p, x, y, &mx, &my)) {
+          /* the enthalpy streamed into the mirror node */
+          double D = 0.0, wu = 0.0;
+          for (int i = 0; i < p->q; i++) {
+            long sx = mx, sy = my;   /* always a lattice node (check) */
+            source(p, mx, my, L->ex[i], L->ey[i], &sx, &sy);
+            D += omega[i * n + sy * nx + sx];
+          }
           for (int i = 0; i < p->q; i++) {
             if (set[i]) D -= g[i];
             else wu += L->w[i];

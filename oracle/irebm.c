@@ -18,6 +18,14 @@
 #define CS 0
 #include "irebm_body.h"
 
+/* The reverse step below transposes the Dirichlet, bounce-back and
+   periodic closures only. */
+static int has_neumann(const orc_params *p) {
+  for (int k = 0; k < (p->dim == 2 ? 4 : 2); k++)
+    if (p->bc[k] == ORC_NEUMANN) return 1;
+  return 0;
+}
+
 static void fill_vals(const orc_params *p, r_vals *v) {
   v->ste = p->ste;
   v->delta = p->delta;
@@ -364,7 +372,7 @@ static void adj_step(const orc_params *p, const r_vals *v, const double *f,
 int orc_adjoint_step(const orc_params *p, const double *f,
                      const double *gbar, double *fbar, double *g_wall,
                      double *g_ste, double *g_delta) {
-  if (r_check(p)) return -1;
+  if (r_check(p) || has_neumann(p)) return -1;
   const long n = p->nx * p->ny;
   double *th = malloc(sizeof(double) * n), *thb = malloc(sizeof(double) * n);
   double *om = malloc(sizeof(double) * p->q * n);
@@ -390,7 +398,7 @@ int orc_adjoint_step(const orc_params *p, const double *f,
 int orc_front_loss_grad(const orc_params *p, const double *T0, long nsteps,
                         const double *target, double *loss, double *g_wall,
                         double *g_ste, double *g_delta) {
-  if (r_check(p) || nsteps < 0 || !target) return -1;
+  if (r_check(p) || has_neumann(p) || nsteps < 0 || !target) return -1;
   const long nx = p->nx, ny = p->ny, n = nx * ny, qn = p->q * n;
   double *F = malloc(sizeof(double) * qn * (nsteps + 1));
   double *gb = malloc(sizeof(double) * qn), *fb = malloc(sizeof(double) * qn);

@@ -156,8 +156,15 @@ static int RN(check)(const orc_params *p) {
   if (!(p->tol > 0.0) || p->max_it < 1) return -1;
   if (p->newton_mode != ORC_SAFEGUARDED && p->newton_mode != ORC_PLAIN)
     return -1;
-  for (int k = 0; k < 4; k++)
-    if (p->bc[k] < ORC_DIRICHLET || p->bc[k] > ORC_PERIODIC) return -1;
+  int neu = 0, bb = 0;
+  for (int k = 0; k < 4; k++) {
+    if (p->bc[k] < ORC_DIRICHLET || p->bc[k] > ORC_NEUMANN) return -1;
+    if (p->dim == 2 || k < 2) {
+      neu |= p->bc[k] == ORC_NEUMANN;
+      bb |= p->bc[k] == ORC_BOUNCEBACK;
+    }
+  }
+  if (neu && bb) return -1;
   if ((p->bc[0] == ORC_PERIODIC) != (p->bc[1] == ORC_PERIODIC)) return -1;
   if (p->dim == 2 && (p->bc[2] == ORC_PERIODIC) != (p->bc[3] == ORC_PERIODIC))
     return -1;
@@ -177,6 +184,23 @@ static int RN(dirichlet_wall)(const orc_params *p, long x, long y) {
 static R RN(wall_value)(const RN(vals) *v, int wall, long x, long y) {
   if (v->wall_profile[wall]) return v->wall_profile[wall][wall < 2 ? y : x];
   return v->wall_T[wall];
+}
+
+/* Mirror node of a node on Neumann walls (Section 4.2, eq. Neu_on_q):
+   the node moved one cell inward across each Neumann wall it lies on
+   (at the corner of two, the diagonal neighbour).  Returns 0 when the
+   node lies on no Neumann wall. */
+static int RN(neumann_mirror)(const orc_params *p, long x, long y, long *mx,
+                              long *my) {
+  long dx = 0, dy = 0;
+  if (x == 0 && p->bc[0] == ORC_NEUMANN) dx = 1;
+  if (x == p->nx - 1 && p->bc[1] == ORC_NEUMANN) dx = -1;
+  if (p->dim == 2 && y == 0 && p->bc[2] == ORC_NEUMANN) dy = 1;
+  if (p->dim == 2 && y == p->ny - 1 && p->bc[3] == ORC_NEUMANN) dy = -1;
+  if (dx == 0 && dy == 0) return 0;
+  *mx = x + dx;
+  *my = y + dy;
+  return 1;
 }
 
 /* Source node of the pull x - e_i, wrapped on periodic axes.  Returns 0
@@ -221,7 +245,12 @@ static int RN(leaves_by_bounceback)(const orc_params *p, long x, long y,
  *      q_i known so far) is shared among the remaining unknowns in
  *      proportion to w_i (for D1Q3 and flat D2Q5 walls there is one such
  *      unknown and it takes all of D).
- *   3. Any unknown still left (corner of two bounce-back walls, where the
+ *   3. Neumann node (Section 4.2, eq. Neu_on_q): M0(q) must equal M0(q)
+ *      at the mirror node (the interior neighbour across the Neumann
+ *      walls, neumann_mirror), whose pulled populations are all known;
+ *      the deficit is shared among the unknowns in proportion to w_i
+ *      (one unknown on flat D2Q5 and D1Q3 walls: eq. Neu_on_q itself).
+ *   4. Any unknown still left (corner of two bounce-back walls, where the
  *      opposite is unknown too) takes the node's own post-collision
  *      population Omega_opp(i)(x).
  * Reports the closure-filled sum to *fill.
@@ -253,6 +282,29 @@ static void RN(pull_close)(const orc_params *p, const RN(vals) *v,
     R target = TD + (RN(phi_)(TD, p->tm, v->delta) -
                      RN(phi_)(theta[n], p->tm, v->delta)) / v->ste;
     R D = target;
+    double wu = 0.0;
+    for (int i = 0; i < p->q; i++) {
+      if (set[i]) D -= q[i];
+      else wu += L->w[i];
+    }
+    for (int i = 0; i < p->q; i++)
+      if (!set[i]) {
+        q[i] = D * (L->w[i] / wu);
+        set[i] = 1;
+        *fill += q[i];
+      }
+  }
+  long mx, my;
+  if (wall < 0 && RN(neumann_mirror)(p, x, y, &mx, &my)) {
+    /* every pull of the mirror is a lattice node: the mirror is one cell
+       inside each Neumann wall of the node, and check() admits no
+       bounce-back wall beside a Neumann one (periodic axes wrap) */
+    R D = 0.0;
+    for (int i = 0; i < p->q; i++) {
+      long sx = mx, sy = my;
+      RN(source)(p, mx, my, L->ex[i], L->ey[i], &sx, &sy);
+      D += omega[(i * ny + sy) * nx + sx];
+    }
     double wu = 0.0;
     for (int i = 0; i < p->q; i++) {
       if (set[i]) D -= q[i];

@@ -21,7 +21,10 @@
 extern "C" {
 #endif
 
-enum { ORC_DIRICHLET = 0, ORC_BOUNCEBACK = 1, ORC_PERIODIC = 2 };
+/* wall kinds; Neumann (eq. Neu_on_q) and bounce-back walls do not mix in
+   one lattice */
+enum { ORC_DIRICHLET = 0, ORC_BOUNCEBACK = 1, ORC_PERIODIC = 2,
+       ORC_NEUMANN = 3 };
 enum { ORC_SAFEGUARDED = 0, ORC_PLAIN = 1 };
 enum { ORC_FRONT_INTEGRAL = 0, ORC_FRONT_CROSSING = 1 };
 

@@ -26,7 +26,7 @@ import numpy as np
 
 DEFAULT_SEED = 20250519
 
-BC_NAMES = ("dirichlet", "bounceback", "periodic")
+BC_NAMES = ("dirichlet", "bounceback", "periodic", "neumann")
 
 
 @dataclass
@@ -125,6 +125,32 @@ def cavity_2d(n=8192, ny=None, nsteps=2000, seed=DEFAULT_SEED,
                    wall_T=(1.0, -0.5, 0.0, 0.0), tol=1e-12, max_it=32,
                    storage=storage, T0=-0.5, nsteps=nsteps,
                    name=f"cavity2d_d2q9_{storage}_{n}x{ny}")
+
+
+# the 2D case of Section 6.2 in scaled units: lengths in L = 1 m,
+# temperatures in T_i - T_f = 10 K from T_f = 0, time in L^2/alpha
+FREEZE_STE = 1.762 * 10.0 / 338.0          # c (T_i - T_f) / h_sl = 0.0521
+FREEZE_T_END = 20.0 * 3600.0 * 1.26e-6     # 20 h, alpha = 1.26e-6 m^2/s
+FREEZE_SIDE = 4.0                          # quarter of the 8 m cavity
+
+
+def freezing_cavity_2d(n=201, q=5, storage="f64", scheme="irebm",
+                       delta=0.02, tau=0.84, t_end=FREEZE_T_END):
+    """The paper's 2D case (Section 6.2): the lower-left quarter of a
+    square cavity of water at 10 C cooled to -20 C on all sides.  A 4 x 4
+    square of n x n nodes (dx = 4/(n - 1)), Dirichlet -2 on the x- and y-
+    walls, homogeneous Neumann (symmetry, eq. Neu_on_q) on x+ and y+,
+    liquid at +1 initially, Ste 0.0521, delta 0.02, tau 0.84; the step
+    count reaches t_end (20 h by default) with dt = (tau - 1/2) dx^2 / 3."""
+    dx = FREEZE_SIDE / (n - 1)
+    dt = (tau - 0.5) * dx * dx / 3.0
+    return Problem(dim=2, q=q, nx=n, ny=n, tau=tau, ste=FREEZE_STE,
+                   delta=delta,
+                   bc=("dirichlet", "neumann", "dirichlet", "neumann"),
+                   wall_T=(-2.0, 0.0, -2.0, 0.0), tol=1e-12, max_it=32,
+                   storage=storage, T0=np.ones((n, n)),
+                   nsteps=int(round(t_end / dt)), dx=dx, scheme=scheme,
+                   name=f"freeze2d_d2q{q}_{scheme}_{storage}_{n}")
 
 
 def batch_table(count=512, seed=DEFAULT_SEED, sizes=None, nsteps=5000,
