@@ -156,13 +156,13 @@ def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
     }
 
 
-def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step):
+def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1):
     """The explicit enthalpy based method (Algorithm 2) on the same
     lattice, same kernels and state layout, no Newton solve; the paper's
     timing tables report the IREBM/EEBM time ratio."""
     from paper_2505_13097_amd import variant_names
     pe = prob.with_(scheme="eebm", name=prob.name + "_eebm")
-    r = time_plain(pe, steps, warmup, -1, autotune=autotune)
+    r = time_plain(pe, steps, warmup, variant, autotune=autotune)
     v = r["variant"] if r["variant"] >= 0 else (0 if pe.q == 3 else 3)
     vname = variant_names(pe.q, pe.storage)[v]
     spl = steps_per_launch(vname)
@@ -178,6 +178,38 @@ def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step):
         "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
         "time_ratio_irebm_to_eebm": round(irebm_ms_per_step / ms, 3),
     }
+
+
+def time_freezing(sizes=(201, 401, 801)):
+    """The paper's 2D freezing case (Section 6.2) run to t = 20 h, D2Q5 and
+    D2Q9, EEBM and IREBM, FP64 populations: the configuration of the
+    paper's 2D timing table, whose IREBM/EEBM ratio is reported beside the
+    times (one launch per step: these lattices are small, so the launches,
+    not HBM, bound them)."""
+    import torch
+    from paper_2505_13097_amd import Stefan
+    import synth as S
+    rows = []
+    for q in (5, 9):
+        for n in sizes:
+            r = {"lattice": f"D2Q{q}", "N": n}
+            for scheme in ("eebm", "irebm"):
+                p = S.freezing_cavity_2d(n=n, q=q, scheme=scheme)
+                g = Stefan(p)
+                g.step(20)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.step(p.nsteps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                g.close()
+                r["steps"] = p.nsteps
+                r[f"{scheme}_s"] = round(dt, 4)
+                r[f"{scheme}_glups"] = round(p.nodes * p.nsteps / dt / 1e9, 2)
+            r["ratio_irebm_to_eebm"] = round(r["irebm_s"] / r["eebm_s"], 3)
+            rows.append(r)
+    return {"workload": "freeze2d_quarter_cavity_f64_20h",
+            "unit": "s per run to 20 h", "runs": rows}
 
 
 def time_adjoint(prob, interval, autotune=True):
@@ -266,9 +298,17 @@ def summarize_profiles(run, args):
     import synth
     from paper_2505_13097_amd import variant_names
 
+    import re
+
     def short(n):
-        n = n.replace("(anonymous namespace)::", "")
+        n = n.replace("(anonymous namespace)::", "").replace("irebm::", "")
         return n.split("(")[0].replace("void ", "")
+
+    def step_kernel_of(k, mode):
+        """k is a single-lattice step kernel of this lattice in node-update
+        mode `mode` (0: IREBM safeguarded Newton, 2: EEBM)."""
+        return re.match(rf"(step2_kernel<{prob.q}, float, {mode},|"
+                        rf"step_kernel<{prob.q}, float, \d, {mode},)", k)
 
     def db(sub):
         d = os.path.join(run, sub)
@@ -281,8 +321,6 @@ def summarize_profiles(run, args):
     V, BV, BB = args.variant, args.batch_variant, args.batch_bpc
     vname, bvname = names[V], bnames[BV]
     spl = steps_per_launch(vname)
-    step_prefix = (f"irebm::step2_kernel<{prob.q}, float" if spl == 2 else
-                   f"irebm::step_kernel<{prob.q}, float")
     launches = args.steps // spl
 
     c = db("prof_all")
@@ -293,9 +331,15 @@ def summarize_profiles(run, args):
     for name, d in c.execute("select name, duration from kernels "
                              "order by dispatch_id"):
         by[short(name)].append(d / 1000.0)          # ns -> us
-    step_us = by[[k for k in by if k.startswith(step_prefix)][0]]
+    kname = "step2_kernel" if spl == 2 else "step_kernel"
+    step_us = by[[k for k in by if step_kernel_of(k, 0) and
+                  k.startswith(kname + "<")][0]]
     # the timed launches are the last ones of the step kernel
     step_avg = sum(step_us[-launches:]) / launches
+    eebm_k = [k for k in by if step_kernel_of(k, 2) and
+              k.startswith(kname + "<")]
+    eebm_avg = (sum(by[eebm_k[0]][-launches:]) / launches
+                if eebm_k and len(by[eebm_k[0]]) >= launches else None)
     bat = [k for k in by if k.startswith("batch_step_kernel<5, float") or
            k.startswith("batch_persistent_kernel<5, float")][0]
     bat_avg = sum(by[bat][-args.batch_steps:]) / args.batch_steps
@@ -312,8 +356,7 @@ def summarize_profiles(run, args):
     copy_w = max(v for k, v in W if "copyBuffer" in k)
     fs, ws = gib_kib / copy_f, gib_kib / copy_w
     def is_step(k):
-        return (k.startswith(f"irebm::step_kernel<{prob.q}, float") or
-                k.startswith(f"irebm::step2_kernel<{prob.q}, float"))
+        return step_kernel_of(k, 0) is not None
     sf = [v for k, v in F if is_step(k)]
     sw = [v for k, v in W if is_step(k)]
     counts = [SWEEP_STEPS // steps_per_launch(nm) for nm in names]
@@ -392,6 +435,20 @@ def summarize_profiles(run, args):
     fn = f"step_kernel_{args.workload}{prob.nx}_d2q{prob.q}_f32.md"
     with open(os.path.join(out, fn), "w") as f:
         f.write("\n".join(lines))
+    if eebm_avg is not None:
+        fe = f"step_kernel_{args.workload}{prob.nx}_d2q{prob.q}_f32_eebm.md"
+        with open(os.path.join(out, fe), "w") as f:
+            f.write("\n".join([
+                f"# {eebm_k[0]} — {prob.nx} x {prob.ny} D2Q{prob.q} "
+                f"{args.workload}, explicit scheme (Algorithm 2), FP32 "
+                f"populations (variant {vname})", "",
+                f"Same kernel trace as {fn} (the bench's eebm form, same "
+                "variant, same step count).", "",
+                f"The {launches} timed launches ({spl} step(s) each) average "
+                f"{eebm_avg:.1f} us, against {cav:.1f} us for the IREBM "
+                f"kernel (time ratio IREBM/EEBM {cav / eebm_avg:.3f}); "
+                f"algorithmic bytes per launch {alg * spl / 1e9:.4f} GB -> "
+                f"{alg * spl / (eebm_avg * 1e-6) / 1e9:.0f} GB/s.", ""]))
     with open(os.path.join(out, "batch_step_kernel_batch512_d2q5_f32.md"), "w") as f:
         f.write("\n".join([
             f"# {bat.split('<')[0]} — {args.batch_count} D2Q5 instances "
@@ -450,9 +507,9 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,adjoint,eebm",
+    ap.add_argument("--forms", default="plain,batched,adjoint,eebm,freezing",
                     help="comma list of extra forms to time: batched, "
-                         "adjoint, eebm")
+                         "adjoint, eebm, freezing")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-variant", type=int, default=-1)
@@ -589,8 +646,13 @@ def main():
     if "eebm" in args.forms.split(","):
         print("[bench] eebm form", file=sys.stderr, flush=True)
         forms["eebm"] = time_eebm(prob, args.steps, args.warmup,
-                                  not args.no_autotune, ms_per_step)
+                                  not args.no_autotune, ms_per_step,
+                                  variant=args.variant)
         print("[bench] eebm done", file=sys.stderr, flush=True)
+    if "freezing" in args.forms.split(","):
+        print("[bench] freezing form", file=sys.stderr, flush=True)
+        forms["freezing"] = time_freezing()
+        print("[bench] freezing done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

@@ -68,6 +68,15 @@ extern "C" {
 #define LBM_BC_DIRICHLET 0   /* eq. Dir_on_q: fixes the wall temperature */
 #define LBM_BC_BOUNCEBACK 1  /* q_i = q_opp(i): homogeneous Neumann */
 #define LBM_BC_PERIODIC 2    /* both walls of the axis must be periodic */
+#define LBM_BC_NEUMANN 3     /* eq. Neu_on_q: homogeneous Neumann by copying
+                                the zeroth moment of the pulled populations
+                                of the interior neighbour across the wall
+                                (the diagonal one at the corner of two
+                                Neumann walls; several unknowns share by
+                                weight).  Not beside a bounce-back wall in
+                                one lattice; such lattices take one step
+                                per launch (two-step variants run as the
+                                default one) and have no reverse mode. */
 
 /* population storage */
 #define LBM_STORE_F64 0
@@ -176,8 +185,8 @@ int lbm_stefan_workspace_bytes(const lbm_stefan_params *p, size_t *bytes);
  * tau <= 1/2, Ste <= 0, delta <= 0, tol <= 0, max_it outside 1..1000,
  * nx < 3, ny < 3 in 2D or != 1 in 1D, lattice/dim mismatch, a periodic
  * axis with one non-periodic wall, workspace too small or misaligned,
- * unknown variant or scheme, LBM_FLAG_ADJOINT with LBM_SCHEME_EEBM),
- * EDEVICE.
+ * unknown variant or scheme, LBM_FLAG_ADJOINT with LBM_SCHEME_EEBM or
+ * a Neumann wall, Neumann and bounce-back walls in one lattice), EDEVICE.
  */
 int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
                     void *workspace, size_t bytes, void *stream,
@@ -352,7 +361,7 @@ typedef struct lbm_stefan_batch lbm_stefan_batch_t;
 
 /* Workspace for `count` instances (params array of length count).
    Errors: EINVAL (an invalid instance, mixed q/storage/newton_mode/
-   scheme). */
+   scheme, an instance with a Neumann wall). */
 int lbm_stefan_batch_workspace_bytes(const lbm_stefan_params *params,
                                      int32_t count, size_t *bytes);
 

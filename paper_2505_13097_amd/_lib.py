@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_stefan.so")
 
 OK, EINVAL, EDEVICE, ENOTCONV, ENAN = 0, -1, -2, -3, -4
-BC_DIRICHLET, BC_BOUNCEBACK, BC_PERIODIC = 0, 1, 2
+BC_DIRICHLET, BC_BOUNCEBACK, BC_PERIODIC, BC_NEUMANN = 0, 1, 2, 3
 STORE_F64, STORE_F32 = 0, 1
 NEWTON_SAFEGUARDED, NEWTON_PLAIN = 0, 1
 FRONT_LIQUID_INTEGRAL, FRONT_ZERO_CROSSING = 0, 1

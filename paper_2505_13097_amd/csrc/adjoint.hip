@@ -108,7 +108,8 @@ __device__ __forceinline__ void local_reverse(const AdjArgs &G, int x, int y,
 #pragma unroll
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
   CloseInfo ci;
-  if (L.known != (1u << Q) - 1u) close_node<Q>(A, x, y, th, om, q, L.known, &ci);
+  if (L.known != (1u << Q) - 1u)
+    close_node<Q>(A, x, y, th, om, q, L.known, 0.0, &ci);
   double m0 = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) m0 += q[i];

@@ -87,6 +87,9 @@ std::string validate_batch(const lbm_stefan_params *ps, int32_t count) {
         ps[k].newton_mode != ps[0].newton_mode ||
         ps[k].scheme != ps[0].scheme)
       return "instances must share lattice, storage, newton_mode and scheme";
+    if (has_neumann(ps[k]))
+      return "instance " + std::to_string(k) +
+             ": the batched form has no Neumann closure";
   }
   return "";
 }
@@ -357,10 +360,10 @@ int lbm_stefan_batch_set_schedule(lbm_stefan_batch_t *b, int32_t variant,
   if (graph_steps < 0 || graph_steps % 2 || graph_steps > 100000)
     return bfail(b, LBM_STEFAN_EINVAL,
                  "graph_steps must be even and in 0..100000");
-  DeviceGuard g(b->device);
   const int nvar = variant < 0 ? (b->q == 3 ? kDefaultVariant1D
                                             : kDefaultVariant2D)
                                : variant;
+  DeviceGuard g(b->device);
   b->blocks_per_cu = blocks_per_cu;
   b->graph_steps = graph_steps;
   drop_graphs(b);

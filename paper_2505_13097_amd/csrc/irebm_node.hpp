@@ -62,11 +62,15 @@ __host__ __device__ constexpr int opp(int i) {
                 : (i - 3) % 4 + 5;
 }
 
-enum { BC_DIRICHLET = 0, BC_BOUNCEBACK = 1, BC_PERIODIC = 2 };
+enum { BC_DIRICHLET = 0, BC_BOUNCEBACK = 1, BC_PERIODIC = 2, BC_NEUMANN = 3 };
 
 // node update of a kernel instance: IREBM with the safeguarded or the
-// printed Newton update (Algorithm 3), or the explicit scheme (Algorithm 2)
-enum Mode : int { kSafeguarded = 0, kPlain = 1, kEebm = 2 };
+// printed Newton update (Algorithm 3), or the explicit scheme (Algorithm 2);
+// kNeumann added to a mode compiles the Neumann closure (one-step kernels
+// of lattices with a Neumann wall; every other kernel is built without it)
+enum Mode : int { kSafeguarded = 0, kPlain = 1, kEebm = 2, kNeumann = 4 };
+constexpr int base_mode(int m) { return m & 3; }
+constexpr bool neumann_mode(int m) { return (m & kNeumann) != 0; }
 enum { SCHEME_IREBM = 0, SCHEME_EEBM = 1 };
 
 // Per-tile statistics slot, accumulated across steps by the one block
@@ -91,6 +95,7 @@ struct StepArgs {
   int32_t reverse;      // sweep the tiles in reverse order
   int32_t periodic_x, periodic_y;
   int32_t scheme;       // SCHEME_IREBM or SCHEME_EEBM
+  int32_t neu;          // bit k: wall k (x-, x+, y-, y+) is a Neumann wall
   double a;             // 1 - 1/tau
   double inv_tau;       // 1/tau
   double wtau[9];       // w_i / tau
@@ -234,7 +239,47 @@ struct NodeLoad {
   S pull[Q];
   uint32_t known;   // bit i: pull source of direction i is a lattice node
   uint32_t out;     // bit i: destination x + e_i leaves the lattice
+  double mirror;    // on a Neumann wall: M0 of the pulls at the mirror node
 };
+
+// Mirror node of (x, y) across the Neumann walls it lies on (eq.
+// Neu_on_q): one cell inward across each, the diagonal neighbour at the
+// corner of two.  Returns false when the node lies on no Neumann wall.
+template <int Q>
+__device__ __forceinline__ bool neumann_mirror(const StepArgs &A, int x, int y,
+                                               int &mx, int &my) {
+  mx = x;
+  my = y;
+  const int neu = A.neu;
+  if (!neu) return false;
+  bool on = false;
+  if ((neu & 1) && x == 0) { mx = 1; on = true; }
+  if ((neu & 2) && x == A.nx - 1) { mx = A.nx - 2; on = true; }
+  if (Q > 3 && (neu & 4) && y == 0) { my = 1; on = true; }
+  if (Q > 3 && (neu & 8) && y == A.ny - 1) { my = A.ny - 2; on = true; }
+  return on;
+}
+
+// M0 of the pulled populations at the mirror node (mx, my), sum_i
+// Omega_i(m - e_i).  The host admits no bounce-back wall beside a Neumann
+// one, so every source is a lattice node (periodic axes wrap); the
+// indices are clamped all the same so that no load leaves the planes.
+template <int Q, typename S>
+__device__ __forceinline__ double mirror_m0(const StepArgs &A,
+                                            const S *__restrict__ src, int mx,
+                                            int my) {
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int sx = mx - cx<Q>(i), sy = my - cy<Q>(i);
+    if (sx < 0) sx = A.periodic_x ? sx + A.nx : 0;
+    if (sx >= A.nx) sx = A.periodic_x ? sx - A.nx : A.nx - 1;
+    if (sy < 0) sy = A.periodic_y ? sy + A.ny : 0;
+    if (sy >= A.ny) sy = A.periodic_y ? sy - A.ny : A.ny - 1;
+    m += (double)src[i * A.plane + (int64_t)sy * A.nx + sx];
+  }
+  return m;
+}
 
 // FAST: every pull source and destination of the node lies inside the
 // lattice without wrapping (interior tile); no checks are compiled.
@@ -242,7 +287,7 @@ struct NodeLoad {
 // lattice elsewhere, so every load is issued unconditionally (no branch
 // around a load); the values of unknown directions are then zeroed and
 // left to the closure.
-template <int Q, typename S, bool FAST>
+template <int Q, typename S, bool FAST, bool NEU = false>
 __device__ __forceinline__ void load_node(const StepArgs &A,
                                           const S *__restrict__ src, int x,
                                           int y, NodeLoad<Q, S> &L) {
@@ -299,6 +344,12 @@ __device__ __forceinline__ void load_node(const StepArgs &A,
       L.known |= 1u << i;
     }
   }
+  L.mirror = 0.0;
+  if (!FAST && NEU) {
+    int mx, my;
+    if (neumann_mirror<Q>(A, x, y, mx, my))
+      L.mirror = mirror_m0<Q, S>(A, src, mx, my);
+  }
 }
 
 // Does the unknown direction i of node (x, y) leave the lattice only
@@ -337,7 +388,10 @@ __device__ __forceinline__ double wall_value(const StepArgs &A, int wall, int x,
 //    temperature is T_D; the deficit is shared by weight among the
 //    remaining unknowns.  EEBM: the zeroth moment is the wall enthalpy
 //    T_D + l(T_D)/Ste (l = 1 above T_m, else 0), whose Theta is T_D;
-// 3. anything left (corner of two bounce-back walls): own Omega_opp(i).
+// 3. on a Neumann node (not Dirichlet), M0(q) is set to M0 of the pulls
+//    at the mirror node (eq. Neu_on_q; `mirror`), the deficit shared by
+//    weight among the remaining unknowns (one on flat D2Q5/D1Q3 walls);
+// 4. anything left (corner of two bounce-back walls): own Omega_opp(i).
 // Masks of how each unknown was closed (for the reverse mode).
 struct CloseInfo {
   uint32_t bb = 0;     // bounce-back from a known opposite
@@ -347,10 +401,11 @@ struct CloseInfo {
   double TD = 0.0, wu = 0.0;
 };
 
-template <int Q, bool EEBM = false>
+template <int Q, bool EEBM = false, bool NEU = true>
 __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
                                     double th, const double *om, double *q,
-                                    uint32_t known, CloseInfo *ci = nullptr) {
+                                    uint32_t known, double mirror,
+                                    CloseInfo *ci = nullptr) {
   uint32_t set = known;
   double fill = 0.0;
 #pragma unroll
@@ -389,6 +444,23 @@ __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
       ci->wu = wu;
     }
     set = (1u << Q) - 1u;
+  } else if (NEU) {
+    int mx, my;
+    if (neumann_mirror<Q>(A, x, y, mx, my)) {
+      double D = mirror, wu = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (set >> i & 1u) D -= q[i];
+        else wu += wt<Q>(i);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (!(set >> i & 1u)) {
+          q[i] = D * (wt<Q>(i) / wu);
+          fill += q[i];
+        }
+      set = (1u << Q) - 1u;
+    }
   }
 #pragma unroll
   for (int i = 1; i < Q; ++i)
@@ -430,8 +502,9 @@ template <int Q, typename S, int MODE, bool FAST>
 __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
                                               const NodeLoad<Q, S> &L,
                                               NodeStats &st, S v[Q]) {
-  constexpr bool PLAIN = MODE == kPlain;
-  constexpr bool EEBM = MODE == kEebm;
+  constexpr bool PLAIN = base_mode(MODE) == kPlain;
+  constexpr bool EEBM = base_mode(MODE) == kEebm;
+  constexpr bool NEU = neumann_mode(MODE);
   double om[Q], q[Q];
   double th = 0.0;
 #pragma unroll
@@ -443,7 +516,8 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
   if (!FAST) {
     if (L.known != (1u << Q) - 1u)
-      st.flux_in += close_node<Q, EEBM>(A, x, y, th, om, q, L.known);
+      st.flux_in += close_node<Q, EEBM, NEU>(A, x, y, th, om, q, L.known,
+                                             L.mirror);
     if (L.out) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)

@@ -114,7 +114,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
       const int x = x0 + (int)threadIdx.x + k * bx;
       if (x < A.nx && y < A.ny) {
         NodeLoad<Q, S> L;
-        load_node<Q, S, false>(A, src, x, y, L);
+        load_node<Q, S, false, neumann_mode(MODE)>(A, src, x, y, L);
         update_node<Q, S, MODE, false, NT>(A, dst, x, y, L, st);
       }
     }
@@ -200,6 +200,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
 // NodeLoad of node (x, y) (lattice coordinates) from a ring of rows in
 // LDS: column t of the window, ring slot of row r at (r - base) % RING.
 // INNER: every pull source is a lattice node and nothing leaves (no masks).
+// The Neumann closure reads two cells away, beyond the ring's reach, so
+// lattices with a Neumann wall never take the two-step kernel (host).
 template <int Q, typename S, int RING, int WIN, bool INNER>
 __device__ __forceinline__ void load_ring(const StepArgs &A,
                                           const S (*ring)[Q][WIN],
@@ -211,6 +213,7 @@ __device__ __forceinline__ void load_ring(const StepArgs &A,
   } else {
     node_masks<Q>(A, x, y, L.known, L.out);
   }
+  L.mirror = 0.0;
   const unsigned so = (unsigned)(r - base) % RING;
 #pragma unroll
   for (int j = 0; j < Q; ++j) L.own[j] = ring[so][j][t];

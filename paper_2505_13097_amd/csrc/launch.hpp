@@ -1,9 +1,10 @@
 // launch.hpp -- launches of the time-step kernels for one node-update
 // mode (safeguarded or printed Newton, or the explicit scheme).  Each
 // mode's kernels are instantiated by small translation units of their own
-// (k_step_<mode>.hip, k_batch_<mode>.hip), so the library's units compile
-// in parallel; host code reaches them through step_launch, step2_launch
-// and batch_launch (lbm_stefan_internal.hpp).
+// (k_step_<mode>.hip, k_batch_<mode>.hip, and k_step_<mode>_neumann.hip for
+// the one-step kernels of lattices with a Neumann wall), so the library's
+// units compile in parallel; host code reaches them through step_launch,
+// step2_launch and batch_launch (lbm_stefan_internal.hpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -223,6 +224,11 @@ hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
       int, int, const irebm::StepArgs &, const irebm::Variant &, bool,     \
       hipStream_t);                                                        \
   template hipError_t irebm::step2_launch_mode<M>(                         \
+      int, int, const irebm::StepArgs &, const irebm::Variant &, bool,     \
+      hipStream_t)
+
+#define IREBM_INSTANTIATE_STEP1(M)                                         \
+  template hipError_t irebm::step_launch_mode<M>(                          \
       int, int, const irebm::StepArgs &, const irebm::Variant &, bool,     \
       hipStream_t)
 

@@ -61,12 +61,18 @@ std::string irebm::validate_params(const lbm_stefan_params *p) {
   if (p->newton_max_it < 1 || p->newton_max_it > 1000)
     return "newton_max_it must be in 1..1000";
   if (!(p->dx >= 0.0) || !std::isfinite(p->dx)) return "dx must be >= 0";
+  bool neu = false, bb = false;
   for (int k = 0; k < 4; ++k) {
     if (p->dim == 1 && k >= 2) break;
-    if (p->bc[k] < LBM_BC_DIRICHLET || p->bc[k] > LBM_BC_PERIODIC)
+    if (p->bc[k] < LBM_BC_DIRICHLET || p->bc[k] > LBM_BC_NEUMANN)
       return "unknown boundary kind";
     if (!std::isfinite(p->wall_T[k])) return "wall_T must be finite";
+    neu |= p->bc[k] == LBM_BC_NEUMANN;
+    bb |= p->bc[k] == LBM_BC_BOUNCEBACK;
   }
+  if (neu && bb) return "Neumann and bounce-back walls do not mix";
+  if (neu && (p->flags & LBM_FLAG_ADJOINT))
+    return "the reverse mode has no Neumann closure";
   if ((p->bc[0] == LBM_BC_PERIODIC) != (p->bc[1] == LBM_BC_PERIODIC))
     return "x walls: both or neither periodic";
   if (p->dim == 2 &&
@@ -142,8 +148,10 @@ void irebm::fill_args(const lbm_stefan_params &p, double *const prof[4],
   A->inv_delta = 1.0 / p.delta;
   A->tol = p.newton_tol;
   A->max_it = p.newton_max_it;
+  A->neu = 0;
   for (int k = 0; k < 4; ++k) {
     A->bc[k] = (p.dim == 1 && k >= 2) ? BC_PERIODIC : p.bc[k];
+    if (A->bc[k] == BC_NEUMANN) A->neu |= 1 << k;
     A->wall_T[k] = p.wall_T[k];
     A->prof[k] = prof ? prof[k] : nullptr;
   }
@@ -158,7 +166,7 @@ void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
 
 bool irebm::two_step_variant(const lbm_stefan_t *h) {
   int nv;
-  return variants(h->p.q, &nv)[h->variant].tb != 0;
+  return variants(h->p.q, &nv)[h->variant].tb != 0 && !has_neumann(h->p);
 }
 
 hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
@@ -489,7 +497,7 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
     return fail(h, LBM_STEFAN_EINVAL, "steps must be in 1..10000");
   DeviceGuard g(h->device);
   int nv;
-  variants(p.q, &nv);
+  const Variant *vt = variants(p.q, &nv);
   const int cur0 = h->cur;
   HIPCHK(h, hipMemcpyAsync(scratch, h->buf[cur0], bytes,
                            hipMemcpyDeviceToDevice, h->stream));
@@ -503,6 +511,8 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
   float best_ms = 0.0f;
   hipError_t err = hipSuccess;
   for (int v = 0; v < nv && err == hipSuccess; ++v) {
+    // a Neumann lattice runs two-step variants as the default one
+    if (vt[v].tb && has_neumann(p)) continue;
     h->variant = v;
     // two untimed steps, then the timed trial (an even count, so that a
     // two-step variant runs its own kernel only)

@@ -102,9 +102,11 @@ template <int MODE>
 hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
                              const Variant &v, hipStream_t stream);
 
-#define IREBM_DECLARE_MODE(M)                                              \
+#define IREBM_DECLARE_STEP1(M)                                             \
   extern template hipError_t step_launch_mode<M>(                          \
-      int, int, const StepArgs &, const Variant &, bool, hipStream_t);     \
+      int, int, const StepArgs &, const Variant &, bool, hipStream_t)
+#define IREBM_DECLARE_MODE(M)                                              \
+  IREBM_DECLARE_STEP1(M);                                                  \
   extern template hipError_t step2_launch_mode<M>(                         \
       int, int, const StepArgs &, const Variant &, bool, hipStream_t);     \
   extern template hipError_t batch_launch_mode<M>(                         \
@@ -112,26 +114,54 @@ hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
 IREBM_DECLARE_MODE(kSafeguarded);
 IREBM_DECLARE_MODE(kPlain);
 IREBM_DECLARE_MODE(kEebm);
+// lattices with a Neumann wall: one-step single-lattice kernels only
+IREBM_DECLARE_STEP1(kSafeguarded | kNeumann);
+IREBM_DECLARE_STEP1(kPlain | kNeumann);
+IREBM_DECLARE_STEP1(kEebm | kNeumann);
 #undef IREBM_DECLARE_MODE
+#undef IREBM_DECLARE_STEP1
 
-// node-update mode of a lattice
+// does a lattice have a Neumann wall (eq. Neu_on_q)?  Its closure reads
+// two cells away, so such lattices take one step per launch
+inline bool has_neumann(const lbm_stefan_params &p) {
+  for (int k = 0; k < (p.dim == 2 ? 4 : 2); ++k)
+    if (p.bc[k] == LBM_BC_NEUMANN) return true;
+  return false;
+}
+
+// node-update mode of a lattice (with kNeumann when it has a Neumann wall)
 inline int mode_of(const lbm_stefan_params &p) {
-  if (p.scheme == LBM_SCHEME_EEBM) return kEebm;
-  return p.newton_mode == LBM_NEWTON_PLAIN ? kPlain : kSafeguarded;
+  const int neu = has_neumann(p) ? (int)kNeumann : 0;
+  if (p.scheme == LBM_SCHEME_EEBM) return kEebm | neu;
+  return (p.newton_mode == LBM_NEWTON_PLAIN ? kPlain : kSafeguarded) | neu;
 }
 
 // one step of one lattice (one-step variant v)
 inline hipError_t step_launch(int mode, int q, int storage, const StepArgs &A,
                               const Variant &v, bool reverse,
                               hipStream_t stream) {
-  if (mode == kEebm)
-    return step_launch_mode<kEebm>(q, storage, A, v, reverse, stream);
-  if (mode == kPlain)
-    return step_launch_mode<kPlain>(q, storage, A, v, reverse, stream);
-  return step_launch_mode<kSafeguarded>(q, storage, A, v, reverse, stream);
+  switch (mode) {
+    case kEebm:
+      return step_launch_mode<kEebm>(q, storage, A, v, reverse, stream);
+    case kPlain:
+      return step_launch_mode<kPlain>(q, storage, A, v, reverse, stream);
+    case kEebm | kNeumann:
+      return step_launch_mode<kEebm | kNeumann>(q, storage, A, v, reverse,
+                                                stream);
+    case kPlain | kNeumann:
+      return step_launch_mode<kPlain | kNeumann>(q, storage, A, v, reverse,
+                                                 stream);
+    case kSafeguarded | kNeumann:
+      return step_launch_mode<kSafeguarded | kNeumann>(q, storage, A, v,
+                                                       reverse, stream);
+    default:
+      return step_launch_mode<kSafeguarded>(q, storage, A, v, reverse,
+                                            stream);
+  }
 }
 
-// two steps (one if two = false) of one 2D lattice (two-step variant v)
+// two steps (one if two = false) of one 2D lattice (two-step variant v;
+// never a lattice with a Neumann wall)
 inline hipError_t step2_launch(int mode, int q, int storage,
                                const StepArgs &A, const Variant &v, bool two,
                                hipStream_t stream) {

@@ -12,7 +12,7 @@ import torch
 from . import _lib as C
 
 _BC = {"dirichlet": C.BC_DIRICHLET, "bounceback": C.BC_BOUNCEBACK,
-       "periodic": C.BC_PERIODIC}
+       "periodic": C.BC_PERIODIC, "neumann": C.BC_NEUMANN}
 _STORE = {"f64": C.STORE_F64, "f32": C.STORE_F32}
 _NEWTON = {"safeguarded": C.NEWTON_SAFEGUARDED, "plain": C.NEWTON_PLAIN}
 _SCHEME = {"irebm": C.SCHEME_IREBM, "eebm": C.SCHEME_EEBM}

@@ -191,3 +191,25 @@ def test_ctypes_structs_match_header(L, tmp_path):
     want += [getattr(L.Params, f).offset for f in fields]
     want += [getattr(L.Stats, f).offset for f in sfields]
     assert out == want
+
+
+def test_neumann_wall_rules(L):
+    """Neumann walls (eq. Neu_on_q): not beside bounce-back walls, no
+    reverse mode, not in the batched form."""
+    from paper_2505_13097_amd.stefan import make_params
+    prob = synth.freezing_cavity_2d(n=33, q=9)
+    p, _ = _params(L, prob)
+    assert p.bc[1] == L.BC_NEUMANN and _ws(L, p)[0] == L.OK
+    p.bc[2] = L.BC_BOUNCEBACK
+    p.bc[3] = L.BC_BOUNCEBACK
+    assert _ws(L, p)[0] == L.EINVAL
+    assert b"bounce-back" in L.lib().lbm_stefan_last_error(None)
+    p, _ = _params(L, prob, flags=L.FLAG_ADJOINT)
+    assert _ws(L, p)[0] == L.EINVAL
+    p.bc[4 - 3] = L.BC_NEUMANN + 1
+    assert _ws(L, p)[0] == L.EINVAL
+    a, _ = make_params(prob)
+    n = ctypes.c_size_t()
+    arr = (L.Params * 2)(a, a)
+    assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.EINVAL
+    assert b"Neumann" in L.lib().lbm_stefan_batch_last_error(None)
