@@ -21,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ("irebm.c", "irebm_cs.c", "eebm.c")
+SOURCES = ("irebm.c", "irebm_cs.c", "eebm.c", "ilfbm.c")
 
 DIRICHLET, BOUNCEBACK, PERIODIC, NEUMANN = 0, 1, 2, 3
 SAFEGUARDED, PLAIN = 0, 1
@@ -108,6 +108,13 @@ def lib():
             "orc_eebm_energy": [P, dp, dp],
             "orc_eebm_front": [P, dp, ctypes.c_int, dp],
             "orc_eebm_collide": [P, dp, dp],
+            "orc_ilfbm_init": [P, dp, dp],
+            "orc_ilfbm_step": [P, dp, dp, S],
+            "orc_ilfbm_run": [P, dp, ctypes.c_long, S, dp, dp],
+            "orc_ilfbm_temperature": [P, dp, dp],
+            "orc_ilfbm_energy": [P, dp, dp],
+            "orc_ilfbm_front": [P, dp, ctypes.c_int, dp],
+            "orc_ilfbm_collide": [P, dp, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -158,10 +165,12 @@ class Setup:
         p.dx = prob.dx
         self.p = p
         self.q, self.nx, self.ny = prob.q, prob.nx, prob.ny
+        # the implicit liquid fraction scheme carries l as one more plane
+        self.planes = prob.q + (getattr(prob, "scheme", "irebm") == "ilfbm")
 
     @property
     def shape(self):
-        return (self.q, self.ny, self.nx)
+        return (self.planes, self.ny, self.nx)
 
     def ref(self):
         return ctypes.byref(self.p)
@@ -202,9 +211,10 @@ def newton(m0, theta, ste, tm, delta, tol=1e-12, max_it=20,
 
 
 def _fn(prob, name):
-    """orc_<name>, or orc_eebm_<name> for the explicit scheme."""
-    if getattr(prob, "scheme", "irebm") == "eebm":
-        return getattr(lib(), "orc_eebm_" + name)
+    """orc_<name>, or orc_<scheme>_<name> for the comparison schemes."""
+    scheme = getattr(prob, "scheme", "irebm")
+    if scheme in ("eebm", "ilfbm"):
+        return getattr(lib(), f"orc_{scheme}_" + name)
     return getattr(lib(), "orc_" + name)
 
 
@@ -220,6 +230,18 @@ def eebm_collide(prob, f):
     f = _f64(f)
     out = np.empty_like(f)
     _check(lib().orc_eebm_collide(s.ref(), _dp(f), _dp(out)), "eebm_collide")
+    return out
+
+
+def ilfbm_collide(prob, f):
+    """Collision without source of the population planes of an ILFBM
+    state (f and l): the populations before the inner loop adds its
+    source (Algorithm 1)."""
+    s = Setup(prob)
+    f = _f64(f)
+    out = np.empty((prob.q, prob.ny, prob.nx))
+    _check(lib().orc_ilfbm_collide(s.ref(), _dp(f), _dp(out)),
+           "ilfbm_collide")
     return out
 
 

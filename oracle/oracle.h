@@ -128,6 +128,25 @@ int orc_eebm_front(const orc_params *p, const double *f, int mode,
    the post-collision populations, whose pull streaming gives the next f */
 int orc_eebm_collide(const orc_params *p, const double *f, double *omega);
 
+/* The implicit liquid fraction based method (Algorithm 1): state f (q
+   planes, M0(f) = theta) followed by the liquid fraction plane l, so
+   (q + 1) planes; the inner loop stops when max |l^(k) - l^(k-1)| <= tol
+   or after max_it iterations (orc_stats: max_it = largest inner
+   iteration count, nonconverged = steps that hit the cap, max_residual =
+   their largest last change of l; delta and newton_mode unused).
+   ilfbm.c states the closures. */
+int orc_ilfbm_init(const orc_params *p, const double *T0, double *f);
+int orc_ilfbm_step(const orc_params *p, const double *f, double *fout,
+                   orc_stats *st);
+int orc_ilfbm_run(const orc_params *p, double *f, long nsteps,
+                  orc_stats *st, double *energy_trace, double *flux_trace);
+int orc_ilfbm_temperature(const orc_params *p, const double *f, double *T);
+int orc_ilfbm_energy(const orc_params *p, const double *f, double *E);
+int orc_ilfbm_front(const orc_params *p, const double *f, int mode,
+                    double *xf);
+/* collision without source of the q population planes of f */
+int orc_ilfbm_collide(const orc_params *p, const double *f, double *omega);
+
 #ifdef __cplusplus
 }
 #endif
