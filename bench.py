@@ -180,6 +180,55 @@ def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1):
     }
 
 
+def _run_seconds(prob, nsteps):
+    """Wall time of nsteps steps of a fresh handle (after 5 warm steps),
+    and its statistics."""
+    import torch
+    from paper_2505_13097_amd import Stefan
+    g = Stefan(prob)
+    g.step(5)
+    g.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = g.step(nsteps, stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    return dt, st
+
+
+def time_paper1d(sizes=(201, 401, 801)):
+    """The paper's 1D case (Section 6.1) to t = 160 s with the three
+    schemes of its 1D timing table (tau 0.62, delta 0.01 for IREBM; D1Q3,
+    FP64; ILFBM inner loop to 1e-12, at most 200 iterations)."""
+    import numpy as np
+    import synth as S
+    ste, th0 = 0.2857, -0.5
+    t_end = 160.0 * 8e-5
+    tau = 0.62
+    rows = []
+    for n in sizes:
+        dx = 1.0 / (n - 1)
+        dt = (tau - 0.5) * dx * dx / 3.0
+        nsteps = int(round(t_end / dt))
+        base = S.Problem(dim=1, q=3, nx=n, ny=1, tau=tau, ste=ste, delta=0.01,
+                         bc=("dirichlet", "dirichlet", "periodic", "periodic"),
+                         wall_T=(1.0, th0, 0.0, 0.0), tol=1e-12, max_it=200,
+                         storage="f64", T0=np.full((1, n), th0))
+        r = {"N": n, "steps": nsteps}
+        for scheme in ("eebm", "irebm", "ilfbm"):
+            sec, st = _run_seconds(base.with_(scheme=scheme), nsteps)
+            r[f"{scheme}_s"] = round(sec, 4)
+            if scheme == "ilfbm":
+                r["ilfbm_max_inner_iterations"] = st["max_newton_it"]
+                r["ilfbm_capped_steps"] = st["nonconverged"]
+        r["ratio_irebm_to_eebm"] = round(r["irebm_s"] / r["eebm_s"], 3)
+        r["ratio_ilfbm_to_irebm"] = round(r["ilfbm_s"] / r["irebm_s"], 3)
+        rows.append(r)
+    return {"workload": "stefan1d_d1q3_f64_to_160s", "unit": "s per run",
+            "runs": rows}
+
+
 def time_freezing(sizes=(201, 401, 801)):
     """The paper's 2D freezing case (Section 6.2) run to t = 20 h, D2Q5 and
     D2Q9, EEBM and IREBM, FP64 populations: the configuration of the
@@ -207,6 +256,14 @@ def time_freezing(sizes=(201, 401, 801)):
                 r[f"{scheme}_s"] = round(dt, 4)
                 r[f"{scheme}_glups"] = round(p.nodes * p.nsteps / dt / 1e9, 2)
             r["ratio_irebm_to_eebm"] = round(r["irebm_s"] / r["eebm_s"], 3)
+            if q == 9 and n <= 401:
+                # ILFBM converges on D2Q9 only (about 80 inner iterations)
+                p = S.freezing_cavity_2d(n=n, q=q, scheme="ilfbm").with_(
+                    max_it=200)
+                sec, st = _run_seconds(p, p.nsteps)
+                r["ilfbm_s"] = round(sec, 4)
+                r["ilfbm_max_inner_iterations"] = st["max_newton_it"]
+                r["ilfbm_capped_steps"] = st["nonconverged"]
             rows.append(r)
     return {"workload": "freeze2d_quarter_cavity_f64_20h",
             "unit": "s per run to 20 h", "runs": rows}
@@ -507,9 +564,10 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,adjoint,eebm,freezing",
+    ap.add_argument("--forms",
+                    default="plain,batched,adjoint,eebm,freezing,paper1d",
                     help="comma list of extra forms to time: batched, "
-                         "adjoint, eebm, freezing")
+                         "adjoint, eebm, freezing, paper1d")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-variant", type=int, default=-1)
@@ -653,6 +711,10 @@ def main():
         print("[bench] freezing form", file=sys.stderr, flush=True)
         forms["freezing"] = time_freezing()
         print("[bench] freezing done", file=sys.stderr, flush=True)
+    if "paper1d" in args.forms.split(","):
+        print("[bench] paper1d form", file=sys.stderr, flush=True)
+        forms["paper1d"] = time_paper1d()
+        print("[bench] paper1d done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:

@@ -90,7 +90,7 @@ extern "C" {
 /* front position of each row y (Section 6: "position of the interface") */
 #define LBM_FRONT_LIQUID_INTEGRAL 0 /* dx * trapezoid sum_x phi(T(x, y));
                                        EEBM: of l(H) = clamp(Ste (H - T_m),
-                                       0, 1) */
+                                       0, 1); ILFBM: of its l plane */
 #define LBM_FRONT_ZERO_CROSSING 1   /* first x where T - T_m goes from > 0
                                        to <= 0, linearly interpolated */
 
@@ -99,10 +99,27 @@ extern "C" {
 #define LBM_SCHEME_EEBM 1  /* Algorithm 2 (Section 3.4): no Newton solve;
                               delta, newton_* and newton_mode are unused
                               but still validated; no reverse mode */
+#define LBM_SCHEME_ILFBM 2 /* Algorithm 1 (Section 3.3): the state adds the
+                              liquid fraction l (workspace); each step runs
+                              the inner loop of collision with the source
+                              (w_i/Ste)(l - l^(k-1)), pull streaming and
+                              l^(k) = clamp(Ste (M0(f^(k)) + l^(k-1)/Ste -
+                              T_m), 0, 1) until max |l^(k) - l^(k-1)| <=
+                              newton_tol or newton_max_it iterations, one
+                              launch per iteration (the host reads a device
+                              flag every few); Dirichlet closures target
+                              T_D.  Kernel variants do not apply; no reverse
+                              mode, not in the batched form.  Statistics:
+                              max_newton_it = most inner iterations of a
+                              step, nonconverged = steps that hit the cap,
+                              max_residual = their largest last change of
+                              l.  E = sum [T + l/Ste]. */
 
 /* fields for lbm_stefan_get_field */
 #define LBM_FIELD_T 0     /* temperature, double [ny][nx] */
 #define LBM_FIELD_STATE 1 /* the state planes, storage type [q][ny][nx] */
+#define LBM_FIELD_LIQUID 2 /* liquid fraction, double [ny][nx]: phi(T)
+                              (IREBM), l(H) (EEBM), the l plane (ILFBM) */
 
 typedef struct lbm_stefan_params {
   int32_t dim;           /* 1 or 2 */
@@ -214,8 +231,9 @@ int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
                            double *energy);
 
 /*
- * Copy a field of the current state to host memory: LBM_FIELD_T (ny*nx
- * doubles) or LBM_FIELD_STATE (q*ny*nx values of the storage type).
+ * Copy a field of the current state to host memory: LBM_FIELD_T or
+ * LBM_FIELD_LIQUID (ny*nx doubles) or LBM_FIELD_STATE (q*ny*nx values of
+ * the storage type).
  * Waits for the stream.  Errors: EINVAL, EDEVICE.
  */
 int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host);
@@ -223,7 +241,8 @@ int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host);
 /*
  * Replace the current state by q planes of the storage type (layout as
  * above), read from device memory (on_device != 0) or host memory.
- * Enqueued on the stream; a host source is copied before return.
+ * Enqueued on the stream; a host source is copied before return.  ILFBM:
+ * the liquid fraction plane is left as it is.
  */
 int lbm_stefan_set_state(lbm_stefan_t *h, const void *state,
                          int32_t on_device);
@@ -254,7 +273,8 @@ int lbm_stefan_set_variant(lbm_stefan_t *h, int32_t variant);
  * before the trials and restored after each one, so the handle's state
  * and step count are unchanged; statistics are reset.  Writes the chosen
  * variant and its time per step (ms); either output may be NULL.  Waits
- * for the stream.  Errors: EINVAL, EDEVICE.
+ * for the stream.  ILFBM (one kernel shape): returns the current variant
+ * and 0 ms without running.  Errors: EINVAL, EDEVICE.
  */
 int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
                         int32_t steps, int32_t *best_variant,

@@ -90,6 +90,9 @@ std::string validate_batch(const lbm_stefan_params *ps, int32_t count) {
     if (has_neumann(ps[k]))
       return "instance " + std::to_string(k) +
              ": the batched form has no Neumann closure";
+    if (ps[k].scheme == LBM_SCHEME_ILFBM)
+      return "instance " + std::to_string(k) +
+             ": the batched form runs IREBM and EEBM only";
   }
   return "";
 }

@@ -135,30 +135,32 @@ inline hipError_t zero_async(void *p, size_t bytes, hipStream_t s) {
 // kEnergyChunk) doubles) as scratch
 inline hipError_t energy_async(const lbm_stefan_params &p, const void *src,
                                double *partials, double *out,
-                               hipStream_t stream) {
+                               hipStream_t stream,
+                               const double *lf = nullptr) {
   const int64_t n = p.nx * p.ny;
   return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     const int64_t parts = (n + kEnergyChunk - 1) / kEnergyChunk;
     energy_partial_kernel<Q, S><<<(unsigned)parts, 256, 0, stream>>>(
         (const S *)src, n, p.scheme == LBM_SCHEME_EEBM, p.t_m, 1.0 / p.delta,
-        1.0 / p.ste, partials);
+        1.0 / p.ste, lf, partials);
     sum_kernel<<<1, 256, 0, stream>>>(partials, parts, out);
     return hipGetLastError();
   });
 }
 
 // per-row front of the state `src` of a lattice with params p (p.dx > 0)
-// into out[0..ny) (device)
+// into out[0..ny) (device); lf: the ILFBM liquid fraction plane
 inline hipError_t front_async(const lbm_stefan_params &p, const void *src,
-                              int mode, double *out, hipStream_t stream) {
+                              int mode, double *out, hipStream_t stream,
+                              const double *lf = nullptr) {
   const int eebm = p.scheme == LBM_SCHEME_EEBM;
   return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     if (mode == LBM_FRONT_LIQUID_INTEGRAL)
       front_integral_kernel<Q, S><<<(unsigned)p.ny, 256, 0, stream>>>(
           (const S *)src, p.nx * p.ny, (int)p.nx, eebm, p.t_m, 1.0 / p.delta,
-          p.ste, p.dx, out);
+          p.ste, lf, p.dx, out);
     else
       front_crossing_kernel<Q, S><<<(unsigned)p.ny, 256, 0, stream>>>(
           (const S *)src, p.nx * p.ny, (int)p.nx, eebm, p.t_m, 1.0 / p.ste,
@@ -181,12 +183,29 @@ inline hipError_t temperature_async(const lbm_stefan_params &p,
   });
 }
 
-// equilibrium initial state of the lattice described by A (A.dst)
+// liquid fraction of every node of the state `src` into out (device)
+inline hipError_t liquid_async(const lbm_stefan_params &p, const void *src,
+                               const double *lf, double *out,
+                               hipStream_t stream) {
+  const int64_t n = p.nx * p.ny;
+  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
+    QS_TYPES(qt, tt);
+    liquid_kernel<Q, S><<<blocks_for(n, 256), 256, 0, stream>>>(
+        (const S *)src, n, p.scheme == LBM_SCHEME_EEBM, p.t_m, 1.0 / p.delta,
+        p.ste, lf, out);
+    return hipGetLastError();
+  });
+}
+
+// equilibrium initial state of the lattice described by A (A.dst), and
+// the ILFBM liquid fraction into lf when given
 inline hipError_t init_async(int q, int storage, const StepArgs &A,
-                             const double *T0, hipStream_t stream) {
+                             const double *T0, hipStream_t stream,
+                             double *lf = nullptr) {
   return dispatch_qs(q, storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
-    init_kernel<Q, S><<<blocks_for(A.plane, 256), 256, 0, stream>>>(A, T0);
+    init_kernel<Q, S><<<blocks_for(A.plane, 256), 256, 0, stream>>>(A, T0,
+                                                                     lf);
     return hipGetLastError();
   });
 }

@@ -71,7 +71,7 @@ enum { BC_DIRICHLET = 0, BC_BOUNCEBACK = 1, BC_PERIODIC = 2, BC_NEUMANN = 3 };
 enum Mode : int { kSafeguarded = 0, kPlain = 1, kEebm = 2, kNeumann = 4 };
 constexpr int base_mode(int m) { return m & 3; }
 constexpr bool neumann_mode(int m) { return (m & kNeumann) != 0; }
-enum { SCHEME_IREBM = 0, SCHEME_EEBM = 1 };
+enum { SCHEME_IREBM = 0, SCHEME_EEBM = 1, SCHEME_ILFBM = 2 };
 
 // Per-tile statistics slot, accumulated across steps by the one block
 // that owns the tile (no atomics; deterministic).
@@ -388,6 +388,7 @@ __device__ __forceinline__ double wall_value(const StepArgs &A, int wall, int x,
 //    temperature is T_D; the deficit is shared by weight among the
 //    remaining unknowns.  EEBM: the zeroth moment is the wall enthalpy
 //    T_D + l(T_D)/Ste (l = 1 above T_m, else 0), whose Theta is T_D;
+//    ILFBM (M0 = theta): T_D itself;
 // 3. on a Neumann node (not Dirichlet), M0(q) is set to M0 of the pulls
 //    at the mirror node (eq. Neu_on_q; `mirror`), the deficit shared by
 //    weight among the remaining unknowns (one on flat D2Q5/D1Q3 walls);
@@ -401,7 +402,7 @@ struct CloseInfo {
   double TD = 0.0, wu = 0.0;
 };
 
-template <int Q, bool EEBM = false, bool NEU = true>
+template <int Q, int SCH = SCHEME_IREBM, bool NEU = true>
 __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
                                     double th, const double *om, double *q,
                                     uint32_t known, double mirror,
@@ -423,9 +424,11 @@ __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
   if (ci) ci->wall = wall;
   if (wall >= 0) {
     const double TD = wall_value(A, wall, x, y);
-    double D = EEBM ? TD + (TD > A.tm ? A.inv_ste : 0.0)
-                    : TD + (phi_only(TD, A.tm, A.inv_delta) -
-                            phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
+    double D = SCH == SCHEME_EEBM    ? TD + (TD > A.tm ? A.inv_ste : 0.0)
+               : SCH == SCHEME_ILFBM ? TD
+                                     : TD + (phi_only(TD, A.tm, A.inv_delta) -
+                                             phi_only(th, A.tm, A.inv_delta)) *
+                                                A.inv_ste;
     double wu = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -516,8 +519,8 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
   if (!FAST) {
     if (L.known != (1u << Q) - 1u)
-      st.flux_in += close_node<Q, EEBM, NEU>(A, x, y, th, om, q, L.known,
-                                             L.mirror);
+      st.flux_in += close_node<Q, EEBM ? SCHEME_EEBM : SCHEME_IREBM, NEU>(
+          A, x, y, th, om, q, L.known, L.mirror);
     if (L.out) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)

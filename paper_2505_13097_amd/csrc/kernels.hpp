@@ -394,16 +394,18 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
 // ---------------------------------------------------------------------
 // init, temperature, zero fill
 
-// IREBM: Omega_i = w_i T.  EEBM: the equilibrium of the enthalpy
-// H = T + l(T)/Ste (l = 1 above T_m, else 0), which collision keeps.
+// IREBM and ILFBM: Omega_i = w_i T (and, when lf is given, the ILFBM
+// liquid fraction l = 1 above T_m, else 0).  EEBM: the equilibrium of the
+// enthalpy H = T + l(T)/Ste, which collision keeps.
 template <int Q, typename S>
-__global__ void init_kernel(StepArgs A, const double *T0) {
+__global__ void init_kernel(StepArgs A, const double *T0, double *lf) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= A.plane) return;
   const int x = (int)(k % A.nx), y = (int)(k / A.nx);
   const int wall = dirichlet_wall<Q>(A, x, y);
   const double T = wall >= 0 ? wall_value(A, wall, x, y) : (T0 ? T0[k] : 0.0);
   S *dst = (S *)A.dst;
+  if (lf) lf[k] = T > A.tm ? 1.0 : 0.0;
   if (A.scheme == SCHEME_EEBM) {
     const double H = T + (T > A.tm ? A.inv_ste : 0.0);
     const double th = eebm_theta(H, A.tm, A.inv_ste);
@@ -427,6 +429,24 @@ __global__ void temp_kernel(const S *src, int64_t plane, int eebm, double tm,
   T[k] = eebm ? eebm_theta(s, tm, inv_ste) : s;
 }
 
+// liquid fraction of every node: phi(T) (IREBM), l(H) (EEBM) or the lf
+// plane (ILFBM)
+template <int Q, typename S>
+__global__ void liquid_kernel(const S *src, int64_t plane, int eebm,
+                              double tm, double inv_delta, double ste,
+                              const double *lf, double *out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= plane) return;
+  if (lf) {
+    out[k] = lf[k];
+    return;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) s += (double)src[j * plane + k];
+  out[k] = eebm ? eebm_lf(s, tm, ste) : phi_only(s, tm, inv_delta);
+}
+
 __global__ void zero_kernel(uint64_t *p, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0;
@@ -447,11 +467,11 @@ __device__ __forceinline__ double block_sum_256(double v) {
 }
 
 // partial[b] = sum over nodes [b*chunk, (b+1)*chunk) of T + phi(T)/Ste,
-// or of the enthalpy M0 itself (eebm)
+// of the enthalpy M0 itself (eebm), or of T + lf/Ste (lf given: ILFBM)
 template <int Q, typename S>
 __global__ __launch_bounds__(256) void energy_partial_kernel(
     const S *src, int64_t plane, int eebm, double tm, double inv_delta,
-    double inv_ste, double *partial) {
+    double inv_ste, const double *lf, double *partial) {
   const int64_t base = (int64_t)blockIdx.x * kEnergyChunk;
   double acc = 0.0;
   for (int j = 0; j < kEnergyChunk / 256; ++j) {
@@ -460,7 +480,8 @@ __global__ __launch_bounds__(256) void energy_partial_kernel(
       double T = 0.0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) T += (double)src[i * plane + k];
-      acc += eebm ? T : T + phi_only(T, tm, inv_delta) * inv_ste;
+      acc += lf ? T + lf[k] * inv_ste
+                : (eebm ? T : T + phi_only(T, tm, inv_delta) * inv_ste);
     }
   }
   const double s = block_sum_256(acc);
@@ -508,19 +529,21 @@ __global__ __launch_bounds__(256) void stats_kernel(const StatSlot *slots,
   }
 }
 
-// front of row blockIdx.x: dx * trapezoid sum of phi(T), or of the sharp
-// liquid fraction l(H) (eebm)
+// front of row blockIdx.x: dx * trapezoid sum of phi(T), of the sharp
+// liquid fraction l(H) (eebm), or of the liquid fraction plane lf (ILFBM)
 template <int Q, typename S>
 __global__ __launch_bounds__(256) void front_integral_kernel(
     const S *src, int64_t plane, int nx, int eebm, double tm, double inv_delta,
-    double ste, double dx, double *out) {
+    double ste, const double *lf, double dx, double *out) {
   const int64_t row = (int64_t)blockIdx.x * nx;
   double acc = 0.0;
   for (int x = threadIdx.x; x < nx; x += 256) {
     double T = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) T += (double)src[i * plane + row + x];
-    const double ph = eebm ? eebm_lf(T, tm, ste) : phi_only(T, tm, inv_delta);
+    const double ph = lf ? lf[row + x]
+                         : (eebm ? eebm_lf(T, tm, ste)
+                                 : phi_only(T, tm, inv_delta));
     acc += (x == 0 || x == nx - 1) ? 0.5 * ph : ph;
   }
   const double s = block_sum_256(acc);

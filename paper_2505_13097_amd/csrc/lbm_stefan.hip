@@ -48,9 +48,10 @@ std::string irebm::validate_params(const lbm_stefan_params *p) {
   if (p->newton_mode != LBM_NEWTON_SAFEGUARDED &&
       p->newton_mode != LBM_NEWTON_PLAIN)
     return "unknown newton_mode";
-  if (p->scheme != LBM_SCHEME_IREBM && p->scheme != LBM_SCHEME_EEBM)
+  if (p->scheme != LBM_SCHEME_IREBM && p->scheme != LBM_SCHEME_EEBM &&
+      p->scheme != LBM_SCHEME_ILFBM)
     return "unknown scheme";
-  if (p->scheme == LBM_SCHEME_EEBM && (p->flags & LBM_FLAG_ADJOINT))
+  if (p->scheme != LBM_SCHEME_IREBM && (p->flags & LBM_FLAG_ADJOINT))
     return "the reverse mode is for the IREBM scheme only";
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return "tau must be > 1/2";
   if (!(p->ste > 0.0) || !std::isfinite(p->ste)) return "ste must be > 0";
@@ -114,6 +115,8 @@ irebm::Layout irebm::layout_for(const lbm_stefan_params *p) {
   L.adjoint = (p->flags & LBM_FLAG_ADJOINT) != 0;
   L.off_adj = off;
   if (L.adjoint) off += adjoint_bytes(p, mt);
+  L.off_lf = off;
+  off += ilfbm_bytes(p);
   L.total = off;
   return L;
 }
@@ -182,6 +185,7 @@ hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
 }
 
 hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
+  if (h->p.scheme == LBM_SCHEME_ILFBM) return ilfbm_advance(h, nsteps);
   if (two_step_variant(h)) {
     for (; nsteps >= 2; nsteps -= 2) {
       const hipError_t e =
@@ -219,12 +223,13 @@ namespace {
 // energy of the state `src` into h->small[kSmallEnergy] (device)
 hipError_t handle_energy_async(const lbm_stefan_t *h, const void *src) {
   return irebm::energy_async(h->p, src, h->partials, h->small + kSmallEnergy,
-                             h->stream);
+                             h->stream, h->lf);
 }
 
 }  // namespace
 
 hipError_t irebm::zero_stats_async(lbm_stefan_t *h) {
+  ilfbm_reset_stats(h);
   return zero_async(h->slots, h->max_items * sizeof(StatSlot), h->stream);
 }
 
@@ -243,6 +248,14 @@ int irebm::read_stats(lbm_stefan_t *h, lbm_stefan_stats *st) {
   st->max_residual = hs[2];
   st->flux_in = hs[3];
   st->flux_out = hs[4];
+  if (h->p.scheme == LBM_SCHEME_ILFBM) {
+    // the inner loop's statistics are kept on the host (per step)
+    st->max_newton_it = h->ilf_max_it;
+    st->nonconverged = h->ilf_nonconv;
+    st->max_residual = h->ilf_max_res;
+    st->flux_in = h->ilf_fin;
+    st->flux_out = h->ilf_fout;
+  }
   st->energy = hs[kSmallEnergy];
   if (!std::isfinite(st->energy))
     return fail(h, LBM_STEFAN_ENAN, "energy is not finite");
@@ -333,12 +346,8 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   fill_step_args(h, &A);
   A.dst = h->buf[0];
   const double *T0d = T0 ? (const double *)h->buf[1] : nullptr;
-  auto r = [&](auto qt, auto tt) {
-    QS_TYPES(qt, tt);
-    init_kernel<Q, S><<<blocks_for(A.plane, 256), 256, 0, h->stream>>>(A, T0d);
-    return hipGetLastError();
-  };
-  if (dispatch_qs(p->q, p->storage, r) != hipSuccess ||
+  if (p->scheme == LBM_SCHEME_ILFBM) ilfbm_attach(h, ws + L.off_lf);
+  if (init_async(p->q, p->storage, A, T0d, h->stream, h->lf) != hipSuccess ||
       zero_stats_async(h) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
     return bail(fail(h, LBM_STEFAN_EDEVICE, "init kernels failed"));
@@ -379,7 +388,7 @@ int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
   const lbm_stefan_params &p = h->p;
   double *fr = h->small + kSmallFront;
   if (front) {
-    HIPCHK(h, front_async(p, h->buf[h->cur], mode, fr, h->stream));
+    HIPCHK(h, front_async(p, h->buf[h->cur], mode, fr, h->stream, h->lf));
     HIPCHK(h, hipMemcpyAsync(front, fr, p.ny * 8, hipMemcpyDeviceToHost,
                              h->stream));
   }
@@ -412,6 +421,10 @@ int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host) {
     double *T = (double *)h->buf[h->cur ^ 1];
     HIPCHK(h, temperature_async(p, h->buf[h->cur], T, h->stream));
     HIPCHK(h, hipMemcpyAsync(host, T, n * 8, hipMemcpyDeviceToHost, h->stream));
+  } else if (what == LBM_FIELD_LIQUID) {
+    double *l = (double *)h->buf[h->cur ^ 1];
+    HIPCHK(h, liquid_async(p, h->buf[h->cur], h->lf, l, h->stream));
+    HIPCHK(h, hipMemcpyAsync(host, l, n * 8, hipMemcpyDeviceToHost, h->stream));
   } else {
     return fail(h, LBM_STEFAN_EINVAL, "unknown field");
   }
@@ -495,6 +508,12 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
     return fail(h, LBM_STEFAN_EINVAL, "scratch smaller than the state");
   if (steps < 1 || steps > 10000)
     return fail(h, LBM_STEFAN_EINVAL, "steps must be in 1..10000");
+  if (p.scheme == LBM_SCHEME_ILFBM) {
+    // one kernel shape: nothing to choose
+    if (best_variant) *best_variant = h->variant;
+    if (best_ms_per_step) *best_ms_per_step = 0.0;
+    return LBM_STEFAN_OK;
+  }
   DeviceGuard g(h->device);
   int nv;
   const Variant *vt = variants(p.q, &nv);

@@ -17,6 +17,8 @@ struct Layout {
   size_t off_buf[2] = {0, 0};
   size_t off_prof[4] = {0, 0, 0, 0};
   size_t off_slots = 0, off_partials = 0, off_small = 0, off_adj = 0;
+  size_t off_lf = 0;    // ILFBM: three liquid fraction planes, the per-
+                        // block pending values and the control block
   size_t total = 0;
   int64_t max_items = 0, n_partials = 0;
   bool adjoint = false;
@@ -48,6 +50,14 @@ struct lbm_stefan {
   int64_t steps = 0;
   void *tape = nullptr;          // last forward tape
   int64_t tape_steps = 0, tape_interval = 0;
+  // ILFBM (Algorithm 1): liquid fraction of the state, two inner-loop
+  // planes, per-block pending values, device control block, and the
+  // statistics of the inner loop kept on the host
+  double *lf = nullptr, *lscr[2] = {nullptr, nullptr}, *pend = nullptr;
+  void *ctrl = nullptr;
+  int32_t ilf_max_it = 0;
+  int64_t ilf_nonconv = 0;
+  double ilf_max_res = 0.0, ilf_fin = 0.0, ilf_fout = 0.0;
   std::string err;
 };
 
@@ -74,6 +84,13 @@ bool two_step_variant(const lbm_stefan_t *h);
 hipError_t advance(lbm_stefan_t *h, int64_t nsteps);
 hipError_t zero_stats_async(lbm_stefan_t *h);
 int read_stats(lbm_stefan_t *h, lbm_stefan_stats *st);
+
+// ILFBM (ilfbm.hip): workspace bytes beyond the common layout, the
+// handle's pointers into it, and nsteps steps of the inner-loop scheme
+size_t ilfbm_bytes(const lbm_stefan_params *p);
+void ilfbm_attach(lbm_stefan_t *h, char *base);
+hipError_t ilfbm_advance(lbm_stefan_t *h, int64_t nsteps);
+void ilfbm_reset_stats(lbm_stefan_t *h);
 
 // ---- kernel launches by node-update mode (launch.hpp; one translation
 // unit per mode instantiates them)

@@ -15,7 +15,8 @@ _BC = {"dirichlet": C.BC_DIRICHLET, "bounceback": C.BC_BOUNCEBACK,
        "periodic": C.BC_PERIODIC, "neumann": C.BC_NEUMANN}
 _STORE = {"f64": C.STORE_F64, "f32": C.STORE_F32}
 _NEWTON = {"safeguarded": C.NEWTON_SAFEGUARDED, "plain": C.NEWTON_PLAIN}
-_SCHEME = {"irebm": C.SCHEME_IREBM, "eebm": C.SCHEME_EEBM}
+_SCHEME = {"irebm": C.SCHEME_IREBM, "eebm": C.SCHEME_EEBM,
+           "ilfbm": C.SCHEME_ILFBM}
 _FRONT = {"integral": C.FRONT_LIQUID_INTEGRAL,
           "crossing": C.FRONT_ZERO_CROSSING}
 
@@ -139,6 +140,13 @@ class Stefan:
         C.check(self._lib.lbm_stefan_get_field(
             self.h, C.FIELD_T, ctypes.c_void_p(T.ctypes.data)), self.h)
         return T
+
+    def liquid(self):
+        """Liquid fraction of every node (the scheme's own definition)."""
+        L = np.empty((self.prob.ny, self.prob.nx))
+        C.check(self._lib.lbm_stefan_get_field(
+            self.h, C.FIELD_LIQUID, ctypes.c_void_p(L.ctypes.data)), self.h)
+        return L
 
     def state(self):
         s = np.empty((self.prob.q, self.prob.ny, self.prob.nx),
