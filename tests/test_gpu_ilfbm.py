@@ -123,6 +123,11 @@ CASES = [
         n=96, ny=40, storage=s).with_(scheme="ilfbm", max_it=300,
                                        tol=ITER_TOL, ste=0.3,
                                        T0=np.full((40, 96), -0.5)), 300),
+    # above 16384 nodes: one launch per inner iteration (the smaller
+    # lattices run whole steps in one resident workgroup)
+    ("d2q9_quarter_multilaunch", lambda s: synth.freezing_cavity_2d(
+        n=131, q=9, storage=s, scheme="ilfbm").with_(
+            max_it=300, tol=ITER_TOL), 30),
     # D2Q5 quarter cavity: the inner loop hits its cap (few steps only:
     # the non-converged iterates amplify rounding differences)
     ("d2q5_quarter_capped", lambda s: synth.freezing_cavity_2d(
