@@ -446,7 +446,8 @@ def summarize_profiles(run, args):
 
     trace_cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof_all -o all"
                  f" -- python bench.py --steps {args.steps} --warmup 5 --variant {V}"
-                 f" --no-autotune --no-cpu-baseline --batch-steps {args.batch_steps}"
+                 f" --no-autotune --no-cpu-baseline --forms plain,batched,adjoint,eebm"
+                 f" --batch-steps {args.batch_steps}"
                  f" --batch-variant {BV} --batch-bpc {BB}")
     pmc_cmd = ("rocprofv3 --pmc {C} -d gpurun_out/{D} -o {O} -- python bench.py"
                f" --traffic-sweep --batch-steps 4 --batch-variant {BV}"
