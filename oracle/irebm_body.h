@@ -226,10 +226,15 @@ static int RN(source)(const orc_params *p, long x, long y, int ex, int ey,
 static int RN(leaves_by_bounceback)(const orc_params *p, long x, long y,
                                     int ex, int ey) {
   long a = x - ex, b = y - ey;
-  if (a < 0 && p->bc[0] != ORC_BOUNCEBACK) return 0;
-  if (a >= p->nx && p->bc[1] != ORC_BOUNCEBACK) return 0;
-  if (b < 0 && p->bc[2] != ORC_BOUNCEBACK) return 0;
-  if (b >= p->ny && p->bc[3] != ORC_BOUNCEBACK) return 0;
+  /* a periodic axis wraps: crossing its seam leaves nothing */
+  if (a < 0 && p->bc[0] != ORC_BOUNCEBACK && p->bc[0] != ORC_PERIODIC)
+    return 0;
+  if (a >= p->nx && p->bc[1] != ORC_BOUNCEBACK && p->bc[1] != ORC_PERIODIC)
+    return 0;
+  if (b < 0 && p->bc[2] != ORC_BOUNCEBACK && p->bc[2] != ORC_PERIODIC)
+    return 0;
+  if (b >= p->ny && p->bc[3] != ORC_BOUNCEBACK && p->bc[3] != ORC_PERIODIC)
+    return 0;
   return 1;
 }
 

@@ -353,15 +353,17 @@ __device__ __forceinline__ void load_node(const StepArgs &A,
 }
 
 // Does the unknown direction i of node (x, y) leave the lattice only
-// through bounce-back walls?
+// through bounce-back walls?  (A periodic axis wraps and is never left.)
 template <int Q>
 __device__ __forceinline__ bool leaves_by_bounceback(const StepArgs &A, int x, int y,
                                             int i) {
   const int sx = x - cx<Q>(i), sy = y - cy<Q>(i);
-  if (sx < 0 && A.bc[0] != BC_BOUNCEBACK) return false;
-  if (sx >= A.nx && A.bc[1] != BC_BOUNCEBACK) return false;
-  if (Q > 3 && sy < 0 && A.bc[2] != BC_BOUNCEBACK) return false;
-  if (Q > 3 && sy >= A.ny && A.bc[3] != BC_BOUNCEBACK) return false;
+  if (sx < 0 && A.bc[0] != BC_BOUNCEBACK && !A.periodic_x) return false;
+  if (sx >= A.nx && A.bc[1] != BC_BOUNCEBACK && !A.periodic_x) return false;
+  if (Q > 3 && sy < 0 && A.bc[2] != BC_BOUNCEBACK && !A.periodic_y)
+    return false;
+  if (Q > 3 && sy >= A.ny && A.bc[3] != BC_BOUNCEBACK && !A.periodic_y)
+    return false;
   return true;
 }
 

@@ -48,6 +48,12 @@ CASES = [
         n=22, ny=9, nsteps=50, storage=st).with_(
             tau=0.8, ste=0.2, delta=1.5 / 21, max_it=40,
             wall_profile=(np.ones(9), None, None, None))),
+    # a bounce-back wall beside a periodic axis (diagonals across the seam)
+    ("d2q9_bounceback_periodic", lambda st: synth.cavity_2d(
+        n=22, ny=9, nsteps=50, storage=st).with_(
+            tau=0.8, ste=0.2, delta=1.5 / 21, max_it=40,
+            bc=("dirichlet", "bounceback", "periodic", "periodic"),
+            wall_profile=(np.ones(9), None, None, None))),
 ]
 
 

@@ -153,6 +153,9 @@ CASES = [
             tm=0.1,
             wall_profile=(0.5 + 0.4 * np.sin(np.linspace(0, 3, 66)), None,
                           0.1 * np.cos(np.linspace(0, 5, 90)), None)), 300),
+    ("d2q9_melt_bounceback_x_periodic_y", lambda s: _melt_field(
+        synth.cavity_2d(n=81, ny=46, storage=s)).with_(
+            bc=("bounceback", "bounceback", "periodic", "periodic")), 300),
     ("d2q5_tiny_3x3", lambda s: synth.planar_2d(n=3, ny=3, storage=s), 40),
 ]
 

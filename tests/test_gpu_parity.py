@@ -146,6 +146,14 @@ CASES = [
             bc=("dirichlet", "bounceback", "dirichlet", "bounceback"),
             wall_profile=(0.02 * np.sin(np.linspace(0, 3, 66)), None,
                           0.01 * np.cos(np.linspace(0, 5, 90)), None)), 200),
+    # bounce-back walls beside a periodic axis: diagonals entering at the
+    # first and last rows cross the seam and still bounce back
+    ("d2q9_bounceback_x_periodic_y", lambda s: _smooth_mushy(synth.cavity_2d(
+        n=81, ny=46, storage=s)).with_(
+            bc=("bounceback", "bounceback", "periodic", "periodic")), 200),
+    ("d2q9_periodic_x_bounceback_y", lambda s: _smooth_mushy(synth.cavity_2d(
+        n=77, ny=52, storage=s)).with_(
+            bc=("periodic", "periodic", "bounceback", "bounceback")), 200),
     ("d2q5_tiny_3x3", lambda s: synth.planar_2d(n=3, ny=3, storage=s), 40),
     ("d1q3_plain_newton", lambda s: synth.stefan_1d(nx=333).with_(
         newton_mode="plain", storage=s), 500),

@@ -254,26 +254,32 @@ def test_long_run_reaches_linear_steady_state():
     assert np.max(np.abs(T - exact)) < 1e-12
 
 
+@pytest.mark.parametrize("xwalls", [("dirichlet", "dirichlet"),
+                                    ("dirichlet", "bounceback")])
 @pytest.mark.parametrize("q,nx", [(5, 40), (9, 40)])
-def test_2d_with_uniform_rows_equals_1d(q, nx):
+def test_2d_with_uniform_rows_equals_1d(q, nx, xwalls):
     """With y-uniform data and a periodic y axis, the sums of the D2Q5/D2Q9
     populations sharing an x velocity evolve as D1Q3 (weights 2/3, 1/6,
-    1/6), and Dirichlet deficits shared by weight add up to the D1Q3 one."""
-    lam = O.stefan_lambda(0.1, -0.5)
+    1/6), and Dirichlet deficits shared by weight add up to the D1Q3 one.
+    With a bounce-back x wall, every D2Q9 diagonal entering through it
+    bounces back (its source also crosses the periodic seam at the first
+    and last rows, which wraps), as the D1Q3 population does."""
     x = np.arange(nx) / (nx - 1)
-    T1 = O.neumann_T(x, 0.004, lam, -0.5)
-    p1 = _prob1d(nx, 0.8, 0.1, 0.03, T1)
+    T1 = 0.4 * np.sin(3 * np.pi * x)        # crosses T_m = 0 twice
+    bc = xwalls + ("periodic", "periodic")
+    p1 = _prob1d(nx, 0.8, 0.1, 0.03, T1).with_(bc=bc)
     f1 = O.init(p1, p1.T0)
     f1, _ = O.run(p1, f1, 400)
     m = 6
     p2 = synth.Problem(dim=2, q=q, nx=nx, ny=m, tau=0.8, ste=0.1, delta=0.03,
-                       bc=DIR2, wall_T=(1.0, -0.5, 0.0, 0.0),
+                       bc=bc, wall_T=(1.0, -0.5, 0.0, 0.0),
                        T0=np.broadcast_to(T1, (m, nx)))
     f2 = O.init(p2, p2.T0)
     f2, _ = O.run(p2, f2, 400)
     T1f = O.temperature(p1, f1)[0]
     T2f = O.temperature(p2, f2)
     assert np.max(np.abs(T2f - T1f[None, :])) < 1e-13
+    assert abs(T1f[-2] - T1[-2]) > 1e-3      # the far wall took part
 
 
 def test_pure_diffusion_second_order_against_erfc():
