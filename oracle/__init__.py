@@ -6,12 +6,14 @@ step of Luddens, Lothode and Danaila (arXiv 2505.13097), Algorithm 3
 (Section 4.1), with the boundary closures of Section 4.2, the Neumann
 similarity solution of Section 2 and a reverse mode of the step; and the
 explicit enthalpy based method the paper compares with (Algorithm 2),
-selected by ``prob.scheme == "eebm"``.
+selected by ``prob.scheme == "eebm"``; and both on the 3D lattices D3Q7 and
+D3Q19 (``prob.dim == 3``).
 
 Only the tests, the smoke check and the CPU-baseline leg of the bench may
 import it.  It shares no code with the GPU library: the C sources in this
 directory are compiled with gcc into ``liboracle.so`` and called through
-ctypes below.  The state is the distribution functions f[i][y][x].
+ctypes below.  The state is the distribution functions f[i][y][x]
+(f[i][z][y][x] in 3D).
 """
 import ctypes
 import os
@@ -21,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ("irebm.c", "irebm_cs.c", "eebm.c", "ilfbm.c")
+SOURCES = ("irebm.c", "irebm_cs.c", "eebm.c", "ilfbm.c", "lattice3d.c")
 
 DIRICHLET, BOUNCEBACK, PERIODIC, NEUMANN = 0, 1, 2, 3
 SAFEGUARDED, PLAIN = 0, 1
@@ -50,6 +52,8 @@ class Params(ctypes.Structure):
         ("wall_profile", ctypes.POINTER(ctypes.c_double) * 4),
         ("tol", ctypes.c_double), ("max_it", ctypes.c_int),
         ("newton_mode", ctypes.c_int), ("dx", ctypes.c_double),
+        ("nz", ctypes.c_long), ("bc_z", ctypes.c_int * 2),
+        ("wall_T_z", ctypes.c_double * 2), ("scheme", ctypes.c_int),
     ]
 
 
@@ -115,6 +119,14 @@ def lib():
             "orc_ilfbm_energy": [P, dp, dp],
             "orc_ilfbm_front": [P, dp, ctypes.c_int, dp],
             "orc_ilfbm_collide": [P, dp, dp],
+            "orc_lattice3": [ctypes.c_int, ip, ip, ip, dp, ip],
+            "orc3_init": [P, dp, dp],
+            "orc3_step": [P, dp, dp, S],
+            "orc3_run": [P, dp, ctypes.c_long, S, dp, dp],
+            "orc3_temperature": [P, dp, dp],
+            "orc3_energy": [P, dp, dp],
+            "orc3_front": [P, dp, ctypes.c_int, dp],
+            "orc3_collide": [P, dp, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -163,14 +175,36 @@ class Setup:
         nm = prob.newton_mode
         p.newton_mode = _NEWTON[nm] if isinstance(nm, str) else int(nm)
         p.dx = prob.dx
+        scheme = getattr(prob, "scheme", "irebm")
+        self.nz = getattr(prob, "nz", 1) if prob.dim == 3 else 1
+        p.nz = self.nz
+        if prob.dim == 3:
+            for k in range(2):
+                b = prob.bc_z[k]
+                p.bc_z[k] = _BC[b] if isinstance(b, str) else int(b)
+                p.wall_T_z[k] = prob.wall_T_z[k]
+            p.scheme = {"irebm": 0, "eebm": 1}.get(scheme, -1)
         self.p = p
         self.q, self.nx, self.ny = prob.q, prob.nx, prob.ny
+        self.dim = prob.dim
         # the implicit liquid fraction scheme carries l as one more plane
-        self.planes = prob.q + (getattr(prob, "scheme", "irebm") == "ilfbm")
+        self.planes = prob.q + (scheme == "ilfbm")
+
+    @property
+    def field(self):
+        """shape of a node field"""
+        if self.dim == 3:
+            return (self.nz, self.ny, self.nx)
+        return (self.ny, self.nx)
+
+    @property
+    def rows(self):
+        """number of rows along x (front values)"""
+        return self.ny * self.nz
 
     @property
     def shape(self):
-        return (self.planes, self.ny, self.nx)
+        return (self.planes,) + self.field
 
     def ref(self):
         return ctypes.byref(self.p)
@@ -211,7 +245,10 @@ def newton(m0, theta, ste, tm, delta, tol=1e-12, max_it=20,
 
 
 def _fn(prob, name):
-    """orc_<name>, or orc_<scheme>_<name> for the comparison schemes."""
+    """orc_<name>, or orc_<scheme>_<name> for the comparison schemes, or
+    orc3_<name> on the 3D lattices (the scheme travels in the params)."""
+    if prob.dim == 3:
+        return getattr(lib(), "orc3_" + name)
     scheme = getattr(prob, "scheme", "irebm")
     if scheme in ("eebm", "ilfbm"):
         return getattr(lib(), f"orc_{scheme}_" + name)
@@ -245,10 +282,29 @@ def ilfbm_collide(prob, f):
     return out
 
 
+def lattice3(q):
+    """D3Q7 / D3Q19 tables: (ex, ey, ez, w, opp)."""
+    t = [(ctypes.c_int * q)() for _ in range(3)]
+    w = (ctypes.c_double * q)()
+    opp = (ctypes.c_int * q)()
+    _check(lib().orc_lattice3(q, t[0], t[1], t[2], w, opp), "orc_lattice3")
+    return tuple(np.array(a[:]) for a in t) + (np.array(w[:]),
+                                                np.array(opp[:]))
+
+
+def collide(prob, f):
+    """Post-collision populations of a 3D state f (the GPU state)."""
+    s = Setup(prob)
+    f = _f64(f)
+    out = np.empty_like(f)
+    _check(lib().orc3_collide(s.ref(), _dp(f), _dp(out)), "orc3_collide")
+    return out
+
+
 def init(prob, T0=None):
     s = Setup(prob)
     f = np.zeros(s.shape)
-    T0a = None if T0 is None else _f64(np.broadcast_to(T0, (s.ny, s.nx)))
+    T0a = None if T0 is None else _f64(np.broadcast_to(T0, s.field))
     _check(_fn(prob, "init")(s.ref(), _dp(T0a), _dp(f)), "init")
     return f
 
@@ -279,7 +335,7 @@ def run(prob, f, nsteps, trace=False):
 
 def temperature(prob, f):
     s = Setup(prob)
-    T = np.empty((s.ny, s.nx))
+    T = np.empty(s.field)
     _check(_fn(prob, "temperature")(s.ref(), _dp(_f64(f)), _dp(T)),
            "temperature")
     return T
@@ -294,10 +350,11 @@ def energy(prob, f):
 
 
 def front(prob, f, mode=FRONT_INTEGRAL):
+    """Front per row along x: shape (ny,), or (nz, ny) in 3D."""
     s = Setup(prob)
-    xf = np.empty(s.ny)
+    xf = np.empty(s.rows)
     _check(_fn(prob, "front")(s.ref(), _dp(_f64(f)), mode, _dp(xf)), "front")
-    return xf
+    return xf.reshape(s.nz, s.ny) if s.dim == 3 else xf
 
 
 def stefan_lambda(ste, theta0):

@@ -10,7 +10,8 @@
  * the tests, by the smoke check and by the CPU-baseline leg of the bench.
  *
  * State layout: distribution functions f[i][y][x] (plane i of q planes,
- * row-major, nx fastest), double precision.  1D lattices use ny = 1.
+ * row-major, nx fastest), double precision.  1D lattices use ny = 1; the
+ * 3D lattices (lattice3d.c) use f[i][z][y][x].
  *
  * Every function returns 0 on success and -1 on an invalid argument.
  */
@@ -26,11 +27,12 @@ extern "C" {
 enum { ORC_DIRICHLET = 0, ORC_BOUNCEBACK = 1, ORC_PERIODIC = 2,
        ORC_NEUMANN = 3 };
 enum { ORC_SAFEGUARDED = 0, ORC_PLAIN = 1 };
+enum { ORC_IREBM = 0, ORC_EEBM = 1 };   /* scheme of the 3D functions */
 enum { ORC_FRONT_INTEGRAL = 0, ORC_FRONT_CROSSING = 1 };
 
 typedef struct {
-  int dim;              /* 1 or 2 */
-  int q;                /* 3 (D1Q3), 5 (D2Q5) or 9 (D2Q9) */
+  int dim;              /* 1, 2 or 3 */
+  int q;                /* 3 (D1Q3), 5 (D2Q5), 9 (D2Q9), 7 (D3Q7), 19 (D3Q19) */
   long nx, ny;          /* node counts; ny = 1 in 1D */
   double tau;           /* BGK relaxation time */
   double ste;           /* Stefan number */
@@ -44,6 +46,11 @@ typedef struct {
   int max_it;           /* Newton iteration cap */
   int newton_mode;      /* ORC_SAFEGUARDED or ORC_PLAIN */
   double dx;            /* lattice spacing, used by the front position */
+  /* 3D lattices only (orc3_*): */
+  long nz;              /* node count along z */
+  int bc_z[2];          /* walls z-, z+ */
+  double wall_T_z[2];   /* their Dirichlet temperatures */
+  int scheme;           /* ORC_IREBM or ORC_EEBM */
 } orc_params;
 
 typedef struct {
@@ -146,6 +153,25 @@ int orc_ilfbm_front(const orc_params *p, const double *f, int mode,
                     double *xf);
 /* collision without source of the q population planes of f */
 int orc_ilfbm_collide(const orc_params *p, const double *f, double *omega);
+
+/* The 3D lattices D3Q7 and D3Q19 (lattice3d.c): one step of IREBM
+   (Algorithm 3) or EEBM (Algorithm 2), selected by p->scheme, with
+   constant wall temperatures (wall_profile must be NULL).  State
+   f[i][z][y][x]; fields [z][y][x]; the front has one value per row along
+   x, rows ordered [z][y].  Statistics as for 2D (bisections not counted).
+   Velocities: rest, +x, +y, +z, -x, -y, -z, then (1,1,0), (1,-1,0),
+   (1,0,1), (1,0,-1), (0,1,1), (0,1,-1) and their negatives. */
+int orc_lattice3(int q, int *ex, int *ey, int *ez, double *w, int *opp);
+int orc3_init(const orc_params *p, const double *T0, double *f);
+int orc3_step(const orc_params *p, const double *f, double *fout,
+              orc_stats *st);
+int orc3_run(const orc_params *p, double *f, long nsteps, orc_stats *st,
+             double *energy_trace, double *flux_trace);
+int orc3_temperature(const orc_params *p, const double *f, double *T);
+int orc3_energy(const orc_params *p, const double *f, double *E);
+int orc3_front(const orc_params *p, const double *f, int mode, double *xf);
+/* the post-collision populations of every node */
+int orc3_collide(const orc_params *p, const double *f, double *omega);
 
 #ifdef __cplusplus
 }

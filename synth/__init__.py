@@ -9,7 +9,9 @@ Conventions (the problem statement of Section 2 in scaled form):
   * temperatures are the scaled theta = (T - T_f)/(T_h - T_f): hot wall 1,
     melting temperature 0;
   * ``nx`` counts nodes on x in [0, 1], so dx = 1/(nx - 1); wall nodes are
-    lattice nodes; a periodic y axis of ny nodes has period ny*dx;
+    lattice nodes; a periodic y (or z) axis of ny nodes has period ny*dx;
+  * 3D lattices (dim 3, D3Q7 or D3Q19) add ``nz`` and the z walls; fields
+    are [z][y][x];
   * ``delta`` (the width of the regularized liquid fraction) is in
     temperature units; workloads quoted in cells use delta = cells * dx.
 
@@ -52,6 +54,9 @@ class Problem:
     name: str = ""
     dx: float = field(default=None)
     scheme: str = "irebm"  # "irebm" (Algorithm 3) or "eebm" (Algorithm 2)
+    nz: int = 1            # 3D lattices: nodes along z
+    bc_z: tuple = ("periodic", "periodic")   # z-, z+ (3D)
+    wall_T_z: tuple = (0.0, 0.0)
 
     def __post_init__(self):
         if self.dx is None:
@@ -59,7 +64,14 @@ class Problem:
 
     @property
     def nodes(self):
-        return self.nx * self.ny
+        return self.nx * self.ny * (self.nz if self.dim == 3 else 1)
+
+    @property
+    def field_shape(self):
+        """shape of a node field: (ny, nx), or (nz, ny, nx) in 3D"""
+        if self.dim == 3:
+            return (self.nz, self.ny, self.nx)
+        return (self.ny, self.nx)
 
     def with_(self, **kw):
         return replace(self, **kw)
@@ -204,3 +216,41 @@ def adjoint_2d(n=512, ny=None, nsteps=4096, storage="f32"):
                    tol=1e-12, max_it=32, storage=storage,
                    T0=np.full((ny, n), -0.5), nsteps=nsteps,
                    name=f"adjoint2d_d2q5_{storage}_{n}x{ny}")
+
+
+def cavity_3d(n=512, ny=None, nz=None, q=19, nsteps=200, seed=DEFAULT_SEED,
+              storage="f32", scheme="irebm"):
+    """3D melting in a cube heated at one face, D3Q19 (or D3Q7): x = 0 at
+    +1, x = 1 at -0.5, adiabatic (bounce-back) y and z walls, initial -0.5
+    plus seeded noise of +-1e-3, Ste log-uniform from the seed (as the 2D
+    cavity), delta 1.5 cells, tau 0.6."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    T0 = -0.5 + node_noise(seed, n * ny * nz, 1e-3).reshape(nz, ny, n)
+    return Problem(dim=3, q=q, nx=n, ny=ny, nz=nz, tau=0.6,
+                   ste=cavity_ste(seed), delta=1.5 / (n - 1),
+                   bc=("dirichlet", "dirichlet", "bounceback", "bounceback"),
+                   bc_z=("bounceback", "bounceback"),
+                   wall_T=(1.0, -0.5, 0.0, 0.0), tol=1e-12, max_it=32,
+                   storage=storage, T0=T0, nsteps=nsteps, scheme=scheme,
+                   name=f"cavity3d_d3q{q}_{scheme}_{storage}_{n}x{ny}x{nz}")
+
+
+def freezing_cube_3d(n=61, q=7, storage="f64", scheme="irebm", delta=0.02,
+                     tau=0.84, t_end=FREEZE_T_END):
+    """The freezing case of Section 6.2 taken to 3D: one octant of a cube
+    of water at 10 C cooled to -20 C on every face, so Dirichlet -2 on the
+    x-, y- and z- faces and symmetry (Neumann, eq. Neu_on_q) on x+, y+ and
+    z+; 4 x 4 x 4 in units of 1 m, n nodes per edge, other parameters as
+    freezing_cavity_2d."""
+    dx = FREEZE_SIDE / (n - 1)
+    dt = (tau - 0.5) * dx * dx / 3.0
+    return Problem(dim=3, q=q, nx=n, ny=n, nz=n, tau=tau, ste=FREEZE_STE,
+                   delta=delta,
+                   bc=("dirichlet", "neumann", "dirichlet", "neumann"),
+                   bc_z=("dirichlet", "neumann"),
+                   wall_T=(-2.0, 0.0, -2.0, 0.0), wall_T_z=(-2.0, 0.0),
+                   tol=1e-12, max_it=32, storage=storage,
+                   T0=np.ones((n, n, n)), nsteps=int(round(t_end / dt)),
+                   dx=dx, scheme=scheme,
+                   name=f"freeze3d_d3q{q}_{scheme}_{storage}_{n}")
