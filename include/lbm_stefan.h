@@ -33,9 +33,21 @@
  *     D1Q3 (2/3, 1/6, 1/6), D2Q5 (1/3, 1/6 x4), D2Q9 (4/9, 1/9 x4,
  *     1/36 x4): the "standard weights" of Section 3.2, whose second moment
  *     is T/3 times the identity as the Chapman-Enskog analysis requires.
+ *   - 3D lattices (dim 3; the enthalpy model of Section 2 holds in 3D):
+ *     D3Q7 and D3Q19.  Velocity order: rest, +x, +y, +z, -x, -y, -z, then
+ *     (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1), (0,1,-1) and their
+ *     negatives in that order (D3Q7: the first seven).  The same second
+ *     moment fixes D3Q19 (1/3, 1/18 x6, 1/36 x12) and D3Q7 (faces 1/6,
+ *     rest 0).  Planes and fields are [nz][ny][nx]; fronts have one value
+ *     per row along x, rows ordered [nz][ny].  The six faces x-, x+, y-,
+ *     y+, z-, z+ take the closures of the 2D walls (the first Dirichlet
+ *     face in that order gives a node's temperature) with constant
+ *     temperatures (no wall profiles).  Schemes IREBM and EEBM; no reverse
+ *     mode, no batched form; kernel variants of their own.
  *   - The state is the set of post-collision populations
  *     Omega_i = (1 - 1/tau) f_i + (w_i/tau) T  (eq. def_qi_omegai) at the
- *     current time, stored as q planes [q][ny][nx] (x fastest) in the
+ *     current time, stored as q planes [q][ny][nx] (3D: [q][nz][ny][nx];
+ *     x fastest) in the
  *     storage type (double or float).  T = sum_i Omega_i = sum_i f_i.
  *     EEBM: Omega_i = f_i - (f_i - f_i^eq)/tau, the populations after the
  *     collision of Algorithm 2 and before its streaming; sum_i Omega_i =
@@ -122,8 +134,8 @@ extern "C" {
                               (IREBM), l(H) (EEBM), the l plane (ILFBM) */
 
 typedef struct lbm_stefan_params {
-  int32_t dim;           /* 1 or 2 */
-  int32_t q;             /* 3 (dim 1), 5 or 9 (dim 2) */
+  int32_t dim;           /* 1, 2 or 3 */
+  int32_t q;             /* 3 (dim 1), 5 or 9 (dim 2), 7 or 19 (dim 3) */
   int64_t nx, ny;        /* node counts; ny = 1 when dim = 1 */
   int32_t storage;       /* LBM_STORE_F64 or LBM_STORE_F32 */
   int32_t newton_mode;   /* LBM_NEWTON_* */
@@ -150,6 +162,9 @@ typedef struct lbm_stefan_params {
                             picks the library default for the lattice */
   int32_t flags;         /* LBM_FLAG_* */
   int32_t scheme;        /* LBM_SCHEME_*; 0 (zeroed params) is IREBM */
+  int64_t nz;            /* dim 3: nodes along z, >= 3; ignored otherwise */
+  int32_t bc_z[2];       /* dim 3: faces z-, z+ (LBM_BC_*) */
+  double wall_T_z[2];    /* dim 3: their Dirichlet temperatures */
 } lbm_stefan_params;
 
 #define LBM_FLAG_ADJOINT 1 /* reserve workspace for the reverse mode */
@@ -193,17 +208,20 @@ int lbm_stefan_workspace_bytes(const lbm_stefan_params *p, size_t *bytes);
  * equilibrium state, f_i = w_i T0), with nodes on Dirichlet walls at their
  * wall temperature (where two Dirichlet walls meet, the first of x-, x+,
  * y-, y+ gives it).
- *   T0         host, nullable: initial temperature [ny][nx] (NULL: 0).
+ *   T0         host, nullable: initial temperature [ny][nx] (3D:
+ *              [nz][ny][nx]) (NULL: 0).
  *   workspace  device, >= lbm_stefan_workspace_bytes(p), 256-byte
  *              aligned; owned by the caller, must outlive the handle.
  *   stream     hipStream_t to enqueue on (NULL: the null stream).
  *   out        receives the handle (host memory owned by the library).
  * Blocks until the state is built.  Errors: EINVAL (invalid params:
  * tau <= 1/2, Ste <= 0, delta <= 0, tol <= 0, max_it outside 1..1000,
- * nx < 3, ny < 3 in 2D or != 1 in 1D, lattice/dim mismatch, a periodic
- * axis with one non-periodic wall, workspace too small or misaligned,
- * unknown variant or scheme, LBM_FLAG_ADJOINT with LBM_SCHEME_EEBM or
- * a Neumann wall, Neumann and bounce-back walls in one lattice), EDEVICE.
+ * nx < 3, ny < 3 in 2D or != 1 in 1D, nz < 3 in 3D, more than 2^31 - 1
+ * nodes, lattice/dim mismatch, a periodic axis with one non-periodic
+ * wall, workspace too small or misaligned, unknown variant or scheme,
+ * LBM_FLAG_ADJOINT with LBM_SCHEME_EEBM, a Neumann wall or a 3D lattice,
+ * Neumann and bounce-back walls in one lattice, a 3D lattice with a wall
+ * profile or LBM_SCHEME_ILFBM), EDEVICE.
  */
 int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
                     void *workspace, size_t bytes, void *stream,
@@ -223,7 +241,8 @@ int lbm_stefan_reset_stats(lbm_stefan_t *h);
 
 /*
  * Front position of every row of the current state (mode LBM_FRONT_*),
- * written to front (host, ny doubles, may be NULL), and the energy E
+ * written to front (host, ny doubles, 3D: nz*ny, may be NULL), and the
+ * energy E
  * (host, may be NULL).  Both reductions are FP64 in a fixed order.
  * Waits for the stream.  Errors: EINVAL (bad mode), ENAN, EDEVICE.
  */
@@ -232,8 +251,8 @@ int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
 
 /*
  * Copy a field of the current state to host memory: LBM_FIELD_T or
- * LBM_FIELD_LIQUID (ny*nx doubles) or LBM_FIELD_STATE (q*ny*nx values of
- * the storage type).
+ * LBM_FIELD_LIQUID (ny*nx doubles, 3D: nz*ny*nx) or LBM_FIELD_STATE
+ * (q times as many values of the storage type).
  * Waits for the stream.  Errors: EINVAL, EDEVICE.
  */
 int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host);
@@ -257,8 +276,9 @@ int lbm_stefan_state_ptr(lbm_stefan_t *h, void **dev_state);
    non-temporal stores, block order reversed every other step; or
    "256x<b>/t2/r<m>[/nt]": two time steps per launch, a 256-column window
    sweeping m rows, b rows per pass; a single trailing step then uses the
-   default variant, and the batched form rejects these); used by
-   autotuners. */
+   default variant, and the batched form rejects these; 3D lattices,
+   q = 7 or 19: "<tile_x>x<tile_y>/npt<k>/z<c>[/nt]", c z slices swept by
+   one block); used by autotuners. */
 int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count);
 const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
                                     int32_t variant);
@@ -269,7 +289,7 @@ int lbm_stefan_set_variant(lbm_stefan_t *h, int32_t variant);
 /*
  * Autotuner: time every compiled variant for `steps` steps (1..10000) with
  * HIP events on the handle's stream, keep the fastest.  The state is saved
- * to `scratch` (device, >= q*nx*ny*sizeof(storage) bytes, caller-owned)
+ * to `scratch` (device, >= q*nodes*sizeof(storage) bytes, caller-owned)
  * before the trials and restored after each one, so the handle's state
  * and step count are unchanged; statistics are reset.  Writes the chosen
  * variant and its time per step (ms); either output may be NULL.  Waits

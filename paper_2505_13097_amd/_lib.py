@@ -37,6 +37,8 @@ class Params(ctypes.Structure):
         ("newton_max_it", ctypes.c_int32), ("strict", ctypes.c_int32),
         ("variant", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("scheme", ctypes.c_int32),
+        ("nz", ctypes.c_int64), ("bc_z", ctypes.c_int32 * 2),
+        ("wall_T_z", ctypes.c_double * 2),
     ]
 
 

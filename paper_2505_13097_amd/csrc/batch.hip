@@ -83,6 +83,9 @@ std::string validate_batch(const lbm_stefan_params *ps, int32_t count) {
   for (int k = 0; k < count; ++k) {
     const std::string e = validate_params(&ps[k]);
     if (!e.empty()) return "instance " + std::to_string(k) + ": " + e;
+    if (ps[k].dim == 3)
+      return "instance " + std::to_string(k) +
+             ": the batched form takes 1D and 2D lattices";
     if (ps[k].q != ps[0].q || ps[k].storage != ps[0].storage ||
         ps[k].newton_mode != ps[0].newton_mode ||
         ps[k].scheme != ps[0].scheme)

@@ -119,6 +119,25 @@ hipError_t dispatch_qs(int q, int storage, F &&f) {
   }
 }
 
+// as dispatch_qs, also for the 3D lattices (q = 7, 19): for the kernels
+// that only loop over the q planes (fields, energy, front)
+template <typename F>
+hipError_t dispatch_qs_all(int q, int storage, F &&f) {
+  const bool f32 = storage == LBM_STORE_F32;
+  if (q == 7) return f32 ? f(QT<7>{}, TT<float>{}) : f(QT<7>{}, TT<double>{});
+  if (q == 19)
+    return f32 ? f(QT<19>{}, TT<float>{}) : f(QT<19>{}, TT<double>{});
+  return dispatch_qs(q, storage, f);
+}
+
+// nodes of a lattice, and its rows along x
+inline int64_t lattice_nodes(const lbm_stefan_params &p) {
+  return p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
+}
+inline int64_t lattice_rows(const lbm_stefan_params &p) {
+  return p.ny * (p.dim == 3 ? p.nz : 1);
+}
+
 #define QS_TYPES(qt, tt)                  \
   constexpr int Q = decltype(qt)::value; \
   using S = typename decltype(tt)::type
@@ -137,8 +156,8 @@ inline hipError_t energy_async(const lbm_stefan_params &p, const void *src,
                                double *partials, double *out,
                                hipStream_t stream,
                                const double *lf = nullptr) {
-  const int64_t n = p.nx * p.ny;
-  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
+  const int64_t n = lattice_nodes(p);
+  return dispatch_qs_all(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     const int64_t parts = (n + kEnergyChunk - 1) / kEnergyChunk;
     energy_partial_kernel<Q, S><<<(unsigned)parts, 256, 0, stream>>>(
@@ -150,21 +169,23 @@ inline hipError_t energy_async(const lbm_stefan_params &p, const void *src,
 }
 
 // per-row front of the state `src` of a lattice with params p (p.dx > 0)
-// into out[0..ny) (device); lf: the ILFBM liquid fraction plane
+// into out[0..rows) (device; rows ny, or nz * ny in 3D); lf: the ILFBM
+// liquid fraction plane
 inline hipError_t front_async(const lbm_stefan_params &p, const void *src,
                               int mode, double *out, hipStream_t stream,
                               const double *lf = nullptr) {
   const int eebm = p.scheme == LBM_SCHEME_EEBM;
-  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
+  const int64_t n = lattice_nodes(p);
+  const unsigned rows = (unsigned)lattice_rows(p);
+  return dispatch_qs_all(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     if (mode == LBM_FRONT_LIQUID_INTEGRAL)
-      front_integral_kernel<Q, S><<<(unsigned)p.ny, 256, 0, stream>>>(
-          (const S *)src, p.nx * p.ny, (int)p.nx, eebm, p.t_m, 1.0 / p.delta,
-          p.ste, lf, p.dx, out);
+      front_integral_kernel<Q, S><<<rows, 256, 0, stream>>>(
+          (const S *)src, n, (int)p.nx, eebm, p.t_m, 1.0 / p.delta, p.ste,
+          lf, p.dx, out);
     else
-      front_crossing_kernel<Q, S><<<(unsigned)p.ny, 256, 0, stream>>>(
-          (const S *)src, p.nx * p.ny, (int)p.nx, eebm, p.t_m, 1.0 / p.ste,
-          p.dx, out);
+      front_crossing_kernel<Q, S><<<rows, 256, 0, stream>>>(
+          (const S *)src, n, (int)p.nx, eebm, p.t_m, 1.0 / p.ste, p.dx, out);
     return hipGetLastError();
   });
 }
@@ -173,8 +194,8 @@ inline hipError_t front_async(const lbm_stefan_params &p, const void *src,
 inline hipError_t temperature_async(const lbm_stefan_params &p,
                                     const void *src, double *T,
                                     hipStream_t stream) {
-  const int64_t n = p.nx * p.ny;
-  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
+  const int64_t n = lattice_nodes(p);
+  return dispatch_qs_all(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     temp_kernel<Q, S><<<blocks_for(n, 256), 256, 0, stream>>>(
         (const S *)src, n, p.scheme == LBM_SCHEME_EEBM, p.t_m, 1.0 / p.ste,
@@ -187,8 +208,8 @@ inline hipError_t temperature_async(const lbm_stefan_params &p,
 inline hipError_t liquid_async(const lbm_stefan_params &p, const void *src,
                                const double *lf, double *out,
                                hipStream_t stream) {
-  const int64_t n = p.nx * p.ny;
-  return dispatch_qs(p.q, p.storage, [&](auto qt, auto tt) {
+  const int64_t n = lattice_nodes(p);
+  return dispatch_qs_all(p.q, p.storage, [&](auto qt, auto tt) {
     QS_TYPES(qt, tt);
     liquid_kernel<Q, S><<<blocks_for(n, 256), 256, 0, stream>>>(
         (const S *)src, n, p.scheme == LBM_SCHEME_EEBM, p.t_m, 1.0 / p.delta,

@@ -158,9 +158,10 @@ __host__ __device__ __forceinline__ double eebm_lf(double H, double tm,
 // (F' >= 1 and 0 <= phi <= 1 make it valid), bisect when the step leaves
 // the bracket or fails to halve the step before the last.  Stops when
 // |t_{k+1} - t_k| <= tol, then takes one more Newton step (below).
-template <bool PLAIN>
+// AR: any argument block with inv_ste, tm, inv_delta, tol and max_it.
+template <bool PLAIN, class AR>
 __device__ __forceinline__ double newton(double m0, double th, double pth,
-                                const StepArgs &A, int &iters, bool &conv) {
+                                const AR &A, int &iters, bool &conv) {
   const double s = A.inv_ste;
   const double c = m0 + pth * s;
   double lo = c - s, hi = c;

@@ -1,0 +1,4 @@
+// 3D step kernels, plain node update (see launch3.hpp)
+#include "launch3.hpp"
+
+IREBM_INSTANTIATE_STEP3(irebm::kPlain);

@@ -1,0 +1,5 @@
+// 3D step kernels, plain node update with the Neumann closure (see
+// launch3.hpp)
+#include "launch3.hpp"
+
+IREBM_INSTANTIATE_STEP3(irebm::kPlain | irebm::kNeumann);

@@ -35,14 +35,34 @@ thread_local std::string g_err = "no error";
 std::string irebm::validate_params(const lbm_stefan_params *p) {
   if (!p) return "params is NULL";
   const bool lat = (p->dim == 1 && p->q == 3) ||
-                   (p->dim == 2 && (p->q == 5 || p->q == 9));
-  if (!lat) return "lattice must be D1Q3, D2Q5 or D2Q9";
+                   (p->dim == 2 && (p->q == 5 || p->q == 9)) ||
+                   (p->dim == 3 && (p->q == 7 || p->q == 19));
+  if (!lat) return "lattice must be D1Q3, D2Q5, D2Q9, D3Q7 or D3Q19";
   if (p->nx < 3) return "nx must be >= 3";
   if (p->dim == 1 && p->ny != 1) return "ny must be 1 for a 1D lattice";
-  if (p->dim == 2 && p->ny < 3) return "ny must be >= 3 for a 2D lattice";
-  if (p->nx * p->ny > ((int64_t)1 << 31) - 1)
-    return "nx * ny must be below 2^31";
-  if (p->nx > INT32_MAX || p->ny > INT32_MAX) return "nx, ny too large";
+  if (p->dim >= 2 && p->ny < 3) return "ny must be >= 3 for a 2D or 3D lattice";
+  if (p->dim == 3 && p->nz < 3) return "nz must be >= 3 for a 3D lattice";
+  if (p->nx > INT32_MAX || p->ny > INT32_MAX ||
+      (p->dim == 3 && p->nz > INT32_MAX))
+    return "nx, ny, nz too large";
+  if (p->nx * p->ny * (p->dim == 3 ? p->nz : 1) > ((int64_t)1 << 31) - 1)
+    return "the node count must be below 2^31";
+  if (p->dim == 3) {
+    if (p->scheme == LBM_SCHEME_ILFBM)
+      return "3D lattices run the IREBM and EEBM schemes";
+    if (p->flags & LBM_FLAG_ADJOINT)
+      return "the reverse mode is for 1D and 2D lattices";
+    for (int k = 0; k < 4; ++k)
+      if (p->wall_profile[k])
+        return "3D lattices take constant wall temperatures (no profiles)";
+    for (int k = 0; k < 2; ++k) {
+      if (p->bc_z[k] < LBM_BC_DIRICHLET || p->bc_z[k] > LBM_BC_NEUMANN)
+        return "unknown boundary kind";
+      if (!std::isfinite(p->wall_T_z[k])) return "wall_T must be finite";
+    }
+    if ((p->bc_z[0] == LBM_BC_PERIODIC) != (p->bc_z[1] == LBM_BC_PERIODIC))
+      return "z walls: both or neither periodic";
+  }
   if (p->storage != LBM_STORE_F64 && p->storage != LBM_STORE_F32)
     return "storage must be LBM_STORE_F64 or LBM_STORE_F32";
   if (p->newton_mode != LBM_NEWTON_SAFEGUARDED &&
@@ -71,6 +91,10 @@ std::string irebm::validate_params(const lbm_stefan_params *p) {
     neu |= p->bc[k] == LBM_BC_NEUMANN;
     bb |= p->bc[k] == LBM_BC_BOUNCEBACK;
   }
+  for (int k = 0; p->dim == 3 && k < 2; ++k) {
+    neu |= p->bc_z[k] == LBM_BC_NEUMANN;
+    bb |= p->bc_z[k] == LBM_BC_BOUNCEBACK;
+  }
   if (neu && bb) return "Neumann and bounce-back walls do not mix";
   if (neu && (p->flags & LBM_FLAG_ADJOINT))
     return "the reverse mode has no Neumann closure";
@@ -80,20 +104,28 @@ std::string irebm::validate_params(const lbm_stefan_params *p) {
       (p->bc[2] == LBM_BC_PERIODIC) != (p->bc[3] == LBM_BC_PERIODIC))
     return "y walls: both or neither periodic";
   int nv;
-  variants(p->q, &nv);
+  if (p->dim == 3) variants3(&nv);
+  else variants(p->q, &nv);
   if (p->variant < -1 || p->variant >= nv) return "unknown kernel variant";
   return "";
 }
 
 irebm::Layout irebm::layout_for(const lbm_stefan_params *p) {
   Layout L;
-  const int64_t n = p->nx * p->ny;
+  const int64_t n = nodes_of(*p);
   const size_t s = p->storage == LBM_STORE_F64 ? 8 : 4;
   L.buf_bytes = align256((size_t)p->q * n * s);
   int nv;
-  const Variant *v = variants(p->q, &nv);
   int64_t mt = 0;
-  for (int i = 0; i < nv; ++i) mt = std::max(mt, items_for(v[i], p->nx, p->ny));
+  if (p->dim == 3) {
+    const Variant3 *v3 = variants3(&nv);
+    for (int i = 0; i < nv; ++i)
+      mt = std::max(mt, items3_for(v3[i], p->nx, p->ny, p->nz));
+  } else {
+    const Variant *v = variants(p->q, &nv);
+    for (int i = 0; i < nv; ++i)
+      mt = std::max(mt, items_for(v[i], p->nx, p->ny));
+  }
   L.max_items = mt;
   L.n_partials = (n + kEnergyChunk - 1) / kEnergyChunk;
   size_t off = 0;
@@ -111,7 +143,7 @@ irebm::Layout irebm::layout_for(const lbm_stefan_params *p) {
   L.off_partials = off;
   off += align256((size_t)L.n_partials * 8);
   L.off_small = off;
-  off += align256((size_t)(std::max<int64_t>(p->ny, 16) + 16) * 8);
+  off += align256((size_t)(std::max<int64_t>(rows_of(*p), 16) + 16) * 8);
   L.adjoint = (p->flags & LBM_FLAG_ADJOINT) != 0;
   L.off_adj = off;
   if (L.adjoint) off += adjoint_bytes(p, mt);
@@ -160,6 +192,37 @@ void irebm::fill_args(const lbm_stefan_params &p, double *const prof[4],
   }
 }
 
+void irebm::fill_args3(const lbm_stefan_params &p, StepArgs3 *A) {
+  std::memset(A, 0, sizeof(*A));
+  A->nx = (int32_t)p.nx;
+  A->ny = (int32_t)p.ny;
+  A->nz = (int32_t)p.nz;
+  A->plane = nodes_of(p);
+  const int32_t bc[6] = {p.bc[0], p.bc[1], p.bc[2], p.bc[3], p.bc_z[0],
+                         p.bc_z[1]};
+  const double wT[6] = {p.wall_T[0], p.wall_T[1], p.wall_T[2],
+                        p.wall_T[3], p.wall_T_z[0], p.wall_T_z[1]};
+  for (int k = 0; k < 6; ++k) {
+    A->bc[k] = bc[k];
+    A->wall_T[k] = wT[k];
+    if (bc[k] == BC_NEUMANN) A->neu |= 1 << k;
+  }
+  for (int a = 0; a < 3; ++a) A->periodic[a] = bc[2 * a] == BC_PERIODIC;
+  A->a = 1.0 - 1.0 / p.tau;
+  A->inv_tau = 1.0 / p.tau;
+  const int rep[3] = {0, 1, 7};  // one direction of each weight class
+  for (int c = 0; c < 3; ++c) {
+    const double w = p.q == 7 ? wt3<7>(rep[c]) : wt3<19>(rep[c]);
+    A->wtau[c] = w / p.tau;
+    A->wste[c] = w / p.ste;
+  }
+  A->inv_ste = 1.0 / p.ste;
+  A->tm = p.t_m;
+  A->inv_delta = 1.0 / p.delta;
+  A->tol = p.newton_tol;
+  A->max_it = p.newton_max_it;
+}
+
 void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
   double *prof[4];
   for (int k = 0; k < 4; ++k) prof[k] = h->has_prof[k] ? h->prof[k] : nullptr;
@@ -168,6 +231,7 @@ void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
 }
 
 bool irebm::two_step_variant(const lbm_stefan_t *h) {
+  if (h->p.dim == 3) return false;
   int nv;
   return variants(h->p.q, &nv)[h->variant].tb != 0 && !has_neumann(h->p);
 }
@@ -186,6 +250,24 @@ hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
 
 hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
   if (h->p.scheme == LBM_SCHEME_ILFBM) return ilfbm_advance(h, nsteps);
+  if (h->p.dim == 3) {
+    StepArgs3 A;
+    fill_args3(h->p, &A);
+    A.slots = h->slots;
+    int nv;
+    const Variant3 &v = variants3(&nv)[h->variant];
+    const int mode = mode_of(h->p);
+    for (int64_t s = 0; s < nsteps; ++s) {
+      A.src = h->buf[h->cur];
+      A.dst = h->buf[h->cur ^ 1];
+      const hipError_t e =
+          step3_launch(mode, h->p.q, h->p.storage, A, v, h->stream);
+      if (e != hipSuccess) return e;
+      h->cur ^= 1;
+      h->steps++;
+    }
+    return hipSuccess;
+  }
   if (two_step_variant(h)) {
     for (; nsteps >= 2; nsteps -= 2) {
       const hipError_t e =
@@ -219,6 +301,25 @@ hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
 }
 
 namespace {
+
+// equilibrium initial state of a 3D lattice (A.dst)
+hipError_t init3_async(int q, int storage, const StepArgs3 &A, bool eebm,
+                       const double *T0, hipStream_t stream) {
+  const unsigned blocks = blocks_for(A.plane, 256);
+  const int e = eebm ? 1 : 0;
+  if (q == 7) {
+    if (storage == LBM_STORE_F32)
+      init3_kernel<7, float><<<blocks, 256, 0, stream>>>(A, e, T0);
+    else
+      init3_kernel<7, double><<<blocks, 256, 0, stream>>>(A, e, T0);
+  } else {
+    if (storage == LBM_STORE_F32)
+      init3_kernel<19, float><<<blocks, 256, 0, stream>>>(A, e, T0);
+    else
+      init3_kernel<19, double><<<blocks, 256, 0, stream>>>(A, e, T0);
+  }
+  return hipGetLastError();
+}
 
 // energy of the state `src` into h->small[kSmallEnergy] (device)
 hipError_t handle_energy_async(const lbm_stefan_t *h, const void *src) {
@@ -300,9 +401,11 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   h->p = *p;
   if (h->p.dx == 0.0) h->p.dx = 1.0 / (double)(p->nx - 1);
   if (p->dim == 1) h->p.bc[2] = h->p.bc[3] = LBM_BC_PERIODIC;
-  int nv;
-  variants(p->q, &nv);
-  h->variant = p->variant >= 0 ? p->variant : (p->q == 3 ? kDefaultVariant1D : kDefaultVariant2D);
+  h->variant = p->variant >= 0
+                   ? p->variant
+                   : (p->dim == 3 ? kDefaultVariant3D
+                                  : (p->q == 3 ? kDefaultVariant1D
+                                               : kDefaultVariant2D));
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
@@ -319,7 +422,7 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   h->partials = (double *)(ws + L.off_partials);
   h->small = (double *)(ws + L.off_small);
   h->adj = ws + L.off_adj;
-  const int64_t n = p->nx * p->ny;
+  const int64_t n = nodes_of(*p);
   for (int k = 0; k < 4; ++k) {
     h->prof[k] = (double *)(ws + L.off_prof[k]);
     h->has_prof[k] = p->wall_profile[k] != nullptr && !(p->dim == 1 && k >= 2);
@@ -342,13 +445,22 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   // T0 is staged through the second population buffer (>= 12 n bytes)
   if (T0 && hipMemcpy(h->buf[1], T0, n * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(h, LBM_STEFAN_EDEVICE, "copy of T0 failed"));
-  StepArgs A;
-  fill_step_args(h, &A);
-  A.dst = h->buf[0];
   const double *T0d = T0 ? (const double *)h->buf[1] : nullptr;
-  if (p->scheme == LBM_SCHEME_ILFBM) ilfbm_attach(h, ws + L.off_lf);
-  if (init_async(p->q, p->storage, A, T0d, h->stream, h->lf) != hipSuccess ||
-      zero_stats_async(h) != hipSuccess ||
+  hipError_t ie;
+  if (p->dim == 3) {
+    StepArgs3 A3;
+    fill_args3(h->p, &A3);
+    A3.dst = h->buf[0];
+    ie = init3_async(p->q, p->storage, A3, p->scheme == LBM_SCHEME_EEBM, T0d,
+                     h->stream);
+  } else {
+    StepArgs A;
+    fill_step_args(h, &A);
+    A.dst = h->buf[0];
+    if (p->scheme == LBM_SCHEME_ILFBM) ilfbm_attach(h, ws + L.off_lf);
+    ie = init_async(p->q, p->storage, A, T0d, h->stream, h->lf);
+  }
+  if (ie != hipSuccess || zero_stats_async(h) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
     return bail(fail(h, LBM_STEFAN_EDEVICE, "init kernels failed"));
   *out = h;
@@ -389,7 +501,7 @@ int lbm_stefan_query_front(lbm_stefan_t *h, int32_t mode, double *front,
   double *fr = h->small + kSmallFront;
   if (front) {
     HIPCHK(h, front_async(p, h->buf[h->cur], mode, fr, h->stream, h->lf));
-    HIPCHK(h, hipMemcpyAsync(front, fr, p.ny * 8, hipMemcpyDeviceToHost,
+    HIPCHK(h, hipMemcpyAsync(front, fr, rows_of(p) * 8, hipMemcpyDeviceToHost,
                              h->stream));
   }
   double e = 0.0;
@@ -411,7 +523,7 @@ int lbm_stefan_get_field(lbm_stefan_t *h, int32_t what, void *host) {
   if (!host) return fail(h, LBM_STEFAN_EINVAL, "host is NULL");
   DeviceGuard g(h->device);
   const lbm_stefan_params &p = h->p;
-  const int64_t n = p.nx * p.ny;
+  const int64_t n = nodes_of(p);
   if (what == LBM_FIELD_STATE) {
     const size_t s = p.storage == LBM_STORE_F64 ? 8 : 4;
     HIPCHK(h, hipMemcpyAsync(host, h->buf[h->cur], p.q * n * s,
@@ -438,7 +550,7 @@ int lbm_stefan_set_state(lbm_stefan_t *h, const void *state, int32_t on_device) 
   DeviceGuard g(h->device);
   const lbm_stefan_params &p = h->p;
   const size_t s = p.storage == LBM_STORE_F64 ? 8 : 4;
-  const size_t bytes = (size_t)p.q * p.nx * p.ny * s;
+  const size_t bytes = (size_t)p.q * nodes_of(p) * s;
   HIPCHK(h, hipMemcpyAsync(h->buf[h->cur], state, bytes,
                            on_device ? hipMemcpyDeviceToDevice
                                      : hipMemcpyHostToDevice,
@@ -454,11 +566,12 @@ int lbm_stefan_state_ptr(lbm_stefan_t *h, void **dev_state) {
 }
 
 int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count) {
-  if (!count || (q != 3 && q != 5 && q != 9) ||
+  if (!count || (q != 3 && q != 5 && q != 9 && q != 7 && q != 19) ||
       (storage != LBM_STORE_F64 && storage != LBM_STORE_F32))
     return fail(nullptr, LBM_STEFAN_EINVAL, "bad lattice, storage or count");
   int n;
-  variants(q, &n);
+  if (q == 7 || q == 19) variants3(&n);
+  else variants(q, &n);
   *count = n;
   return LBM_STEFAN_OK;
 }
@@ -467,9 +580,16 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
                                     int32_t variant) {
   static thread_local char buf[64];
   int n;
-  if ((q != 3 && q != 5 && q != 9) ||
-      (storage != LBM_STORE_F64 && storage != LBM_STORE_F32))
-    return "";
+  if (storage != LBM_STORE_F64 && storage != LBM_STORE_F32) return "";
+  if (q == 7 || q == 19) {
+    const Variant3 *v3 = variants3(&n);
+    if (variant < 0 || variant >= n) return "";
+    const Variant3 &w = v3[variant];
+    std::snprintf(buf, sizeof(buf), "%dx%d/npt%d/z%d%s", w.bx * w.npt, w.by,
+                  w.npt, w.cz, w.nt ? "/nt" : "");
+    return buf;
+  }
+  if (q != 3 && q != 5 && q != 9) return "";
   const Variant *v = variants(q, &n);
   if (variant < 0 || variant >= n) return "";
   const Variant &w = v[variant];
@@ -487,7 +607,8 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
 int lbm_stefan_set_variant(lbm_stefan_t *h, int32_t variant) {
   if (!h) return fail(nullptr, LBM_STEFAN_EINVAL, "handle is NULL");
   int n;
-  variants(h->p.q, &n);
+  if (h->p.dim == 3) variants3(&n);
+  else variants(h->p.q, &n);
   if (variant < 0 || variant >= n)
     return fail(h, LBM_STEFAN_EINVAL, "unknown kernel variant");
   DeviceGuard g(h->device);
@@ -503,7 +624,7 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
   if (!h) return fail(nullptr, LBM_STEFAN_EINVAL, "handle is NULL");
   const lbm_stefan_params &p = h->p;
   const size_t sb = p.storage == LBM_STORE_F64 ? 8 : 4;
-  const size_t bytes = (size_t)p.q * p.nx * p.ny * sb;
+  const size_t bytes = (size_t)p.q * nodes_of(p) * sb;
   if (!scratch || scratch_bytes < bytes)
     return fail(h, LBM_STEFAN_EINVAL, "scratch smaller than the state");
   if (steps < 1 || steps > 10000)
@@ -516,7 +637,9 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
   }
   DeviceGuard g(h->device);
   int nv;
-  const Variant *vt = variants(p.q, &nv);
+  const Variant *vt = nullptr;
+  if (p.dim == 3) variants3(&nv);
+  else vt = variants(p.q, &nv);
   const int cur0 = h->cur;
   HIPCHK(h, hipMemcpyAsync(scratch, h->buf[cur0], bytes,
                            hipMemcpyDeviceToDevice, h->stream));
@@ -531,7 +654,7 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
   hipError_t err = hipSuccess;
   for (int v = 0; v < nv && err == hipSuccess; ++v) {
     // a Neumann lattice runs two-step variants as the default one
-    if (vt[v].tb && has_neumann(p)) continue;
+    if (vt && vt[v].tb && has_neumann(p)) continue;
     h->variant = v;
     // two untimed steps, then the timed trial (an even count, so that a
     // two-step variant runs its own kernel only)

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "irebm_node.hpp"
+#include "lattice3d.hpp"
 #include "lbm_stefan.h"
 
 namespace irebm {
@@ -74,6 +75,9 @@ void fill_args(const lbm_stefan_params &p, double *const prof[4],
                StepArgs *A);
 void fill_step_args(const lbm_stefan_t *h, StepArgs *A);
 hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst);
+// StepArgs3 of a 3D lattice from its params; src, dst and the tile fields
+// are left zero
+void fill_args3(const lbm_stefan_params &p, StepArgs3 *A);
 // two steps (or one, two = false) in one launch of the two-step kernel
 // (the handle's variant is a two-step variant)
 hipError_t launch_step2(const lbm_stefan_t *h, const void *src, void *dst,
@@ -135,15 +139,36 @@ IREBM_DECLARE_MODE(kEebm);
 IREBM_DECLARE_STEP1(kSafeguarded | kNeumann);
 IREBM_DECLARE_STEP1(kPlain | kNeumann);
 IREBM_DECLARE_STEP1(kEebm | kNeumann);
+#define IREBM_DECLARE_STEP3(M)                                             \
+  extern template hipError_t step3_launch_mode<M>(                         \
+      int, int, const StepArgs3 &, const Variant3 &, hipStream_t)
+IREBM_DECLARE_STEP3(kSafeguarded);
+IREBM_DECLARE_STEP3(kPlain);
+IREBM_DECLARE_STEP3(kEebm);
+IREBM_DECLARE_STEP3(kSafeguarded | kNeumann);
+IREBM_DECLARE_STEP3(kPlain | kNeumann);
+IREBM_DECLARE_STEP3(kEebm | kNeumann);
+#undef IREBM_DECLARE_STEP3
 #undef IREBM_DECLARE_MODE
 #undef IREBM_DECLARE_STEP1
 
 // does a lattice have a Neumann wall (eq. Neu_on_q)?  Its closure reads
 // two cells away, so such lattices take one step per launch
 inline bool has_neumann(const lbm_stefan_params &p) {
-  for (int k = 0; k < (p.dim == 2 ? 4 : 2); ++k)
+  for (int k = 0; k < (p.dim >= 2 ? 4 : 2); ++k)
     if (p.bc[k] == LBM_BC_NEUMANN) return true;
+  if (p.dim == 3)
+    for (int k = 0; k < 2; ++k)
+      if (p.bc_z[k] == LBM_BC_NEUMANN) return true;
   return false;
+}
+
+// nodes of a lattice, and its rows along x (one front value each)
+inline int64_t nodes_of(const lbm_stefan_params &p) {
+  return p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
+}
+inline int64_t rows_of(const lbm_stefan_params &p) {
+  return p.ny * (p.dim == 3 ? p.nz : 1);
 }
 
 // node-update mode of a lattice (with kNeumann when it has a Neumann wall)
@@ -187,6 +212,25 @@ inline hipError_t step2_launch(int mode, int q, int storage,
   if (mode == kPlain)
     return step2_launch_mode<kPlain>(q, storage, A, v, two, stream);
   return step2_launch_mode<kSafeguarded>(q, storage, A, v, two, stream);
+}
+
+// one step of one 3D lattice (3D variant v)
+inline hipError_t step3_launch(int mode, int q, int storage,
+                               const StepArgs3 &A, const Variant3 &v,
+                               hipStream_t stream) {
+  switch (mode) {
+    case kEebm: return step3_launch_mode<kEebm>(q, storage, A, v, stream);
+    case kPlain: return step3_launch_mode<kPlain>(q, storage, A, v, stream);
+    case kEebm | kNeumann:
+      return step3_launch_mode<kEebm | kNeumann>(q, storage, A, v, stream);
+    case kPlain | kNeumann:
+      return step3_launch_mode<kPlain | kNeumann>(q, storage, A, v, stream);
+    case kSafeguarded | kNeumann:
+      return step3_launch_mode<kSafeguarded | kNeumann>(q, storage, A, v,
+                                                        stream);
+    default:
+      return step3_launch_mode<kSafeguarded>(q, storage, A, v, stream);
+  }
 }
 
 inline hipError_t batch_launch(int mode, int q, int storage,

@@ -49,7 +49,20 @@ def make_params(prob, variant=-1, flags=0, strict=False):
     p.flags = flags
     sc = getattr(prob, "scheme", "irebm")
     p.scheme = _SCHEME[sc] if isinstance(sc, str) else int(sc)
+    if prob.dim == 3:
+        p.nz = prob.nz
+        for k in range(2):
+            b = prob.bc_z[k]
+            p.bc_z[k] = _BC[b] if isinstance(b, str) else int(b)
+            p.wall_T_z[k] = prob.wall_T_z[k]
     return p, keep
+
+
+def _field_shape(prob):
+    """(ny, nx), or (nz, ny, nx) on a 3D lattice"""
+    if prob.dim == 3:
+        return (prob.nz, prob.ny, prob.nx)
+    return (prob.ny, prob.nx)
 
 
 def workspace_bytes(prob, variant=-1, flags=0):
@@ -94,7 +107,8 @@ class Stefan:
             T0p = None
             if prob.T0 is not None:
                 T0 = np.ascontiguousarray(
-                    np.broadcast_to(prob.T0, (prob.ny, prob.nx)), dtype=np.float64)
+                    np.broadcast_to(prob.T0, _field_shape(prob)),
+                    dtype=np.float64)
                 T0p = T0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             h = ctypes.c_void_p()
             C.check(self._lib.lbm_stefan_init(
@@ -123,7 +137,8 @@ class Stefan:
 
     # -- queries -------------------------------------------------------
     def front(self, mode="integral"):
-        out = np.empty(self.prob.ny)
+        """Front of every row along x: shape (ny,), (nz, ny) in 3D."""
+        out = np.empty(_field_shape(self.prob)[:-1])
         C.check(self._lib.lbm_stefan_query_front(
             self.h, _FRONT[mode], out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
             None), self.h)
@@ -136,20 +151,20 @@ class Stefan:
         return e.value
 
     def temperature(self):
-        T = np.empty((self.prob.ny, self.prob.nx))
+        T = np.empty(_field_shape(self.prob))
         C.check(self._lib.lbm_stefan_get_field(
             self.h, C.FIELD_T, ctypes.c_void_p(T.ctypes.data)), self.h)
         return T
 
     def liquid(self):
         """Liquid fraction of every node (the scheme's own definition)."""
-        L = np.empty((self.prob.ny, self.prob.nx))
+        L = np.empty(_field_shape(self.prob))
         C.check(self._lib.lbm_stefan_get_field(
             self.h, C.FIELD_LIQUID, ctypes.c_void_p(L.ctypes.data)), self.h)
         return L
 
     def state(self):
-        s = np.empty((self.prob.q, self.prob.ny, self.prob.nx),
+        s = np.empty((self.prob.q,) + _field_shape(self.prob),
                      dtype=self.state_dtype)
         C.check(self._lib.lbm_stefan_get_field(
             self.h, C.FIELD_STATE, ctypes.c_void_p(s.ctypes.data)), self.h)
@@ -162,7 +177,7 @@ class Stefan:
 
     def set_state(self, state):
         """state: host numpy array or device tensor of shape (q, ny, nx)
-        and the storage dtype."""
+        ((q, nz, ny, nx) in 3D) and the storage dtype."""
         if isinstance(state, torch.Tensor):
             t = state.contiguous()
             C.check(self._lib.lbm_stefan_set_state(

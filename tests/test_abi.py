@@ -231,3 +231,63 @@ def test_ilfbm_rules_and_workspace(L):
     n = ctypes.c_size_t()
     arr = (L.Params * 2)(a, a)
     assert L.lib().lbm_stefan_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == L.EINVAL
+
+
+def test_3d_rules_and_workspace(L):
+    """D3Q7 / D3Q19: accepted with z faces of their own; workspace holds two
+    state buffers of q * nx * ny * nz values; the 3D restrictions return
+    EINVAL."""
+    for q in (7, 19):
+        prob = synth.cavity_3d(n=40, ny=24, nz=17, q=q)
+        p, _ = _params(L, prob)
+        rc, n = _ws(L, p)
+        assert rc == 0
+        assert n >= 2 * q * 40 * 24 * 17 * 4
+        for field, value in (("nz", 2), ("q", 9), ("scheme", L.SCHEME_ILFBM),
+                             ("flags", L.FLAG_ADJOINT), ("variant", 10)):
+            p, _ = _params(L, prob)
+            setattr(p, field, value)
+            assert _ws(L, p)[0] == L.EINVAL, (q, field)
+        p, _ = _params(L, prob)
+        p.bc_z[1] = L.BC_PERIODIC          # one periodic z face
+        assert _ws(L, p)[0] == L.EINVAL
+        p, _ = _params(L, prob)
+        p.bc_z[0] = L.BC_NEUMANN           # beside bounce-back y walls
+        assert _ws(L, p)[0] == L.EINVAL
+        p, _ = _params(L, synth.freezing_cube_3d(n=9, q=q))
+        assert _ws(L, p)[0] == 0
+        p.bc_z[1] = 7
+        assert _ws(L, p)[0] == L.EINVAL
+    # wall profiles are 2D only
+    import numpy as np
+    prob = synth.cavity_3d(n=16, q=7).with_(
+        wall_profile=(np.ones(16), None, None, None))
+    p, keep = _params(L, prob)
+    assert _ws(L, p)[0] == L.EINVAL
+    # 2^31 nodes or more
+    p, _ = _params(L, synth.cavity_3d(n=16, q=7))
+    p.nx, p.ny, p.nz = 2048, 1024, 1024
+    assert _ws(L, p)[0] == L.EINVAL
+    # the batched form refuses 3D instances
+    a, _ = _params(L, synth.cavity_3d(n=16, q=7))
+    arr = (L.Params * 2)(a, a)
+    n = ctypes.c_size_t()
+    assert L.lib().lbm_stefan_batch_workspace_bytes(
+        arr, 2, ctypes.byref(n)) == L.EINVAL
+    assert "1D and 2D" in L.lib().lbm_stefan_batch_last_error(None).decode()
+
+
+def test_3d_variants_listed(L):
+    """Every 3D variant fits the kernel's launch bound (256 threads) with
+    whole waves along x: block = (tile_x / npt) x tile_y threads."""
+    import re
+    from paper_2505_13097_amd import variant_names
+    for q in (7, 19):
+        names = variant_names(q, "f32")
+        assert len(names) >= 8
+        for n in names:
+            m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?", n)
+            assert m, n
+            tx, ty, npt, cz = (int(m.group(k)) for k in range(1, 5))
+            bx = tx // npt
+            assert bx % 64 == 0 and bx * ty <= 256 and cz >= 1, n
