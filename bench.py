@@ -76,6 +76,36 @@ def measured_traffic(workload, variant_name):
     return None if v is None else v.get("bytes_per_launch")
 
 
+KERNEL3_SOURCES = ("irebm_node.hpp", "kernels.hpp", "lattice3d.hpp",
+                   "launch3.hpp", "k_step3_safeguarded.hip")
+TRAFFIC3_JSON = os.path.join(ROOT, "profiles", "step3_kernel_traffic.json")
+
+
+def kernel3_source_hash():
+    """sha256 of the sources that define the 3D step kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2505_13097_amd", "csrc")
+    for name in KERNEL3_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic3(workload, variant_name):
+    """HBM bytes per launch of the 3D step kernel, from the committed
+    counter summary when it matches the current sources, else None."""
+    try:
+        with open(TRAFFIC3_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel3_source_hash():
+        return None
+    v = rec.get("lattices", {}).get(workload, {}).get(variant_name)
+    return None if v is None else v.get("bytes_per_launch")
+
+
 def bytes_per_node(prob):
     s = 8 if prob.storage == "f64" else 4
     return 2 * prob.q * s
@@ -178,6 +208,193 @@ def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1):
         "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
         "time_ratio_irebm_to_eebm": round(irebm_ms_per_step / ms, 3),
     }
+
+
+CUBE3D_N = 512
+
+
+def time_cube3d(steps=50, warmup=5, autotune=True, variant=-1, n=CUBE3D_N):
+    """The 3D lattices (the enthalpy model holds in 3D, Section 2): the
+    n^3 cube heated at one face (Dirichlet x faces, bounce-back y and z
+    faces), D3Q19 and D3Q7, FP32 populations, IREBM and then EEBM on the
+    same kernel variant; algorithmic bytes 2 q s per lattice update."""
+    import synth as S
+    from paper_2505_13097_amd import variant_names
+    rows = []
+    for q in (19, 7):
+        p = S.cavity_3d(n=n, q=q)
+        print(f"[bench] cube3d D3Q{q} {n}^3", file=sys.stderr, flush=True)
+        r = time_plain(p, steps, warmup, variant, autotune=autotune)
+        v = r["variant"] if r["variant"] >= 0 else 0
+        vname = variant_names(q, p.storage)[v]
+        launch_ms = r["gpu_ms"] / steps
+        alg = p.nodes * bytes_per_node(p)
+        gbps = alg / (launch_ms * 1e-3) / 1e9
+        pe = p.with_(scheme="eebm", name=p.name.replace("irebm", "eebm"))
+        e = time_plain(pe, steps, warmup, v, autotune=False)
+        e_ms = e["gpu_ms"] / steps
+        rows.append({
+            "workload": p.name, "lattice": f"D3Q{q}", "nodes": p.nodes,
+            "steps": steps, "kernel_variant": vname,
+            "autotuned": r["tuned"] is not None,
+            "value": round(p.nodes * steps / r["wall_s"] / 1e6, 1),
+            "unit": "MLUPS",
+            "avg_launch_us": round(launch_ms * 1e3, 2),
+            "bytes_per_lattice_update": bytes_per_node(p),
+            "hbm_gbps_algorithmic": round(gbps, 1),
+            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
+            "traffic": measured_traffic3(p.name, vname),
+            "newton_max_it": r["stats"]["max_newton_it"],
+            "nonconverged": r["stats"]["nonconverged"],
+            "eebm_avg_launch_us": round(e_ms * 1e3, 2),
+            "eebm_hbm_gbps_algorithmic": round(alg / (e_ms * 1e-3) / 1e9, 1),
+            "time_ratio_irebm_to_eebm": round(launch_ms / e_ms, 3),
+        })
+    return {"unit": "MLUPS per lattice", "runs": rows}
+
+
+def traffic_sweep3(n=CUBE3D_N):
+    """Counter runs of the 3D step kernel: every 3D variant for SWEEP_STEPS
+    steps on the D3Q19, then the D3Q7 cube (IREBM), in table order."""
+    import torch
+    import synth as S
+    from paper_2505_13097_amd import Stefan, variant_names
+    for q in (19, 7):
+        g = Stefan(S.cavity_3d(n=n, q=q))
+        for v in range(len(variant_names(q, "f32"))):
+            g.set_variant(v)
+            g.step(SWEEP_STEPS)
+        torch.cuda.synchronize()
+        g.close()
+        torch.cuda.empty_cache()
+
+
+def summarize_profiles3(run, args):
+    """profiles/ summaries of the 3D step kernel from run/prof3d (kernel
+    trace of bench.py --cube3d-only with a fixed variant) and
+    run/pmc3d_fetch, run/pmc3d_write (bench.py --traffic-sweep-3d)."""
+    import collections
+    import re
+    import sqlite3
+    import synth as S
+    from paper_2505_13097_amd import variant_names
+
+    def short(nm):
+        nm = nm.replace("(anonymous namespace)::", "").replace("irebm::", "")
+        return nm.split("(")[0].replace("void ", "")
+
+    def db(sub):
+        d = os.path.join(run, sub)
+        f = [x for x in os.listdir(d) if x.endswith("_results.db")]
+        return sqlite3.connect(os.path.join(d, f[0]))
+
+    def kq(k):
+        m = re.match(r"step3_kernel<(\d+), float, \d, (\d+),", k)
+        return (int(m.group(1)), int(m.group(2))) if m else None
+
+    c = db("prof3d")
+    trace = [(short(r[0]), r[1], r[2], r[3], r[4]) for r in c.execute(
+        "select name, total_calls, total_duration, average, percentage "
+        "from top_kernels")]
+    by = collections.defaultdict(list)
+    for name, d in c.execute("select name, duration from kernels "
+                             "order by dispatch_id"):
+        by[short(name)].append(d / 1000.0)
+    steps = args.steps3d
+    avg = {}
+    for k, ds in by.items():
+        t = kq(k)
+        if t is not None:
+            avg.setdefault(t, []).append(sum(ds[-steps:]) / steps)
+
+    def counters(sub, cn):
+        rows = db(sub).execute(
+            "select kernel_name, value from counters_collection where "
+            "counter_name=? order by dispatch_id", (cn,)).fetchall()
+        return [(short(k), v) for k, v in rows]
+    F = counters("pmc3d_fetch", "FETCH_SIZE")
+    W = counters("pmc3d_write", "WRITE_SIZE")
+    gib_kib = 1024.0 * 1024.0
+    copy_f = max(v for k, v in F if "copyBuffer" in k)
+    copy_w = max(v for k, v in W if "copyBuffer" in k)
+    fs, ws = gib_kib / copy_f, gib_kib / copy_w
+    lattices = {}
+    src = kernel3_source_hash()
+    for q in (19, 7):
+        p = S.cavity_3d(n=args.cube3d_n, q=q)
+        names = variant_names(q, "f32")
+        sf = [v for k, v in F if kq(k) == (q, 0)]
+        sw = [v for k, v in W if kq(k) == (q, 0)]
+        if len(sf) != SWEEP_STEPS * len(names) or len(sw) != len(sf):
+            raise SystemExit(f"D3Q{q}: expected {SWEEP_STEPS * len(names)} "
+                             f"dispatches, found {len(sf)} / {len(sw)}")
+        alg = p.nodes * bytes_per_node(p)
+        rec = {}
+        for i, nm in enumerate(names):
+            fk = sum(sf[i * SWEEP_STEPS:(i + 1) * SWEEP_STEPS]) / SWEEP_STEPS
+            wk = sum(sw[i * SWEEP_STEPS:(i + 1) * SWEEP_STEPS]) / SWEEP_STEPS
+            b = fk * 1024 * fs + wk * 1024 * ws
+            rec[nm] = {"fetch_kib_per_dispatch": round(fk, 1),
+                       "write_kib_per_dispatch": round(wk, 1),
+                       "bytes_per_launch": round(b),
+                       "bytes_per_lattice_update": round(b / p.nodes, 3),
+                       "ratio_to_algorithmic": round(b / alg, 4)}
+        lattices[p.name] = rec
+    vname = {q: variant_names(q, "f32")[args.variant3d] for q in (19, 7)}
+    trace_cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof3d -o p3"
+                 f" -- python bench.py --cube3d-only --no-autotune"
+                 f" --variant3d {args.variant3d} --steps3d {steps}")
+    pmc_cmd = ("rocprofv3 --pmc {C} -d gpurun_out/{D} -o {O} -- python "
+               "bench.py --traffic-sweep-3d")
+    lines = [f"# step3_kernel — {args.cube3d_n}^3 cube heated at one face, "
+             "D3Q19 and D3Q7, FP32 populations", "",
+             "Kernel trace (rocprofv3 on MI355X; run from /tmp with "
+             "TMPDIR=/tmp, paths absolute; summary written by bench.py "
+             "--summarize-profiles3):", "", "    " + trace_cmd, "",
+             "| kernel | calls | total us | average us | % |",
+             "|---|---|---|---|---|"]
+    for r in trace[:12]:
+        lines.append(f"| {r[0]} | {r[1]} | {r[2]:.0f} | {r[3]:.1f} | "
+                     f"{r[4]:.2f} |")
+    lines += ["", "Timed launches (the last " + str(steps) + " of each "
+              "kernel; mode 0 IREBM, 2 EEBM):", "",
+              "| lattice | mode | variant | average us | algorithmic GB/s |",
+              "|---|---|---|---|---|"]
+    for (q, mode), vals in sorted(avg.items(), reverse=True):
+        p = S.cavity_3d(n=args.cube3d_n, q=q)
+        a = vals[-1]
+        lines.append(f"| D3Q{q} | {mode} | {vname[q]} | {a:.1f} | "
+                     f"{p.nodes * bytes_per_node(p) / (a * 1e-6) / 1e9:.0f} |")
+    lines += ["", "HBM traffic per launch of every variant (IREBM, two "
+              "counter runs, one counter each):", "",
+              "    " + pmc_cmd.format(C="FETCH_SIZE", D="pmc3d_fetch",
+                                      O="fetch"),
+              "    " + pmc_cmd.format(C="WRITE_SIZE", D="pmc3d_write",
+                                      O="write"), "",
+              f"Counter scale from a 1 GiB device copy in the same runs: "
+              f"FETCH_SIZE x{fs:.4f}, WRITE_SIZE x{ws:.4f}.", ""]
+    for wl, rec in lattices.items():
+        lines += [f"{wl}:", "",
+                  "| variant | FETCH KiB | WRITE KiB | bytes/launch | "
+                  "B per lattice update | / algorithmic |",
+                  "|---|---|---|---|---|---|"]
+        for nm, r in rec.items():
+            lines.append(f"| {nm} | {r['fetch_kib_per_dispatch']:.0f} | "
+                         f"{r['write_kib_per_dispatch']:.0f} | "
+                         f"{r['bytes_per_launch'] / 1e9:.3f} GB | "
+                         f"{r['bytes_per_lattice_update']:.2f} | "
+                         f"{r['ratio_to_algorithmic']:.4f} |")
+        lines.append("")
+    lines += [f"Kernel sources sha256 {src}.", ""]
+    fn = f"step3_kernel_cube{args.cube3d_n}_d3q19_d3q7_f32.md"
+    with open(os.path.join(ROOT, "profiles", fn), "w") as f:
+        f.write("\n".join(lines))
+    with open(TRAFFIC3_JSON, "w") as f:
+        json.dump({"kernel": "step3_kernel", "sources_sha256": src,
+                   "fetch_scale": fs, "write_scale": ws,
+                   "lattices": lattices, "source": "profiles/" + fn}, f,
+                  indent=1)
+    print(f"wrote profiles/{fn}, {os.path.relpath(TRAFFIC3_JSON, ROOT)}")
 
 
 def _run_seconds(prob, nsteps):
@@ -566,9 +783,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--forms",
-                    default="plain,batched,adjoint,eebm,freezing,paper1d",
+                    default="plain,batched,adjoint,eebm,freezing,paper1d,"
+                            "cube3d",
                     help="comma list of extra forms to time: batched, "
-                         "adjoint, eebm, freezing, paper1d")
+                         "adjoint, eebm, freezing, paper1d, cube3d")
+    ap.add_argument("--cube3d-only", action="store_true",
+                    help="time the 3D form alone (profile runs)")
+    ap.add_argument("--cube3d-n", type=int, default=CUBE3D_N)
+    ap.add_argument("--steps3d", type=int, default=50)
+    ap.add_argument("--variant3d", type=int, default=-1)
+    ap.add_argument("--traffic-sweep-3d", action="store_true",
+                    help="counter runs of the 3D kernel: 1 GiB copy, every "
+                         f"3D variant for {SWEEP_STEPS} steps; no timing")
+    ap.add_argument("--summarize-profiles3", metavar="RUN_DIR",
+                    help="write the 3D profiles/ summary (CPU only; "
+                         "--variant3d and --steps3d as in the trace run)")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-variant", type=int, default=-1)
@@ -586,6 +815,9 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args)
         return
+    if args.summarize_profiles3:
+        summarize_profiles3(args.summarize_profiles3, args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; "
                           "--gpus must be 1"}))
@@ -595,6 +827,22 @@ def main():
     import synth  # noqa: F401
     from paper_2505_13097_amd import variant_names
     torch.cuda.set_device(0)
+
+    if args.cube3d_only:
+        r = time_cube3d(args.steps3d, 5, not args.no_autotune,
+                        args.variant3d, args.cube3d_n)
+        print(json.dumps({"cube3d": r}), flush=True)
+        return
+    if args.traffic_sweep_3d:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        del a, b
+        traffic_sweep3(args.cube3d_n)
+        print(json.dumps({"traffic_sweep_3d": args.cube3d_n,
+                          "steps_each": SWEEP_STEPS}), flush=True)
+        return
 
     prob = workload(args.workload)
     if args.traffic_sweep:
@@ -716,6 +964,12 @@ def main():
         print("[bench] paper1d form", file=sys.stderr, flush=True)
         forms["paper1d"] = time_paper1d()
         print("[bench] paper1d done", file=sys.stderr, flush=True)
+    if "cube3d" in args.forms.split(","):
+        print("[bench] cube3d form", file=sys.stderr, flush=True)
+        forms["cube3d"] = time_cube3d(
+            args.steps3d, 5, not args.no_autotune, args.variant3d,
+            args.cube3d_n)
+        print("[bench] cube3d done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:
