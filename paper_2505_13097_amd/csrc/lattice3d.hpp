@@ -511,7 +511,9 @@ inline const Variant3 *variants3(int *n) {
       {64, 4, 1, 8, 1},  {64, 4, 1, 8, 0},  {64, 4, 1, 32, 1},
       {64, 4, 1, 1, 1},  {128, 2, 1, 16, 1}, {256, 1, 1, 16, 1},
       {64, 2, 2, 16, 1}, {64, 4, 2, 8, 1},  {128, 1, 2, 16, 1},
-      {64, 2, 1, 8, 1}};
+      {64, 2, 1, 8, 1},  {128, 1, 2, 4, 1},  {128, 1, 2, 8, 1},
+      {128, 1, 2, 32, 1}, {128, 1, 2, 16, 0}, {64, 1, 2, 16, 1},
+      {64, 2, 2, 8, 1}};
   *n = (int)(sizeof(v) / sizeof(Variant3));
   return v;
 }

@@ -244,7 +244,7 @@ def test_3d_rules_and_workspace(L):
         assert rc == 0
         assert n >= 2 * q * 40 * 24 * 17 * 4
         for field, value in (("nz", 2), ("q", 9), ("scheme", L.SCHEME_ILFBM),
-                             ("flags", L.FLAG_ADJOINT), ("variant", 10)):
+                             ("flags", L.FLAG_ADJOINT), ("variant", 99)):
             p, _ = _params(L, prob)
             setattr(p, field, value)
             assert _ws(L, p)[0] == L.EINVAL, (q, field)

@@ -202,3 +202,77 @@ def test_z_uniform_3d_run_equals_2d_gpu_run():
     T3 = g3.temperature()
     g3.close()
     assert np.max(np.abs(T3 - T2[None])) < 1e-12 * (1 + 1 / p2.ste)
+
+
+def _mushy3(prob, cells=2.0):
+    """Stress input: a smooth field inside the melting band (|T - T_m| ~
+    delta, so nearly every node runs a multi-iteration Newton solve) plus
+    seeded noise, with the Dirichlet faces inside the band too (the
+    well-conditioned form of a melting field, see test_gpu_parity)."""
+    d = prob.delta
+    z, y, x = np.meshgrid(np.arange(prob.nz) / prob.nz,
+                          np.arange(prob.ny) / prob.ny,
+                          np.arange(prob.nx) / (prob.nx - 1), indexing="ij")
+    T0 = prob.tm + 0.3 * d + cells * d * np.sin(2 * np.pi * 3 * x) * \
+        np.cos(2 * np.pi * 2 * y) * np.cos(2 * np.pi * z)
+    T0 = T0 + synth.node_noise(9, prob.nodes, 0.2 * d).reshape(T0.shape)
+    return prob.with_(T0=T0, wall_T=(cells * d, -cells * d, 0.0, 0.0))
+
+
+def _window3(prob, o, w):
+    """The cube [o, o + w)^3 of prob as a lattice of its own: faces on the
+    real boundary keep its closure, artificial faces get bounce-back."""
+    n = (prob.nx, prob.ny, prob.nz)
+    walls = list(prob.bc) + list(prob.bc_z)
+    bc = []
+    for a in range(3):
+        bc.append(walls[2 * a] if o[a] == 0 else "bounceback")
+        bc.append(walls[2 * a + 1] if o[a] + w == n[a] else "bounceback")
+    assert "periodic" not in bc and "neumann" not in bc
+    T0 = prob.T0[o[2]:o[2] + w, o[1]:o[1] + w, o[0]:o[0] + w]
+    return prob.with_(nx=w, ny=w, nz=w, bc=tuple(bc[:4]),
+                      bc_z=tuple(bc[4:]), T0=T0, dx=prob.dx)
+
+
+@pytest.mark.parametrize("q,storage,tol", [(19, "f32", TOL32),
+                                           (19, "f64", TOL64),
+                                           (7, "f32", TOL32)])
+def test_full_size_cube_sampled_windows(q, storage, tol):
+    """The 512^3 cube of the bench in the variant its autotuner picks,
+    from a field in the melting band: after 6 steps, 14 windows of 18^3
+    nodes (corners, edges, faces, interior) rerun by the oracle; nodes at
+    least 6 cells from a window's artificial faces must match."""
+    from paper_2505_13097_amd import Stefan, variant_names
+    steps, w, n = 6, 18, 512
+    prob = _mushy3(synth.cavity_3d(n=n, q=q, storage=storage))
+    g = Stefan(prob)
+    v, _ = g.autotune(steps=3)
+    st = g.step(steps, stats=True)
+    T = g.temperature()
+    g.close()
+    assert st["nonconverged"] == 0
+    rng = np.random.Generator(np.random.PCG64(21))
+    e = n - w
+    origins = [(0, 0, 0), (e, e, e), (0, e, 0), (e, 0, e), (0, 0, e // 2),
+               (e // 2, 0, 0), (0, e // 2, e), (e // 2, e // 2, 0),
+               (0, e // 3, e // 2), (e, e // 2, e // 3)]
+    origins += [tuple(int(c) for c in rng.integers(0, e, 3)) for _ in range(4)]
+    worst = 0.0
+    for o in origins:
+        sub = _window3(prob, o, w)
+        f, ost = O.run(sub, O.init(sub, sub.T0), steps)
+        To = O.temperature(sub, f)
+        sl = []
+        for a, m in zip((0, 1, 2), (prob.nx, prob.ny, prob.nz)):
+            lo = 0 if o[a] == 0 else steps
+            hi = w if o[a] + w == m else w - steps
+            sl.append(slice(lo, hi))
+        gz, gy, gx = (slice(o[2] + sl[2].start, o[2] + sl[2].stop),
+                      slice(o[1] + sl[1].start, o[1] + sl[1].stop),
+                      slice(o[0] + sl[0].start, o[0] + sl[0].stop))
+        d = np.abs(T[gz, gy, gx] - To[sl[2], sl[1], sl[0]])
+        worst = max(worst, float(d.max()))
+        assert ost["max_it"] > 2          # the window ran real solves
+    print(f"cube512 D3Q{q} {storage} ({variant_names(q, storage)[v]}): "
+          f"{len(origins)} windows, max|dT| = {worst:.3e}", flush=True)
+    assert worst <= tol * max(1.0, np.abs(T).max())
