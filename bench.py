@@ -974,7 +974,8 @@ def main():
         out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, 1 if prob.nodes > 1e6 else 200)
+        # about 10-30 s of single-threaded oracle work
+        out["cpu_baseline"] = cpu_baseline(prob, 3 if prob.nodes > 1e6 else 200)
     print(json.dumps(out), flush=True)
 
 
