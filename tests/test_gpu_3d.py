@@ -276,3 +276,62 @@ def test_full_size_cube_sampled_windows(q, storage, tol):
     print(f"cube512 D3Q{q} {storage} ({variant_names(q, storage)[v]}): "
           f"{len(origins)} windows, max|dT| = {worst:.3e}", flush=True)
     assert worst <= tol * max(1.0, np.abs(T).max())
+
+
+@pytest.mark.parametrize("scheme", ["irebm", "eebm"])
+def test_liquid_field_crossing_front_and_state_roundtrip(scheme):
+    """The liquid-fraction field (phi(T) for IREBM, l(H) for EEBM), the
+    zero-crossing front of every x row and a state round trip on a 3D
+    lattice, FP64."""
+    from paper_2505_13097_amd import Stefan
+    prob, steps = _make(0, "f64", scheme)
+    g = Stefan(prob)
+    s0 = g.state()
+    T0 = g.temperature()
+    g.step(steps)
+    lg = g.liquid()
+    cg = g.front("crossing")
+    s1 = g.state()
+    g.set_state(s0)
+    assert np.array_equal(g.temperature(), T0)
+    g.set_state(s1)
+    assert np.array_equal(g.state(), s1)
+    g.close()
+    f, _ = O.run(prob, O.init(prob, prob.T0), steps)
+    T = O.temperature(prob, f)
+    if scheme == "irebm":
+        want = np.vectorize(lambda t: O.phi(t, prob.tm, prob.delta))(T)
+    else:
+        want = np.clip(prob.ste * (f.sum(axis=0) - prob.tm), 0.0, 1.0)
+    assert np.max(np.abs(lg - want)) < 1e-10
+    co = O.front(prob, f, O.FRONT_CROSSING)
+    assert co.shape == cg.shape == (prob.nz, prob.ny)
+    # rows whose first crossing does not move when the stored zeroth
+    # moment (T, or H for EEBM) is nudged by +-1e-9: there the crossing is
+    # a continuous function of the state at the observed error
+    m = f.sum(axis=0)
+    ok = np.ones(co.shape, dtype=bool)
+    for eps in (-1e-9, 1e-9):
+        Tp = (m + eps if scheme == "irebm" else
+              np.vectorize(lambda h: O.eebm_theta(h, prob.ste, prob.tm))(
+                  m + eps))
+        ok &= np.abs(_crossing(Tp - prob.tm, prob.dx) - co) <= 1e-6 * prob.dx
+    assert ok.mean() > 0.5
+    assert np.max(np.abs(cg - co)[ok]) <= 1e-9 * prob.nx * prob.dx
+    assert 0.0 < co[ok].mean() < prob.nx * prob.dx     # a front is present
+
+
+def _crossing(d, dx):
+    """first place along x where d goes from > 0 to <= 0, interpolated (0
+    if d(0) <= 0, the far wall if it stays positive), for every row"""
+    out = np.full(d.shape[:-1], (d.shape[-1] - 1) * dx)
+    for idx in np.ndindex(*d.shape[:-1]):
+        r = d[idx]
+        if r[0] <= 0.0:
+            out[idx] = 0.0
+            continue
+        k = np.nonzero((r[:-1] > 0.0) & (r[1:] <= 0.0))[0]
+        if k.size:
+            k = k[0]
+            out[idx] = dx * (k + r[k] / (r[k] - r[k + 1]))
+    return out
