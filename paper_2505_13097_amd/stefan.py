@@ -81,11 +81,17 @@ def variant_names(q, storage="f32"):
 
 
 class Stefan:
-    """One IREBM lattice on the current CUDA (HIP) device.
+    """One lattice on the current CUDA (HIP) device: D1Q3, D2Q5, D2Q9,
+    D3Q7 or D3Q19, stepped by IREBM (Algorithm 3), EEBM (Algorithm 2) or
+    ILFBM (Algorithm 1, 1D and 2D) as prob.scheme says.
 
     prob      synth.Problem-like description (lattice, sizes, tau, Ste,
-              delta, walls, Newton settings, storage, initial T0).
+              delta, walls, Newton settings, storage, scheme, initial T0;
+              nz and the z walls on a 3D lattice).
     variant   kernel variant (-1: library default).
+
+    Fields come back as (ny, nx) arrays, (nz, ny, nx) in 3D; fronts as
+    one value per x row.
     """
 
     def __init__(self, prob, variant=-1, flags=0, strict=False,
