@@ -486,6 +486,37 @@ def time_freezing(sizes=(201, 401, 801)):
             "unit": "s per run to 20 h", "runs": rows}
 
 
+def time_freezing3d(sizes=(101, 201)):
+    """The freezing case taken to 3D (the octant of a cube cooled on every
+    face, Dirichlet and symmetry faces, the 2D case's parameters), run to
+    t = 20 h, D3Q7 and D3Q19, EEBM and IREBM, FP64 populations: the 2D
+    timing table's IREBM/EEBM ratio in 3D."""
+    import torch
+    from paper_2505_13097_amd import Stefan
+    import synth as S
+    rows = []
+    for q in (7, 19):
+        for n in sizes:
+            r = {"lattice": f"D3Q{q}", "N": n}
+            for scheme in ("eebm", "irebm"):
+                p = S.freezing_cube_3d(n=n, q=q, scheme=scheme)
+                g = Stefan(p)
+                g.step(5)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.step(p.nsteps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                g.close()
+                r["steps"] = p.nsteps
+                r[f"{scheme}_s"] = round(dt, 4)
+                r[f"{scheme}_glups"] = round(p.nodes * p.nsteps / dt / 1e9, 2)
+            r["ratio_irebm_to_eebm"] = round(r["irebm_s"] / r["eebm_s"], 3)
+            rows.append(r)
+    return {"workload": "freeze3d_octant_f64_20h",
+            "unit": "s per run to 20 h", "runs": rows}
+
+
 def time_adjoint(prob, interval, autotune=True):
     """The reverse mode: forward run keeping a checkpoint tape, then the
     reverse sweep (segment recompute + reverse steps) giving dL/dT_wall
@@ -784,9 +815,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--forms",
                     default="plain,batched,adjoint,eebm,freezing,paper1d,"
-                            "cube3d",
+                            "cube3d,freezing3d",
                     help="comma list of extra forms to time: batched, "
-                         "adjoint, eebm, freezing, paper1d, cube3d")
+                         "adjoint, eebm, freezing, paper1d, cube3d, "
+                         "freezing3d")
     ap.add_argument("--cube3d-only", action="store_true",
                     help="time the 3D form alone (profile runs)")
     ap.add_argument("--cube3d-n", type=int, default=CUBE3D_N)
@@ -964,6 +996,10 @@ def main():
         print("[bench] paper1d form", file=sys.stderr, flush=True)
         forms["paper1d"] = time_paper1d()
         print("[bench] paper1d done", file=sys.stderr, flush=True)
+    if "freezing3d" in args.forms.split(","):
+        print("[bench] freezing3d form", file=sys.stderr, flush=True)
+        forms["freezing3d"] = time_freezing3d()
+        print("[bench] freezing3d done", file=sys.stderr, flush=True)
     if "cube3d" in args.forms.split(","):
         print("[bench] cube3d form", file=sys.stderr, flush=True)
         forms["cube3d"] = time_cube3d(
