@@ -10,6 +10,12 @@ Default workload: the 8192 x 8192 D2Q9 cavity (FP32 populations, FP64
 per-node arithmetic), heated at x = 0, adiabatic y walls, Ste drawn from
 the seed, delta = 1.5 cells, tau = 0.6, Newton tol 1e-12.
 
+Further forms in "forms" (--forms): the batched form (512 D2Q5 lattices,
+64^2 to 1024^2), the reverse mode (512^2 D2Q5, 4096 steps), the explicit
+scheme on the same cavity, the paper's 2D freezing case and 1D case with
+the three schemes, the 512^3 cube on D3Q19 and D3Q7, and the freezing
+case taken to 3D.
+
 Prints one JSON line.  Roofline: algorithmic bytes per launch
 (2 q sizeof(population) per lattice update: each population read once and
 written once, times the updates one launch performs) over the average
