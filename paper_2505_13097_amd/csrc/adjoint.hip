@@ -98,7 +98,7 @@ __device__ __forceinline__ void local_reverse(const AdjArgs &G, int x, int y,
                                              double &accS, double &accD) {
   const StepArgs &A = G.A;
   NodeLoad<Q, S> L;
-  load_node<Q, S, false>(A, (const S *)A.src, x, y, L);
+  load_node<Q, S, false>(A, to_global((const S *)A.src), x, y, L);
   double om[Q], q[Q], th = 0.0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -114,13 +114,13 @@ __device__ __forceinline__ void local_reverse(const AdjArgs &G, int x, int y,
 #pragma unroll
   for (int i = 0; i < Q; ++i) m0 += q[i];
   const double is = A.inv_ste, tm = A.tm, dl = G.delta;
-  const double P = phi_only(th, tm, A.inv_delta);
+  double P, d;
+  phi_dphi(th, tm, A.inv_delta, P, d);
   int it;
   bool conv;
-  const double tn = newton<PLAIN>(m0, th, P, A, it, conv);
-  double Pt, dt, Pd_, d;
+  const double tn = newton<PLAIN>(m0, th, P, d, A, it, conv);
+  double Pt, dt;
   phi_dphi(tn, tm, A.inv_delta, Pt, dt);
-  phi_dphi(th, tm, A.inv_delta, Pd_, d);
   const double dP = dphi_ddelta(th, tm, dl, d);
   const double dPt = dphi_ddelta(tn, tm, dl, dt);
   // reverse of Omega' = a f~ + (w/tau) sum f~

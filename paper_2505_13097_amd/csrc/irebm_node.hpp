@@ -64,6 +64,19 @@ __host__ __device__ constexpr int opp(int i) {
 
 enum { BC_DIRICHLET = 0, BC_BOUNCEBACK = 1, BC_PERIODIC = 2, BC_NEUMANN = 3 };
 
+// Pointers into global memory (address space 1).  The node loads and
+// stores take them, so that a pointer the kernel reads from memory (a
+// batch descriptor) still gives global loads and stores with a scalar base
+// and a 32-bit lane offset; through a generic pointer every access would
+// be a flat instruction with a 64-bit address computed per lane.  Every
+// state buffer the library hands its kernels lies in global memory.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T *p) {
+  return (gptr<T>)p;
+}
+
 // node update of a kernel instance: IREBM with the safeguarded or the
 // printed Newton update (Algorithm 3), or the explicit scheme (Algorithm 2);
 // kNeumann added to a mode compiles the Neumann closure (one-step kernels
@@ -152,7 +165,9 @@ __host__ __device__ __forceinline__ double eebm_lf(double H, double tm,
 
 // ---- local Newton solve of eq. rhs_fl_2:
 //   F(t) = t + phi(t)/Ste - c = 0,  c = m0 + phi(T)/Ste,
-// started from t = T (Algorithm 3).  PLAIN takes the printed update.
+// started from t = T (Algorithm 3); pth and dpth are phi(T) and phi'(T),
+// which the caller has (they are the first iterate's values).  PLAIN takes
+// the printed update.
 // The safeguarded form keeps the same step inside the rtsafe rule
 // (Press et al., Numerical Recipes, sec. 9.4): bracket [c - 1/Ste, c]
 // (F' >= 1 and 0 <= phi <= 1 make it valid), bisect when the step leaves
@@ -161,7 +176,8 @@ __host__ __device__ __forceinline__ double eebm_lf(double H, double tm,
 // AR: any argument block with inv_ste, tm, inv_delta, tol and max_it.
 template <bool PLAIN, class AR>
 __device__ __forceinline__ double newton(double m0, double th, double pth,
-                                const AR &A, int &iters, bool &conv) {
+                                         double dpth, const AR &A, int &iters,
+                                         bool &conv) {
   const double s = A.inv_ste;
   const double c = m0 + pth * s;
   double lo = c - s, hi = c;
@@ -183,11 +199,13 @@ __device__ __forceinline__ double newton(double m0, double th, double pth,
     }
   }
   double cur = th, cand = th;
+  // phi and phi' at the current iterate: evaluated once per iterate, at
+  // the end of the iteration that produced it, so the final step below
+  // reuses the converged iterate's values
+  double ph = pth, dph = dpth;
   int k = 0;
   conv = false;
   while (k < A.max_it) {
-    double ph, dph;
-    phi_dphi(cur, A.tm, A.inv_delta, ph, dph);
     if (PLAIN) {
       cand = (m0 + pth * s + dph * cur * s - ph * s) / (1.0 + dph * s);
     } else {
@@ -206,6 +224,7 @@ __device__ __forceinline__ double newton(double m0, double th, double pth,
       }
     }
     ++k;
+    phi_dphi(cand, A.tm, A.inv_delta, ph, dph);
     if (fabs(cand - cur) <= A.tol) {
       conv = true;
       break;
@@ -217,8 +236,6 @@ __device__ __forceinline__ double newton(double m0, double th, double pth,
   // on a bisection step is then the root to rounding, not any point within
   // tol of it, so the result does not depend on the safeguard's path
   if (conv) {
-    double ph, dph;
-    phi_dphi(cand, A.tm, A.inv_delta, ph, dph);
     const double F = cand + ph * s - c;
     cand -= (dph == 0.0) ? F : F / (1.0 + dph * s);
   }
@@ -267,8 +284,8 @@ __device__ __forceinline__ bool neumann_mirror(const StepArgs &A, int x, int y,
 // indices are clamped all the same so that no load leaves the planes.
 template <int Q, typename S>
 __device__ __forceinline__ double mirror_m0(const StepArgs &A,
-                                            const S *__restrict__ src, int mx,
-                                            int my) {
+                                            gptr<const S> __restrict__ src,
+                                            int mx, int my) {
   double m = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -290,8 +307,8 @@ __device__ __forceinline__ double mirror_m0(const StepArgs &A,
 // left to the closure.
 template <int Q, typename S, bool FAST, bool NEU = false>
 __device__ __forceinline__ void load_node(const StepArgs &A,
-                                          const S *__restrict__ src, int x,
-                                          int y, NodeLoad<Q, S> &L) {
+                                          gptr<const S> __restrict__ src,
+                                          int x, int y, NodeLoad<Q, S> &L) {
   const int64_t P = A.plane;
   const int nx = A.nx;
   int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
@@ -319,9 +336,9 @@ __device__ __forceinline__ void load_node(const StepArgs &A,
   // row pointers and unsigned column offsets: when the caller's y is
   // wave-uniform the row pointers are scalar and each load takes a scalar
   // base plus a 32-bit lane offset
-  const S *r0 = src + (int64_t)y * nx;
-  const S *rm = src + (int64_t)ym * nx;
-  const S *rp = src + (int64_t)yp * nx;
+  const gptr<const S> r0 = src + (int64_t)y * nx;
+  const gptr<const S> rm = src + (int64_t)ym * nx;
+  const gptr<const S> rp = src + (int64_t)yp * nx;
 #pragma unroll
   for (int j = 0; j < Q; ++j) L.own[j] = (r0 + j * P)[(uint32_t)x];
   L.known = 1u;
@@ -331,7 +348,7 @@ __device__ __forceinline__ void load_node(const StepArgs &A,
   for (int i = 1; i < Q; ++i) {
     const int ex = cx<Q>(i), ey = cy<Q>(i);
     const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
-    const S *sr = ey == 1 ? rm : (ey == -1 ? rp : r0);
+    const gptr<const S> sr = ey == 1 ? rm : (ey == -1 ? rp : r0);
     L.pull[i] = (sr + i * P)[(uint32_t)sx];
     if (!FAST) {
       const bool ok = (ex == 1 ? vxm : (ex == -1 ? vxp : true)) &&
@@ -380,7 +397,7 @@ __device__ __forceinline__ int dirichlet_wall(const StepArgs &A, int x, int y) {
 __device__ __forceinline__ double wall_value(const StepArgs &A, int wall, int x,
                                     int y) {
   const double *p = A.prof[wall];
-  return p ? p[wall < 2 ? y : x] : A.wall_T[wall];
+  return p ? to_global(p)[wall < 2 ? y : x] : A.wall_T[wall];
 }
 
 // Closure of the unknown pulled populations (Section 4.2):
@@ -564,10 +581,11 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
       return;
     }
   }
-  const double pth = phi_only(th, A.tm, A.inv_delta);
+  double pth, dpth;
+  phi_dphi(th, A.tm, A.inv_delta, pth, dpth);
   int it;
   bool conv;
-  const double tn = newton<PLAIN>(m0, th, pth, A, it, conv);
+  const double tn = newton<PLAIN>(m0, th, pth, dpth, A, it, conv);
   const double pnew = phi_only(tn, A.tm, A.inv_delta);
   const double dphi_s = pth - pnew;
   double f[Q];
@@ -588,15 +606,16 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
 
 // The update of one node from its loads; writes the next state.
 template <int Q, typename S, int MODE, bool FAST, bool NT = false>
-__device__ __forceinline__ void update_node(const StepArgs &A, S *__restrict__ dst,
-                                   int x, int y, const NodeLoad<Q, S> &L,
-                                   NodeStats &st) {
+__device__ __forceinline__ void update_node(const StepArgs &A,
+                                            gptr<S> __restrict__ dst, int x,
+                                            int y, const NodeLoad<Q, S> &L,
+                                            NodeStats &st) {
   S v[Q];
   update_values<Q, S, MODE, FAST>(A, x, y, L, st, v);
-  S *row = dst + (int64_t)y * A.nx;
+  const gptr<S> row = dst + (int64_t)y * A.nx;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    S *p = (row + i * A.plane) + (uint32_t)x;
+    const gptr<S> p = (row + i * A.plane) + (uint32_t)x;
     if (NT) __builtin_nontemporal_store(v[i], p);
     else *p = v[i];
   }

@@ -87,9 +87,9 @@ __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
 // returns whether the tile took the interior path.
 template <int Q, typename S, int NPT, int MODE, bool NT>
 __device__ __forceinline__ bool step_tile(const StepArgs &A,
-                                          const S *__restrict__ src,
-                                          S *__restrict__ dst, int tx, int ty,
-                                          NodeStats &st) {
+                                          gptr<const S> __restrict__ src,
+                                          gptr<S> __restrict__ dst, int tx,
+                                          int ty, NodeStats &st) {
   const int bx = blockDim.x, by = blockDim.y;
   const int TW = bx * NPT;
   const int x0 = tx * TW, y0 = ty * by;
@@ -130,8 +130,8 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
 template <int Q, typename S, int NPT, int MODE, bool NT = false,
           bool LOOP = false>
 __device__ __forceinline__ void step_item(const StepArgs &A,
-                                          const S *__restrict__ src,
-                                          S *__restrict__ dst, int item,
+                                          gptr<const S> __restrict__ src,
+                                          gptr<S> __restrict__ dst, int item,
                                           StatSlot *slot) {
   const int tx = item % A.tiles_x;
   const int ty0 = (item / A.tiles_x) * A.group;
@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int b = blockIdx.x;
   if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
   const int t = xcd_item(b, A.per_xcd, A.nitems, A.reverse);
-  step_item<Q, S, NPT, MODE, NT>(A, (const S *)A.src, (S *)A.dst, t,
-                                  A.slots + t);
+  step_item<Q, S, NPT, MODE, NT>(A, to_global((const S *)A.src),
+                                  to_global((S *)A.dst), t, A.slots + t);
 }
 
 // ---------------------------------------------------------------------
@@ -248,8 +248,8 @@ __device__ __forceinline__ void ring_update(const StepArgs &A,
 // one (the rows of step n + 1 are then written out directly).
 template <int Q, typename S, int MODE, bool NT, int BY, int WIN>
 __device__ __forceinline__ void step2_body(const StepArgs &A,
-                                           const S *__restrict__ src,
-                                           S *__restrict__ dst, int strip,
+                                           gptr<const S> __restrict__ src,
+                                           gptr<S> __restrict__ dst, int strip,
                                            int seg, int seg_rows, bool two,
                                            StatSlot *slot) {
   constexpr int RING = BY + 2;
@@ -386,7 +386,8 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
   const int per_xcd = (nitems + 7) >> 3;
   const int item = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (item >= nitems) return;
-  step2_body<Q, S, MODE, NT, BY, WIN>(A, (const S *)A.src, (S *)A.dst,
+  step2_body<Q, S, MODE, NT, BY, WIN>(A, to_global((const S *)A.src),
+                                       to_global((S *)A.dst),
                                        item % nstrips, item / nstrips,
                                        seg_rows, two != 0, A.slots + item);
 }

@@ -367,10 +367,11 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
       return;
     }
   }
-  const double pth = phi_only(th, A.tm, A.inv_delta);
+  double pth, dpth;
+  phi_dphi(th, A.tm, A.inv_delta, pth, dpth);
   int it;
   bool conv;
-  const double tn = newton<PLAIN>(m0, th, pth, A, it, conv);
+  const double tn = newton<PLAIN>(m0, th, pth, dpth, A, it, conv);
   const double pnew = phi_only(tn, A.tm, A.inv_delta);
   const double dphi_s = pth - pnew;
   double f[Q];

@@ -31,8 +31,8 @@ __device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
   const int inst = __builtin_amdgcn_readfirstlane(e.x);
   const int item = __builtin_amdgcn_readfirstlane(e.y);
   const StepArgs &A = descs[inst];
-  const S *src = (const S *)(parity ? A.dst : A.src);
-  S *dst = (S *)(parity ? A.src : A.dst);
+  const auto src = to_global((const S *)(parity ? A.dst : A.src));
+  const auto dst = to_global((S *)(parity ? A.src : A.dst));
   step_item<Q, S, NPT, MODE, NT, LOOP>(A, src, dst, item, A.slots + item);
 }
 
@@ -79,8 +79,8 @@ void batch_step2_kernel(const StepArgs *__restrict__ descs,
   const int inst = __builtin_amdgcn_readfirstlane(e.x);
   const int item = __builtin_amdgcn_readfirstlane(e.y);
   const StepArgs &A = descs[inst];
-  const S *src = (const S *)(parity ? A.dst : A.src);
-  S *dst = (S *)(parity ? A.src : A.dst);
+  const auto src = to_global((const S *)(parity ? A.dst : A.src));
+  const auto dst = to_global((S *)(parity ? A.src : A.dst));
   step2_body<Q, S, MODE, true, BY, WIN>(A, src, dst, item % A.tiles_x,
                                         item / A.tiles_x, A.group, two != 0,
                                         A.slots + item);
