@@ -12,7 +12,8 @@ the seed, delta = 1.5 cells, tau = 0.6, Newton tol 1e-12.
 
 Further forms in "forms" (--forms): the batched form (512 D2Q5 lattices,
 64^2 to 1024^2), the reverse mode (512^2 D2Q5, 4096 steps), the explicit
-scheme on the same cavity, the paper's 2D freezing case and 1D case with
+scheme on the same cavity, the 2048^2 D2Q5 planar front (10,000 steps,
+both schemes), the paper's 2D freezing case and 1D case with
 the three schemes, the 512^3 cube on D3Q19 and D3Q7, and the freezing
 case taken to 3D.
 
@@ -214,6 +215,44 @@ def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1):
         "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
         "time_ratio_irebm_to_eebm": round(irebm_ms_per_step / ms, 3),
     }
+
+
+def time_planar(steps=10000, warmup=20, autotune=True):
+    """The plain step on the 2048^2 planar-front lattice (D2Q5, FP32
+    storage, 10,000 steps): both state buffers (2 x 84 MB) fit in the
+    memory-side cache, so the algorithmic rate can exceed what HBM alone
+    delivers.  The explicit scheme on the same lattice gives the time
+    ratio."""
+    import synth
+    from paper_2505_13097_amd import variant_names
+    out = {}
+    for scheme in ("irebm", "eebm"):
+        prob = synth.planar_2d(nsteps=steps)
+        if scheme == "eebm":
+            prob = prob.with_(scheme="eebm", name=prob.name + "_eebm")
+        r = time_plain(prob, steps, warmup, -1, autotune=autotune)
+        v = r["variant"] if r["variant"] >= 0 else 3
+        vname = variant_names(prob.q, prob.storage)[v]
+        spl = steps_per_launch(vname)
+        launch_ms = r["gpu_ms"] / (steps // spl)
+        gbps = prob.nodes * bytes_per_node(prob) * spl / (launch_ms * 1e-3) / 1e9
+        out[scheme] = {
+            "workload": prob.name, "steps": steps,
+            "value": round(prob.nodes * steps / r["wall_s"] / 1e6, 1),
+            "unit": "MLUPS",
+            "ms_per_step": round(r["gpu_ms"] / steps, 5),
+            "kernel_variant": vname,
+            "hbm_gbps_algorithmic": round(gbps, 1),
+            "frac_of_peak": round(gbps / HBM_PEAK_GBPS, 4),
+            "newton_max_it": r["stats"]["max_newton_it"],
+            "nonconverged": r["stats"]["nonconverged"],
+            "front_mean": round(r["front_mean"], 6),
+        }
+    irebm = out["irebm"]
+    irebm["eebm_ms_per_step"] = out["eebm"]["ms_per_step"]
+    irebm["time_ratio_irebm_to_eebm"] = round(
+        irebm["ms_per_step"] / out["eebm"]["ms_per_step"], 3)
+    return irebm
 
 
 CUBE3D_N = 512
@@ -820,10 +859,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--forms",
-                    default="plain,batched,adjoint,eebm,freezing,paper1d,"
-                            "cube3d,freezing3d",
+                    default="plain,batched,adjoint,eebm,planar,freezing,"
+                            "paper1d,cube3d,freezing3d",
                     help="comma list of extra forms to time: batched, "
-                         "adjoint, eebm, freezing, paper1d, cube3d, "
+                         "adjoint, eebm, planar, freezing, paper1d, cube3d, "
                          "freezing3d")
     ap.add_argument("--cube3d-only", action="store_true",
                     help="time the 3D form alone (profile runs)")
@@ -994,6 +1033,10 @@ def main():
                                   not args.no_autotune, ms_per_step,
                                   variant=args.variant)
         print("[bench] eebm done", file=sys.stderr, flush=True)
+    if "planar" in args.forms.split(","):
+        print("[bench] planar form", file=sys.stderr, flush=True)
+        forms["planar"] = time_planar(autotune=not args.no_autotune)
+        print("[bench] planar done", file=sys.stderr, flush=True)
     if "freezing" in args.forms.split(","):
         print("[bench] freezing form", file=sys.stderr, flush=True)
         forms["freezing"] = time_freezing()

@@ -159,7 +159,9 @@ typedef struct lbm_stefan_params {
   int32_t strict;        /* nonzero: lbm_stefan_step returns
                             LBM_STEFAN_ENOTCONV if a solve hit the cap */
   int32_t variant;       /* kernel variant (lbm_stefan_variant_name); -1
-                            picks the library default for the lattice */
+                            picks the library default for the lattice
+                            (D1Q3 lattices the resident variant takes:
+                            that one) */
   int32_t flags;         /* LBM_FLAG_* */
   int32_t scheme;        /* LBM_SCHEME_*; 0 (zeroed params) is IREBM */
   int64_t nz;            /* dim 3: nodes along z, >= 3; ignored otherwise */
@@ -274,11 +276,14 @@ int lbm_stefan_state_ptr(lbm_stefan_t *h, void **dev_state);
    name of one ("<tile_x>x<tile_y>/npt<k>[/r<m>][/nt][/rev]": tile size,
    nodes per thread, m tiles stacked along y per thread block,
    non-temporal stores, block order reversed every other step; or
-   "256x<b>/t2/r<m>[/nt]": two time steps per launch, a 256-column window
+   "<w>x<b>/t2/r<m>[/nt]": two time steps per launch, a w-column window
    sweeping m rows, b rows per pass; a single trailing step then uses the
-   default variant, and the batched form rejects these; 3D lattices,
-   q = 7 or 19: "<tile_x>x<tile_y>/npt<k>/z<c>[/nt]", c z slices swept by
-   one block); used by autotuners. */
+   default variant, and a lattice with a Neumann wall runs the default
+   variant; q = 3 also "resident2048": D1Q3 lattices of at most 2048 nodes
+   with no Neumann wall run many steps per launch in one workgroup, both
+   states in LDS (others run the default variant; the batched form rejects
+   it); 3D lattices, q = 7 or 19: "<tile_x>x<tile_y>/npt<k>/z<c>[/nt]", c z
+   slices swept by one block); used by autotuners. */
 int lbm_stefan_variant_count(int32_t q, int32_t storage, int32_t *count);
 const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
                                     int32_t variant);

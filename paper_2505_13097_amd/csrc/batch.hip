@@ -358,9 +358,12 @@ int lbm_stefan_batch_set_schedule(lbm_stefan_batch_t *b, int32_t variant,
                                   int32_t blocks_per_cu, int32_t graph_steps) {
   if (!b) return bfail(nullptr, LBM_STEFAN_EINVAL, "batch is NULL");
   int nv;
-  variants(b->q, &nv);
+  const Variant *vt = variants(b->q, &nv);
   if (variant < -1 || variant >= nv)
     return bfail(b, LBM_STEFAN_EINVAL, "unknown kernel variant");
+  if (variant >= 0 && vt[variant].res)
+    return bfail(b, LBM_STEFAN_EINVAL,
+                 "the resident variant runs single lattices only");
   if (blocks_per_cu < 0 || blocks_per_cu > 32)
     return bfail(b, LBM_STEFAN_EINVAL, "blocks_per_cu must be in 0..32");
   if (graph_steps < 0 || graph_steps % 2 || graph_steps > 100000)
@@ -534,6 +537,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
   int rc = LBM_STEFAN_OK;
   hipError_t err = hipSuccess;
   for (int v = 0; v < nv && rc == LBM_STEFAN_OK && err == hipSuccess; ++v) {
+    if (vt[v].res) continue;  // single lattices only
     if (v != b->variant) {
       b->variant = v;
       rc = build_schedule(b);

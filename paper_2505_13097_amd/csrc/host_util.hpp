@@ -20,14 +20,17 @@ namespace irebm {
 // that the rows written last (still in the memory-side cache) are read
 // first.  tb: two steps per launch (step2_kernel): a window of bx columns
 // (bx - 4 written), by rows per pass, `rows` rows per block, non-temporal
-// stores.
+// stores.  res: D1Q3 lattices of at most kResident1D nodes run many steps
+// per launch in one workgroup (resident1d_kernel); others take the default
+// one-step tiling.
 struct Variant {
-  int bx, by, npt, nt, rev, rows, tb;
+  int bx, by, npt, nt, rev, rows, tb, res;
 };
 
 inline const Variant *variants(int q, int *n) {
   static const Variant v1[] = {{256, 1, 1, 0, 0, 1, 0}, {128, 1, 1, 0, 0, 1, 0},
-                               {64, 1, 1, 0, 0, 1, 0},  {256, 1, 2, 0, 0, 1, 0}};
+                               {64, 1, 1, 0, 0, 1, 0},  {256, 1, 2, 0, 0, 1, 0},
+                               {1024, 1, 2, 0, 0, 1, 0, 1}};
   static const Variant v2[] = {
       {64, 4, 1, 0, 0, 1, 0}, {256, 1, 1, 0, 0, 1, 0}, {128, 2, 1, 0, 0, 1, 0},
       {64, 4, 2, 0, 0, 1, 0}, {128, 2, 2, 0, 0, 1, 0}, {256, 1, 2, 0, 0, 1, 0},
@@ -49,6 +52,7 @@ inline const Variant *variants(int q, int *n) {
   return v2;
 }
 constexpr int kDefaultVariant1D = 0;
+constexpr int kResidentVariant1D = 4;
 constexpr int kDefaultVariant2D = 3;
 
 inline int64_t tiles_x_for(const Variant &v, int64_t nx) {

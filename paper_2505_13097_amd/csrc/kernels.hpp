@@ -393,6 +393,86 @@ void step2_kernel(StepArgs A, int32_t nstrips, int32_t seg_rows,
 }
 
 // ---------------------------------------------------------------------
+// small 1D lattices: many steps in one resident workgroup
+
+// Largest D1Q3 lattice the resident kernel takes: both states of 2048
+// nodes fit in LDS (96 KB in FP64).
+constexpr int kResident1D = 2048;
+
+// nsteps steps of a D1Q3 lattice of at most kResident1D nodes with no
+// Neumann wall, in one workgroup of 1024 threads: the state at A.src is
+// loaded once into LDS, each step reads one LDS state and writes the
+// other (the same per-node code as step_kernel), a barrier separates the
+// steps, and at the end the two LDS
+// states go back to the two global buffers exactly as nsteps one-step
+// launches would leave them: the last state in A.src when nsteps is even
+// (A.dst otherwise), the one before it in the other buffer.  Statistics
+// of all nsteps go to slot 0.
+template <typename S, int MODE>
+__global__ __launch_bounds__(1024) void resident1d_kernel(StepArgs A,
+                                                          int32_t nsteps) {
+  constexpr int Q = 3;
+  __shared__ S st_lds[2][Q][kResident1D];
+  const int n = A.nx;
+  if (n > kResident1D) return;  // the host never launches such a lattice
+  const int t = (int)threadIdx.x;
+  const gptr<S> b0 = to_global((S *)A.src);
+  const gptr<S> b1 = to_global((S *)A.dst);
+  const int64_t P = A.plane;
+  for (int x = t; x < n; x += 1024) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) st_lds[0][j][x] = b0[j * P + x];
+  }
+  __syncthreads();
+  const bool px = A.periodic_x != 0;
+  NodeStats st;
+  for (int s = 0; s < nsteps; ++s) {
+    const int c = s & 1;
+    // arguments read in place each step (see step_item); a by-value copy
+    // would index the wall arrays from private memory
+    int k0 = 0;
+    asm volatile("" : "+s"(k0));
+    const StepArgs &B = (&A)[k0];
+    for (int x = t; x < n; x += 1024) {
+      NodeLoad<Q, S> L;
+      // directions +x (1) and -x (2): the pull source x - 1 (x + 1) is a
+      // lattice node, or the destination x + 1 (x - 1) leaves the lattice
+      // (node_masks for D1Q3, written out)
+      const bool vm = x >= 1 || px, vp = x + 1 < n || px;
+      L.known = 1u | (vm ? 2u : 0u) | (vp ? 4u : 0u);
+      L.out = (vp ? 0u : 2u) | (vm ? 0u : 4u);
+      L.mirror = 0.0;
+      // pull sources wrapped on a periodic axis, clamped otherwise (then
+      // masked)
+      const int xm = x >= 1 ? x - 1 : (px ? n - 1 : 0);
+      const int xp = x + 1 < n ? x + 1 : (px ? 0 : n - 1);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) L.own[j] = st_lds[c][j][x];
+      L.pull[0] = L.own[0];
+      L.pull[1] = (L.known >> 1 & 1u) ? st_lds[c][1][xm] : (S)0;
+      L.pull[2] = (L.known >> 2 & 1u) ? st_lds[c][2][xp] : (S)0;
+      // the closures run only where a direction is unknown or leaves
+      S v[Q];
+      update_values<Q, S, MODE, false>(B, x, 0, L, st, v);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st_lds[c ^ 1][i][x] = v[i];
+    }
+    __syncthreads();
+  }
+  // state k lies in LDS state k % 2, as in global buffer k % 2
+  for (int x = t; x < n; x += 1024) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      b1[j * P + x] = st_lds[1][j][x];
+      b0[j * P + x] = st_lds[0][j][x];
+    }
+  }
+  StatSlot pre{};
+  if (t == 0) pre = A.slots[0];
+  block_stats_to_slot<false>(st, false, pre, A.slots);
+}
+
+// ---------------------------------------------------------------------
 // init, temperature, zero fill
 
 // IREBM and ILFBM: Omega_i = w_i T (and, when lf is given, the ILFBM

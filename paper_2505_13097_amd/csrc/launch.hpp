@@ -209,6 +209,16 @@ hipError_t step2_launch_mode(int q, int storage, const StepArgs &A,
 }
 
 template <int MODE>
+hipError_t resident_launch_mode(int storage, const StepArgs &A,
+                                int32_t nsteps, hipStream_t stream) {
+  if (storage == LBM_STORE_F32)
+    resident1d_kernel<float, MODE><<<1, 1024, 0, stream>>>(A, nsteps);
+  else
+    resident1d_kernel<double, MODE><<<1, 1024, 0, stream>>>(A, nsteps);
+  return hipGetLastError();
+}
+
+template <int MODE>
 hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
                              const Variant &v, hipStream_t stream) {
   return dispatch_qs(q, storage, [&](auto qt, auto tt) {
@@ -225,7 +235,9 @@ hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
       hipStream_t);                                                        \
   template hipError_t irebm::step2_launch_mode<M>(                         \
       int, int, const irebm::StepArgs &, const irebm::Variant &, bool,     \
-      hipStream_t)
+      hipStream_t);                                                        \
+  template hipError_t irebm::resident_launch_mode<M>(                      \
+      int, const irebm::StepArgs &, int32_t, hipStream_t)
 
 #define IREBM_INSTANTIATE_STEP1(M)                                         \
   template hipError_t irebm::step_launch_mode<M>(                          \

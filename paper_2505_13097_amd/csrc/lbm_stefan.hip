@@ -268,6 +268,27 @@ hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
     }
     return hipSuccess;
   }
+  {
+    int nv;
+    if (variants(h->p.q, &nv)[h->variant].res && resident_ok(h->p)) {
+      StepArgs A;
+      fill_step_args(h, &A);
+      const int mode = mode_of(h->p);
+      while (nsteps > 0) {
+        // bounded launches (a few ms each)
+        const int32_t k = (int32_t)std::min<int64_t>(nsteps, 4096);
+        A.src = h->buf[h->cur];
+        A.dst = h->buf[h->cur ^ 1];
+        const hipError_t e =
+            resident_launch(mode, h->p.storage, A, k, h->stream);
+        if (e != hipSuccess) return e;
+        h->cur ^= k & 1;
+        h->steps += k;
+        nsteps -= k;
+      }
+      return hipSuccess;
+    }
+  }
   if (two_step_variant(h)) {
     for (; nsteps >= 2; nsteps -= 2) {
       const hipError_t e =
@@ -294,8 +315,11 @@ hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
   A.dst = dst;
   int nv;
   const Variant *vt = variants(h->p.q, &nv);
-  // a single step under a two-step variant takes the default tiling
-  const Variant &v = vt[vt[h->variant].tb ? kDefaultVariant2D : h->variant];
+  // a single step under a two-step variant takes the default tiling, and
+  // so does a step under the resident variant
+  const Variant &v = vt[vt[h->variant].tb    ? kDefaultVariant2D
+                        : vt[h->variant].res ? kDefaultVariant1D
+                                             : h->variant];
   return step_launch(mode_of(h->p), h->p.q, h->p.storage, A, v,
                      v.rev && (h->steps & 1), h->stream);
 }
@@ -401,10 +425,13 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   h->p = *p;
   if (h->p.dx == 0.0) h->p.dx = 1.0 / (double)(p->nx - 1);
   if (p->dim == 1) h->p.bc[2] = h->p.bc[3] = LBM_BC_PERIODIC;
+  // default: the resident kernel for the small 1D lattices it takes
   h->variant = p->variant >= 0
                    ? p->variant
                    : (p->dim == 3 ? kDefaultVariant3D
-                                  : (p->q == 3 ? kDefaultVariant1D
+                                  : (p->q == 3 ? (resident_ok(*p)
+                                                      ? kResidentVariant1D
+                                                      : kDefaultVariant1D)
                                                : kDefaultVariant2D));
   h->stream = (hipStream_t)stream;
   if (hipGetDevice(&h->device) != hipSuccess) {
@@ -595,7 +622,9 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
   const Variant &w = v[variant];
   char rows[16] = "";
   if (w.rows > 1) std::snprintf(rows, sizeof(rows), "/r%d", w.rows);
-  if (w.tb)
+  if (w.res)
+    std::snprintf(buf, sizeof(buf), "resident%d", (int)kResident1D);
+  else if (w.tb)
     std::snprintf(buf, sizeof(buf), "%dx%d/t2%s%s", w.bx, w.by, rows,
                   w.nt ? "/nt" : "");
   else
@@ -653,8 +682,10 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
   float best_ms = 0.0f;
   hipError_t err = hipSuccess;
   for (int v = 0; v < nv && err == hipSuccess; ++v) {
-    // a Neumann lattice runs two-step variants as the default one
+    // a Neumann lattice runs two-step variants as the default one, and a
+    // lattice the resident kernel does not take runs that variant so too
     if (vt && vt[v].tb && has_neumann(p)) continue;
+    if (vt && vt[v].res && !resident_ok(p)) continue;
     h->variant = v;
     // two untimed steps, then the timed trial (an even count, so that a
     // two-step variant runs its own kernel only)

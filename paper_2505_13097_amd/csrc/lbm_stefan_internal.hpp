@@ -122,6 +122,11 @@ hipError_t step2_launch_mode(int q, int storage, const StepArgs &A,
 template <int MODE>
 hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
                              const Variant &v, hipStream_t stream);
+// nsteps steps of a small D1Q3 lattice in one resident workgroup
+// (resident1d_kernel; the lattice passes resident_ok)
+template <int MODE>
+hipError_t resident_launch_mode(int storage, const StepArgs &A,
+                                int32_t nsteps, hipStream_t stream);
 
 #define IREBM_DECLARE_STEP1(M)                                             \
   extern template hipError_t step_launch_mode<M>(                          \
@@ -130,6 +135,8 @@ hipError_t batch_launch_mode(int q, int storage, const BatchLaunch &b,
   IREBM_DECLARE_STEP1(M);                                                  \
   extern template hipError_t step2_launch_mode<M>(                         \
       int, int, const StepArgs &, const Variant &, bool, hipStream_t);     \
+  extern template hipError_t resident_launch_mode<M>(                      \
+      int, const StepArgs &, int32_t, hipStream_t);                       \
   extern template hipError_t batch_launch_mode<M>(                         \
       int, int, const BatchLaunch &, const Variant &, hipStream_t)
 IREBM_DECLARE_MODE(kSafeguarded);
@@ -161,6 +168,23 @@ inline bool has_neumann(const lbm_stefan_params &p) {
     for (int k = 0; k < 2; ++k)
       if (p.bc_z[k] == LBM_BC_NEUMANN) return true;
   return false;
+}
+
+// can the lattice run under the resident variant (resident1d_kernel)?
+// D1Q3, at most kResident1D nodes, no Neumann wall, IREBM or EEBM
+inline bool resident_ok(const lbm_stefan_params &p) {
+  return p.dim == 1 && p.q == 3 && p.nx <= kResident1D && !has_neumann(p) &&
+         p.scheme != LBM_SCHEME_ILFBM;
+}
+
+// one launch of resident1d_kernel: nsteps steps of one small 1D lattice
+inline hipError_t resident_launch(int mode, int storage, const StepArgs &A,
+                                  int32_t nsteps, hipStream_t stream) {
+  if (mode == kEebm)
+    return resident_launch_mode<kEebm>(storage, A, nsteps, stream);
+  if (mode == kPlain)
+    return resident_launch_mode<kPlain>(storage, A, nsteps, stream);
+  return resident_launch_mode<kSafeguarded>(storage, A, nsteps, stream);
 }
 
 // nodes of a lattice, and its rows along x (one front value each)

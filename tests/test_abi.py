@@ -120,7 +120,10 @@ def test_variants_listed(L):
         names = variant_names(q)
         assert len(names) >= 3
         assert all(re.fullmatch(r"\d+x\d+(/npt\d|/t2)(/r\d+)?(/nt)?(/rev)?", n)
-                   for n in names)
+                   or (q == 3 and n == "resident2048") for n in names)
+    # D1Q3 only: the resident variant, last in its list
+    assert variant_names(3)[-1] == "resident2048"
+    assert "resident2048" not in variant_names(5) + variant_names(9)
     assert L.lib().lbm_stefan_variant_name(5, 1, 999) == b""
 
 
