@@ -615,9 +615,15 @@ def time_adjoint(prob, interval, autotune=True):
 SWEEP_STEPS = 4
 
 
-def steps_per_launch(variant_name):
+RESIDENT_STEPS = 4096   # steps per launch of the resident D1Q3 kernel
+
+
+def steps_per_launch(variant_name, steps=1):
     """Time steps one launch of this variant advances (two for the
-    temporally blocked "/t2" variants)."""
+    temporally blocked "/t2" variants; up to RESIDENT_STEPS of a run of
+    `steps` for the resident D1Q3 kernel)."""
+    if variant_name.startswith("resident"):
+        return min(steps, RESIDENT_STEPS)
     return 2 if "/t2" in variant_name else 1
 
 
@@ -948,14 +954,16 @@ def main():
     mlups = prob.nodes * args.steps / r["wall_s"] / 1e6
     v = r["variant"] if r["variant"] >= 0 else (0 if prob.q == 3 else 3)
     vname = variant_names(prob.q, prob.storage)[v]
-    spl = steps_per_launch(vname)
-    if args.steps % spl:
+    resident = vname.startswith("resident")
+    spl = steps_per_launch(vname, args.steps)
+    if args.steps % 2 and spl == 2:
         raise SystemExit("--steps must be even for a two-step variant")
-    launch_ms = r["gpu_ms"] / (args.steps // spl)
+    launches = -(-args.steps // spl)
+    launch_ms = r["gpu_ms"] / launches
     bpn = bytes_per_node(prob)
     # algorithmic bytes per launch: 2 q s per lattice update, times the
-    # updates one launch performs
-    achieved = prob.nodes * bpn * spl / (launch_ms * 1e-3) / 1e9
+    # updates one launch performs (the same rate over the whole run)
+    achieved = prob.nodes * bpn * args.steps / (r["gpu_ms"] * 1e-3) / 1e9
 
     if args.copy_probe:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -998,7 +1006,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": measured_traffic(prob.name, vname),
-            "kernel": "step2_kernel" if spl == 2 else "step_kernel",
+            "kernel": ("resident1d_kernel" if resident else
+                       "step2_kernel" if spl == 2 else "step_kernel"),
             "steps_per_launch": spl,
             "bytes_per_lattice_update": bpn,
             "avg_launch_us": round(launch_ms * 1e3, 2),
@@ -1009,6 +1018,11 @@ def main():
             "max_residual": r["stats"]["max_residual"],
         },
     }
+    if resident:
+        out["roofline"]["note"] = (
+            "the state stays in LDS between steps: the rate is the "
+            "metric's algorithmic bytes, HBM is touched once per launch; "
+            "the per-step latency of one workgroup bounds this kernel")
     forms = {}
     if "batched" in args.forms.split(","):
         import synth as S
