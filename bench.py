@@ -943,7 +943,7 @@ def main():
         print(json.dumps({"traffic_sweep": prob.name, "variants": names,
                           "steps_each": SWEEP_STEPS}), flush=True)
         return
-    print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D2Q{prob.q} "
+    print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D{prob.dim}Q{prob.q} "
           f"steps {args.steps} warmup {args.warmup}", file=sys.stderr,
           flush=True)
     r = time_plain(prob, args.steps, args.warmup, args.variant,
