@@ -115,6 +115,13 @@ def _smooth_mushy(prob, amp_cells=2.0, walls_cells=2.0):
     return prob.with_(T0=T0, wall_T=wall)
 
 
+def _shift_tm(prob, tm):
+    """The same problem with melting temperature tm: T0 and the wall
+    temperatures move with it."""
+    return prob.with_(tm=tm, T0=np.asarray(prob.T0) + tm,
+                      wall_T=tuple(w + tm for w in prob.wall_T))
+
+
 def test_stefan_1d_full_run_fp64():
     """The 1D workload at full length: D1Q3, N = 256, 20k steps, FP64."""
     prob = synth.stefan_1d()
@@ -155,6 +162,17 @@ CASES = [
         n=77, ny=52, storage=s)).with_(
             bc=("periodic", "periodic", "bounceback", "bounceback")), 200),
     ("d2q5_tiny_3x3", lambda s: synth.planar_2d(n=3, ny=3, storage=s), 40),
+    # degenerate parameters: no latent heat (1/Ste = 1e-12: one or two
+    # Newton iterations, BGK diffusion), a sharp band (delta half a cell),
+    # tau next to 1/2 (a = 1 - 1/tau near -1), melting at T_m = 0.25
+    ("d2q5_no_latent_heat", lambda s: _smooth_mushy(synth.planar_2d(
+        n=96, ny=40, storage=s)).with_(ste=1e12), 200),
+    ("d2q9_sharp_delta", lambda s: _smooth_mushy(synth.cavity_2d(
+        n=101, ny=58, storage=s).with_(delta=0.5 / 100)), 200),
+    ("d2q5_tau_near_half", lambda s: _smooth_mushy(synth.planar_2d(
+        n=96, ny=40, storage=s)).with_(tau=0.5005), 200),
+    ("d2q9_melting_at_0.25", lambda s: _shift_tm(_smooth_mushy(
+        synth.cavity_2d(n=88, ny=61, storage=s)), 0.25), 200),
     ("d1q3_plain_newton", lambda s: synth.stefan_1d(nx=333).with_(
         newton_mode="plain", storage=s), 500),
 ]
