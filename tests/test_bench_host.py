@@ -1,0 +1,44 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU refusal, steps per
+launch of each kind of kernel variant, and the algorithmic bytes per
+lattice update the roofline uses (2 q sizeof(population))."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import synth  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_steps_per_launch():
+    assert bench.steps_per_launch("128x4/t2/r32/nt") == 2
+    assert bench.steps_per_launch("256x1/npt1") == 1
+    assert bench.steps_per_launch("128x4/npt2/r16/nt/rev") == 1
+    # the resident D1Q3 kernel: up to RESIDENT_STEPS steps per launch
+    assert bench.steps_per_launch("resident2048", 20000) == bench.RESIDENT_STEPS
+    assert bench.steps_per_launch("resident2048", 100) == 100
+
+
+def test_bytes_per_lattice_update():
+    assert bench.bytes_per_node(synth.cavity_2d(n=64)) == 72          # D2Q9 FP32
+    assert bench.bytes_per_node(synth.planar_2d(n=64)) == 40          # D2Q5 FP32
+    assert bench.bytes_per_node(synth.stefan_1d(nx=64)) == 48         # D1Q3 FP64
+    assert bench.bytes_per_node(synth.cavity_3d(n=8, q=19)) == 152    # D3Q19 FP32
+    assert bench.bytes_per_node(synth.cavity_3d(n=8, q=7)) == 56      # D3Q7 FP32
+
+
+def test_traffic_of_an_unmeasured_variant_is_null():
+    assert bench.measured_traffic("cavity2d_d2q9_f32_8192x8192",
+                                  "no/such/variant") is None
