@@ -118,9 +118,10 @@ __device__ __forceinline__ void local_reverse(const AdjArgs &G, int x, int y,
   phi_dphi(th, tm, A.inv_delta, P, d);
   int it;
   bool conv;
-  const double tn = newton<PLAIN>(m0, th, P, d, A, it, conv);
-  double Pt, dt;
-  phi_dphi(tn, tm, A.inv_delta, Pt, dt);
+  PhiAt at;
+  const double tn = newton<PLAIN>(m0, th, P, d, A, it, conv, at);
+  double Pt = at.ph, dt = at.dph;
+  if (!at.ok) phi_dphi(tn, tm, A.inv_delta, Pt, dt);
   const double dP = dphi_ddelta(th, tm, dl, d);
   const double dPt = dphi_ddelta(tn, tm, dl, dt);
   // reverse of Omega' = a f~ + (w/tau) sum f~

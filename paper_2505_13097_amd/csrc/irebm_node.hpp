@@ -163,6 +163,13 @@ __host__ __device__ __forceinline__ double eebm_lf(double H, double tm,
   return l < 0.0 ? 0.0 : (l > 1.0 ? 1.0 : l);
 }
 
+// phi and phi' at the value a Newton solve returns, when the solve
+// already evaluated them there (ok); the caller then needs no evaluation
+struct PhiAt {
+  double ph = 0.0, dph = 0.0;
+  bool ok = false;
+};
+
 // ---- local Newton solve of eq. rhs_fl_2:
 //   F(t) = t + phi(t)/Ste - c = 0,  c = m0 + phi(T)/Ste,
 // started from t = T (Algorithm 3); pth and dpth are phi(T) and phi'(T),
@@ -177,7 +184,7 @@ __host__ __device__ __forceinline__ double eebm_lf(double H, double tm,
 template <bool PLAIN, class AR>
 __device__ __forceinline__ double newton(double m0, double th, double pth,
                                          double dpth, const AR &A, int &iters,
-                                         bool &conv) {
+                                         bool &conv, PhiAt &at) {
   const double s = A.inv_ste;
   const double c = m0 + pth * s;
   double lo = c - s, hi = c;
@@ -195,6 +202,8 @@ __device__ __forceinline__ double newton(double m0, double th, double pth,
       const bool one = fabs(d) <= A.tol;
       conv = one || A.max_it >= 2;
       iters = (one || A.max_it < 2) ? 1 : 2;
+      at.ph = at.dph = 0.0;  // m0 lies below the band too
+      at.ok = true;
       return m0;
     }
   }
@@ -234,10 +243,17 @@ __device__ __forceinline__ double newton(double m0, double th, double pth,
   iters = k;
   // one more Newton step from the converged iterate: a solve that stopped
   // on a bisection step is then the root to rounding, not any point within
-  // tol of it, so the result does not depend on the safeguard's path
+  // tol of it, so the result does not depend on the safeguard's path.
+  // ph, dph belong to cand; they still do when the step changes nothing
+  // (or when the solve stopped at the cap)
+  at.ph = ph;
+  at.dph = dph;
+  at.ok = true;
   if (conv) {
     const double F = cand + ph * s - c;
-    cand -= (dph == 0.0) ? F : F / (1.0 + dph * s);
+    const double next = cand - ((dph == 0.0) ? F : F / (1.0 + dph * s));
+    at.ok = next == cand;
+    cand = next;
   }
   return cand;
 }
@@ -585,8 +601,9 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   phi_dphi(th, A.tm, A.inv_delta, pth, dpth);
   int it;
   bool conv;
-  const double tn = newton<PLAIN>(m0, th, pth, dpth, A, it, conv);
-  const double pnew = phi_only(tn, A.tm, A.inv_delta);
+  PhiAt at;
+  const double tn = newton<PLAIN>(m0, th, pth, dpth, A, it, conv, at);
+  const double pnew = at.ok ? at.ph : phi_only(tn, A.tm, A.inv_delta);
   const double dphi_s = pth - pnew;
   double f[Q];
   double tsum = 0.0;

@@ -371,8 +371,9 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
   phi_dphi(th, A.tm, A.inv_delta, pth, dpth);
   int it;
   bool conv;
-  const double tn = newton<PLAIN>(m0, th, pth, dpth, A, it, conv);
-  const double pnew = phi_only(tn, A.tm, A.inv_delta);
+  PhiAt at;
+  const double tn = newton<PLAIN>(m0, th, pth, dpth, A, it, conv, at);
+  const double pnew = at.ok ? at.ph : phi_only(tn, A.tm, A.inv_delta);
   const double dphi_s = pth - pnew;
   double f[Q];
   double tsum = 0.0;
