@@ -1,0 +1,340 @@
+"""CPU replay of the index arithmetic of the 3D step kernel (step3_kernel,
+load3, the Neumann mirror loads) and of the two-step 2D kernel
+(step2_body: the prefetched rows, the LDS rings, the delayed stores) for
+every kernel variant the library lists, on lattices smaller than one tile,
+one z slice group or one two-step window, and on ragged ones.
+
+Each replay walks the launch grid the host builds (blocks, XCD-contiguous
+item order, threads, z slices or row passes) with the formulas of the
+kernel source and asserts that every global load and store offset lies
+inside the q planes, every statistics slot inside the item table, every
+LDS index inside its array, and, for the rings, that each row read from
+LDS is the row the update wants (no slot was overwritten too early).
+The variant table is read from the library (lbm_stefan_variant_name), so
+a variant added to the table is replayed too; nothing runs on a GPU.
+"""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def names():
+    from paper_2505_13097_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2505_13097_amd import build
+        build.build(verbose=False)
+    from paper_2505_13097_amd import variant_names
+    return {q: variant_names(q, "f64") for q in (5, 9, 7, 19)}
+
+
+def _dirs3(q):
+    """velocity set of D3Q7 (faces) or D3Q19 (faces and edges)"""
+    out = [(0, 0, 0)]
+    for v in itertools.product((-1, 0, 1), repeat=3):
+        nz = sum(abs(c) for c in v)
+        if nz == 1 or (q == 19 and nz == 2):
+            out.append(v)
+    assert len(out) == q
+    return out
+
+
+def _dirs2(q):
+    out = [(0, 0)]
+    for v in itertools.product((-1, 0, 1), repeat=2):
+        nz = sum(abs(c) for c in v)
+        if nz == 1 or (q == 9 and nz == 2):
+            out.append(v)
+    assert len(out) == q
+    return out
+
+
+# ---------------------------------------------------------------------
+# 3D: step3_kernel
+
+def _parse3(name):
+    m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?", name)
+    tw, by, npt, cz = (int(m.group(k)) for k in range(1, 5))
+    return tw // npt, by, npt, cz
+
+
+def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
+            neu=(0, 0, 0, 0, 0, 0), bad_fast=False):
+    """Every offset step3_kernel touches; returns the number checked.
+    bad_fast: widen the fast path's x guard by one (a planted mistake)."""
+    P = nx * ny * nz
+    n = (nx, ny, nz)
+    tw = bx * npt
+    tiles = (-(-nx // tw), -(-ny // by), -(-nz // cz))
+    nitems = tiles[0] * tiles[1] * tiles[2]
+    per_xcd = (nitems + 7) // 8
+    dirs = _dirs3(q)
+    assert bx % 64 == 0 and bx * by <= 256      # __launch_bounds__(256)
+    checked = 0
+    seen = np.zeros(nitems, dtype=int)
+    tyy, txx = np.meshgrid(np.arange(by), np.arange(bx), indexing="ij")
+
+    def check(i, cx, cy, cz_):
+        """node (cx, cy, cz_) of plane i: each coordinate inside its axis,
+        the flat offset inside the planes"""
+        nonlocal checked
+        for v, m in ((cx, nx), (cy, ny), (cz_, nz)):
+            v = np.asarray(v)
+            assert v.min() >= 0 and v.max() < m, (v.min(), v.max(), m)
+        off = i * P + (np.asarray(cz_) * ny + cy) * nx + cx
+        assert off.min() >= 0 and off.max() < q * P
+        checked += np.size(off)
+
+    for b in range(8 * per_xcd):
+        t = (b & 7) * per_xcd + (b >> 3)
+        if t >= nitems:
+            continue
+        seen[t] += 1                      # the block's statistics slot
+        tx = t % tiles[0]
+        r = t // tiles[0]
+        ty, tz = r % tiles[1], r // tiles[1]
+        x0, y0 = tx * tw, ty * by
+        z0, z1 = tz * cz, min(tz * cz + cz, nz)
+        fxy = (x0 >= 1 and x0 + tw <= nx - (0 if bad_fast else 1) and
+               y0 >= 1 and y0 + by <= ny - 1)
+        for z in range(z0, z1):
+            fast = fxy and 1 <= z <= nz - 2
+            for k in range(npt):
+                x = (x0 + txx + k * bx).ravel()
+                y = (y0 + tyy).ravel()
+                if not fast:
+                    keep = (x < nx) & (y < ny)
+                    x, y = x[keep], y[keep]
+                if x.size == 0:
+                    continue
+                c = (x, y, np.full_like(x, z))
+                # neighbours: unclamped on the fast path, wrapped or
+                # clamped elsewhere (neighbours3)
+                m, p = [], []
+                for a in range(3):
+                    mm, pp = c[a] - 1, c[a] + 1
+                    if not fast:
+                        mm = np.where(mm < 0, mm + n[a] if periodic[a] else 0,
+                                      mm)
+                        pp = np.where(pp >= n[a], pp - n[a] if periodic[a]
+                                      else n[a] - 1, pp)
+                    m.append(mm)
+                    p.append(pp)
+                for i, e in enumerate(dirs):
+                    check(i, x, y, z)             # own populations, store
+                    s = [m[a] if e[a] == 1 else (p[a] if e[a] == -1 else c[a])
+                         for a in range(3)]
+                    check(i, s[0], s[1], s[2])
+                if not fast and any(neu):
+                    # mirror_m0_3: sources of the mirror node, clamped
+                    mir = [c[a].copy() for a in range(3)]
+                    on = np.zeros(x.size, dtype=bool)
+                    for a in range(3):
+                        if neu[2 * a]:
+                            hit = c[a] == 0
+                            mir[a] = np.where(hit, 1, mir[a])
+                            on |= hit
+                        if neu[2 * a + 1]:
+                            hit = c[a] == n[a] - 1
+                            mir[a] = np.where(hit, n[a] - 2, mir[a])
+                            on |= hit
+                    for i, e in enumerate(dirs):
+                        s = []
+                        for a in range(3):
+                            v = mir[a][on] - e[a]
+                            v = np.where(v < 0, v + n[a] if periodic[a] else 0,
+                                         v)
+                            v = np.where(v >= n[a], v - n[a] if periodic[a]
+                                         else n[a] - 1, v)
+                            s.append(v)
+                        if s[0].size:
+                            check(i, s[0], s[1], s[2])
+    assert np.all(seen == 1)              # every item once, one slot each
+    return checked
+
+
+SHAPES3 = [(12, 9, 7), (3, 3, 3), (4, 3, 5), (65, 5, 9), (130, 6, 10)]
+
+
+@pytest.mark.parametrize("q", [7, 19])
+def test_3d_kernel_offsets_inside_planes(names, q):
+    for name in names[q]:
+        bx, by, npt, cz = _parse3(name)
+        for shape in SHAPES3:
+            for per in ((0, 0, 0), (1, 0, 1)):
+                assert replay3(q, *shape, bx, by, npt, cz, per) > 0
+            # the freezing octant's Neumann faces (x+, y+, z+)
+            replay3(q, *shape, bx, by, npt, cz, (0, 0, 0),
+                    (0, 1, 0, 1, 0, 1))
+
+
+def test_3d_replay_detects_an_overrun():
+    """The replay itself: with the fast path's x guard one node too wide
+    (x0 + tw <= nx instead of nx - 1) the +x pull of the last column leaves
+    the lattice, and the replay says so."""
+    replay3(7, 128, 6, 6, 64, 2, 1, 4)
+    with pytest.raises(AssertionError):
+        replay3(7, 128, 6, 6, 64, 2, 1, 4, bad_fast=True)
+
+
+# ---------------------------------------------------------------------
+# 2D two-step kernel: step2_body
+
+def _parse_t2(name):
+    m = re.fullmatch(r"(\d+)x(\d+)/t2(/r(\d+))?(/nt)?", name)
+    return int(m.group(1)), int(m.group(2)), int(m.group(4) or 1)
+
+
+def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None):
+    """Every offset and LDS row step2_body touches; returns the number of
+    global accesses checked.  ring_rows: ring size other than the kernel's
+    BY + 2 (a planted mistake)."""
+    P = nx * ny
+    ring = by + 2 if ring_rows is None else ring_rows
+    nstrips = (nx + win - 5) // (win - 4)
+    nseg = -(-ny // rows)
+    nitems = nstrips * nseg
+    per_xcd = (nitems + 7) // 8
+    assert win % 64 == 0 and win * by <= 1024
+    dirs = _dirs2(q)
+    seen = np.zeros(nitems, dtype=int)
+    written = np.zeros((ny, nx), dtype=int)   # stores of the launch
+    checked = 0
+
+    def gcheck(j, gx, gy):
+        nonlocal checked
+        assert 0 <= gx < nx and 0 <= gy < ny, (gx, gy)
+        assert 0 <= j * P + gy * nx + gx < q * P
+        checked += 1
+
+    def lrow(r):
+        if 0 <= r < ny:
+            return r
+        return r % ny if py else -1
+
+    for bidx in range(8 * per_xcd):
+        item = (bidx & 7) * per_xcd + (bidx >> 3)
+        if item >= nitems:
+            continue
+        seen[item] += 1
+        strip, seg = item % nstrips, item // nstrips
+        s0 = seg * rows
+        s1 = min(s0 + rows, ny)
+        base = s0 - 12
+        iters = (s1 - s0 + 4 + by - 1) // by
+        # ring contents: the lattice row (window row index) in each slot
+        l0 = [None] * ring
+        l1 = [None] * ring
+        for t in range(win):
+            x = strip * (win - 4) - 2 + t
+            assert -2 <= x <= nx + win       # the window may overhang
+        cols = []
+        for t in range(win):
+            x = strip * (win - 4) - 2 + t
+            gx, col = x, 0 <= x < nx
+            if not col and px:
+                gx, col = x % nx, True
+            own_col = 2 <= t < win - 2 and 0 <= x < nx
+            cols.append((x, gx, col, own_col))
+        # first prefetch
+        for ty in range(by):
+            gr = lrow(s0 - 2 + ty)
+            for t in range(win):
+                x, gx, col, _ = cols[t]
+                for j in range(q):
+                    gcheck(j, gx if col else 0, 0 if gr < 0 else gr)
+        pend = []                        # stores waiting for the next pass
+        for i in range(iters):
+            a = s0 - 2 + i * by
+            for ty in range(by):
+                slot = a + ty - base
+                assert slot >= 0          # the unsigned modulo is the slot
+                l0[slot % ring] = a + ty
+            for (wx, wy) in pend:
+                for j in range(q):
+                    gcheck(j, wx, wy)
+            pend = []
+            if i + 1 < iters:
+                for ty in range(by):
+                    gr = lrow(a + by + ty)
+                    for t in range(win):
+                        x, gx, col, _ = cols[t]
+                        for j in range(q):
+                            gcheck(j, gx if col else 0, 0 if gr < 0 else gr)
+            # step n + 1 (barrier before: the ring holds rows a .. a+by-1)
+            new_l1 = {}
+            for ty in range(by):
+                rb = a - 1 + ty
+                gb = lrow(rb)
+                for t in range(win):
+                    x, gx, col, own_col = cols[t]
+                    if two:
+                        if not (1 <= t < win - 1 and col and gb >= 0 and
+                                s0 - 1 <= rb <= s1):
+                            continue
+                    elif not (own_col and s0 <= rb < s1):
+                        continue
+                    for (ex, ey) in dirs:
+                        rr = rb - ey
+                        assert 0 <= t - ex < win
+                        # a source row outside a non-periodic lattice is
+                        # read from LDS and masked: only real rows must be
+                        # the ones wanted
+                        if lrow(rr) >= 0:
+                            assert l0[(rr - base) % ring] == rr, (rr, l0)
+                    if two:
+                        new_l1[(rb - base) % ring] = rb
+                    else:
+                        pend.append((x, rb))
+                        written[rb, x] += 1
+            for k, v in new_l1.items():
+                l1[k] = v
+            # step n + 2 (after the second barrier)
+            if two:
+                for ty in range(by):
+                    c = a - 2 + ty
+                    for t in range(win):
+                        x, gx, col, own_col = cols[t]
+                        if not (own_col and s0 <= c < s1):
+                            continue
+                        for (ex, ey) in dirs:
+                            rr = c - ey
+                            assert 0 <= t - ex < win
+                            if lrow(rr) >= 0:
+                                assert l1[(rr - base) % ring] == rr, (rr, l1)
+                        pend.append((x, c))
+                        written[c, x] += 1
+        for (wx, wy) in pend:
+            for j in range(q):
+                gcheck(j, wx, wy)
+    assert np.all(seen == 1)
+    assert np.all(written == 1)          # every node stored exactly once
+    return checked
+
+
+SHAPES2 = [(3, 3), (5, 4), (3, 40), (124, 5), (125, 6), (126, 3), (252, 9),
+           (253, 17), (130, 70)]
+
+
+@pytest.mark.parametrize("q", [5, 9])
+def test_two_step_kernel_offsets_inside_planes(names, q):
+    t2 = [n for n in names[q] if "/t2" in n]
+    assert t2
+    for name in t2:
+        win, by, rows = _parse_t2(name)
+        for (nx, ny) in SHAPES2:
+            for px, py in ((False, False), (True, True), (False, True)):
+                for two in (True, False):
+                    assert replay_t2(q, nx, ny, win, by, rows, px, py,
+                                     two) > 0
+
+
+def test_two_step_replay_detects_a_short_ring():
+    """The replay itself: a ring of BY + 1 rows loses a row the second step
+    still needs."""
+    replay_t2(5, 40, 20, 128, 2, 16, False, False)
+    with pytest.raises(AssertionError):
+        replay_t2(5, 40, 20, 128, 2, 16, False, False, ring_rows=3)
