@@ -310,6 +310,39 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
 int lbm_stefan_destroy(lbm_stefan_t *h);
 
 /* ---------------------------------------------------------------------
+ * A step that allocates nothing, for callers that cannot allocate device
+ * memory or own a workspace: code under HIP graph capture, tight serving
+ * loops and harnesses that forbid hipMalloc.
+ *
+ * lbm_stefan_step_noalloc: one time step of the lattice described by p
+ * from the state src to dst, the same step lbm_stefan_step takes on a
+ * handle made from p whose state is src (bit for bit, in the one-step
+ * tiling of p->variant: a two-step variant's single step and the resident
+ * variant's step take the library defaults, as on a handle).
+ *   src, dst  device, distinct, q planes of the storage type each (the
+ *             layout of lbm_stefan_state_ptr), on the current device.
+ *   stats     host, nullable: the statistics of this one step (steps = 1;
+ *             energy of dst).  With stats (or p->strict) the call waits
+ *             for the stream; without, it only enqueues a fill kernel and
+ *             the step kernel on `stream`.
+ *   stream    hipStream_t (NULL: the null stream).
+ * The per-item statistics, energy partials and the result block live in
+ * a fixed device array of LBM_STEFAN_NOALLOC_SCRATCH_BYTES per device,
+ * held until the process ends; nothing is allocated.  Every call on a
+ * device shares that array (the call clears what it needs first), so
+ * calls that overlap on one device (several streams or threads) race;
+ * calls on one stream are ordered.
+ * Errors (text in lbm_stefan_last_error(NULL)): EINVAL (invalid params as
+ * for lbm_stefan_init, NULL or equal buffers, wall profiles, the ILFBM
+ * scheme, LBM_FLAG_ADJOINT, or a lattice whose statistics slots and
+ * energy partials exceed the fixed array), ENOTCONV (strict), ENAN (the
+ * energy of dst is not finite), EDEVICE.
+ */
+#define LBM_STEFAN_NOALLOC_SCRATCH_BYTES (16u << 20)
+int lbm_stefan_step_noalloc(const lbm_stefan_params *p, const void *src,
+                            void *dst, lbm_stefan_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------------
  * Reverse mode (handle created with LBM_FLAG_ADJOINT).  The reverse step
  * is the exact adjoint of the forward step of this library (Algorithm 3,
  * Section 4.1, with the closures of Section 4.2): the transposes of the

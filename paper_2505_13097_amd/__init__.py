@@ -9,7 +9,7 @@ built, using it raises LibraryMissing.
 """
 from ._lib import LbmError, LibraryMissing  # noqa: F401
 from .stefan import (HotWallFront, Stefan, StefanBatch, make_params,  # noqa: F401
-                     variant_names,
+                     step_noalloc, variant_names,
                      workspace_bytes)
 
 __version__ = "0.1.0"

@@ -80,6 +80,8 @@ SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_int32),
                                            _c_double_p]),
     "lbm_stefan_destroy": (ctypes.c_int, [_vp]),
+    "lbm_stefan_step_noalloc": (ctypes.c_int, [_P, _vp, _vp, ctypes.POINTER(Stats),
+                                                _vp]),
     "lbm_stefan_adjoint_reset": (ctypes.c_int, [_vp]),
     "lbm_stefan_front_vjp": (ctypes.c_int, [_vp, _vp, _c_double_p, _vp]),
     "lbm_stefan_adjoint_step": (ctypes.c_int, [_vp, _vp, _vp, _vp]),

@@ -80,6 +80,25 @@ def variant_names(q, storage="f32"):
     return [L.lbm_stefan_variant_name(q, s, v).decode() for v in range(n.value)]
 
 
+def step_noalloc(prob, src, dst, stats=False, variant=-1, strict=False,
+                 stream=None):
+    """One step of prob's lattice from the device state src to dst
+    (torch tensors of the state's bytes on the current device) through
+    lbm_stefan_step_noalloc: no workspace, nothing allocated.  With
+    stats=True waits and returns the step's statistics as a dict."""
+    p, keep = make_params(prob, variant, 0, strict)
+    st = C.Stats() if stats else None
+    s = torch.cuda.current_stream() if stream is None else stream
+    rc = C.lib().lbm_stefan_step_noalloc(
+        ctypes.byref(p), ctypes.c_void_p(src.data_ptr()),
+        ctypes.c_void_p(dst.data_ptr()),
+        ctypes.byref(st) if st is not None else None,
+        ctypes.c_void_p(s.cuda_stream))
+    del keep
+    C.check(rc)
+    return st.as_dict() if st is not None else None
+
+
 class Stefan:
     """One lattice on the current CUDA (HIP) device: D1Q3, D2Q5, D2Q9,
     D3Q7 or D3Q19, stepped by IREBM (Algorithm 3), EEBM (Algorithm 2) or

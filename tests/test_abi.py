@@ -294,3 +294,34 @@ def test_3d_variants_listed(L):
             tx, ty, npt, cz = (int(m.group(k)) for k in range(1, 5))
             bx = tx // npt
             assert bx % 64 == 0 and bx * ty <= 256 and cz >= 1, n
+
+
+def test_step_noalloc_refusals(L):
+    """lbm_stefan_step_noalloc refuses, before any device call, what it
+    cannot run in its fixed scratch: NULL or equal buffers, wall profiles,
+    ILFBM, the reverse mode, and lattices whose statistics slots and energy
+    partials exceed LBM_STEFAN_NOALLOC_SCRATCH_BYTES (the buffer pointers
+    are never dereferenced on these paths)."""
+    import numpy as np
+    lib = L.lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)
+
+    def call(prob, src=a, dst=b, **over):
+        p, keep = _params(L, prob, **over)
+        rc = lib.lbm_stefan_step_noalloc(ctypes.byref(p), src, dst, None, None)
+        return rc, lib.lbm_stefan_last_error(None).decode()
+
+    prob = synth.planar_2d(n=64, ny=32)
+    assert call(prob, src=None)[0] == L.EINVAL
+    assert call(prob, dst=a)[0] == L.EINVAL
+    assert call(prob, scheme=L.SCHEME_ILFBM)[0] == L.EINVAL
+    assert call(prob, flags=L.FLAG_ADJOINT)[0] == L.EINVAL
+    assert call(prob, tau=0.5)[0] == L.EINVAL
+    rc, msg = call(prob.with_(wall_profile=(np.ones(32), None, None, None)))
+    assert rc == L.EINVAL and "profile" in msg
+    # 8192 x 8192 D2Q9 fits (131072 slots of 32 B, 32768 partials); a
+    # 40000 x 40000 lattice needs 3.1 M slots, about 100 MB
+    rc, msg = call(synth.cavity_2d(n=40000))
+    assert rc == L.EINVAL and "fixed scratch" in msg
+    rc, msg = call(synth.cavity_3d(n=1024, ny=1024, nz=1536, q=7))
+    assert rc == L.EINVAL and "fixed scratch" in msg
