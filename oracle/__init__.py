@@ -15,6 +15,7 @@ directory are compiled with gcc into ``liboracle.so`` and called through
 ctypes below.  The state is the distribution functions f[i][y][x]
 (f[i][z][y][x] in 3D).
 """
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -33,13 +34,19 @@ _BC = {"dirichlet": DIRICHLET, "bounceback": BOUNCEBACK, "periodic": PERIODIC,
 _NEWTON = {"safeguarded": SAFEGUARDED, "plain": PLAIN}
 
 
+ALT_LIB_PATH = os.path.join(_HERE, "liboracle_alt.so")
+
+
 def build():
-    """Compile liboracle.so with gcc (plain -O2, single thread)."""
+    """Compile liboracle.so with gcc (plain -O2, single thread), and
+    liboracle_alt.so: the same sources with phi rounded another way (see
+    alternate_rounding)."""
     srcs = [os.path.join(_HERE, s) for s in SOURCES]
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o",
-           LIB_PATH + ".tmp"] + srcs + ["-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    for path, defs in ((LIB_PATH, []), (ALT_LIB_PATH, ["-DORC_PHI_LOGISTIC"])):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared"] + \
+            defs + ["-o", path + ".tmp"] + srcs + ["-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(path + ".tmp", path)
 
 
 class Params(ctypes.Structure):
@@ -75,71 +82,99 @@ class Stats(ctypes.Structure):
 
 
 _lib_handle = None
+_alt_handle = None
+_use_alt = False
+
+
+@contextlib.contextmanager
+def alternate_rounding():
+    """Inside the block every oracle call runs liboracle_alt.so: the same
+    scheme with tanh(z) evaluated as 2/(1 + exp(-2z)) - 1 (the other way of
+    writing phi), so that the spread between the two results measures how
+    strongly an input amplifies rounding.  Not thread-safe."""
+    global _use_alt
+    prev = _use_alt
+    _use_alt = True
+    try:
+        yield
+    finally:
+        _use_alt = prev
 
 
 def lib():
-    global _lib_handle
+    global _lib_handle, _alt_handle
+    if _use_alt:
+        if _alt_handle is None:
+            if not os.path.exists(ALT_LIB_PATH):
+                build()
+            _alt_handle = _load(ALT_LIB_PATH)
+        return _alt_handle
     if _lib_handle is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int)
-        P = ctypes.POINTER(Params)
-        S = ctypes.POINTER(Stats)
-        sig = {
-            "orc_lattice": [ctypes.c_int, ctypes.c_int, ip, ip, dp, ip],
-            "orc_newton": [ctypes.c_double] * 6 + [ctypes.c_int, ctypes.c_int,
-                                                   dp, ip, ip],
-            "orc_init": [P, dp, dp],
-            "orc_step": [P, dp, dp, S],
-            "orc_run": [P, dp, ctypes.c_long, S, dp, dp],
-            "orc_temperature": [P, dp, dp],
-            "orc_energy": [P, dp, dp],
-            "orc_front": [P, dp, ctypes.c_int, dp],
-            "orc_stefan_lambda": [ctypes.c_double, ctypes.c_double, dp],
-            "orc_front_loss": [P, dp, ctypes.c_long, dp, dp],
-            "orc_front_loss_grad": [P, dp, ctypes.c_long, dp, dp, dp, dp, dp],
-            "orc_adjoint_step": [P, dp, dp, dp, dp, dp, dp],
-            "orc_cs_step": [P, dp, dp, ctypes.c_double, ctypes.c_double, dp,
-                            dp, dp],
-            "orc_cs_front_loss": [P, dp, ctypes.c_long, dp, ctypes.c_double,
-                                  ctypes.c_double, dp, dp, dp],
-            "orc_eebm_init": [P, dp, dp],
-            "orc_eebm_step": [P, dp, dp, S],
-            "orc_eebm_run": [P, dp, ctypes.c_long, S, dp, dp],
-            "orc_eebm_temperature": [P, dp, dp],
-            "orc_eebm_energy": [P, dp, dp],
-            "orc_eebm_front": [P, dp, ctypes.c_int, dp],
-            "orc_eebm_collide": [P, dp, dp],
-            "orc_ilfbm_init": [P, dp, dp],
-            "orc_ilfbm_step": [P, dp, dp, S],
-            "orc_ilfbm_run": [P, dp, ctypes.c_long, S, dp, dp],
-            "orc_ilfbm_temperature": [P, dp, dp],
-            "orc_ilfbm_energy": [P, dp, dp],
-            "orc_ilfbm_front": [P, dp, ctypes.c_int, dp],
-            "orc_ilfbm_collide": [P, dp, dp],
-            "orc_lattice3": [ctypes.c_int, ip, ip, ip, dp, ip],
-            "orc3_init": [P, dp, dp],
-            "orc3_step": [P, dp, dp, S],
-            "orc3_run": [P, dp, ctypes.c_long, S, dp, dp],
-            "orc3_temperature": [P, dp, dp],
-            "orc3_energy": [P, dp, dp],
-            "orc3_front": [P, dp, ctypes.c_int, dp],
-            "orc3_collide": [P, dp, dp],
-        }
-        for name, args in sig.items():
-            fn = getattr(L, name)
-            fn.argtypes = args
-            fn.restype = ctypes.c_int
-        for name in ("orc_phi", "orc_dphi", "orc_eebm_theta"):
-            fn = getattr(L, name)
-            fn.argtypes = [ctypes.c_double] * 3
-            fn.restype = ctypes.c_double
-        L.orc_neumann_T.argtypes = [ctypes.c_double] * 4
-        L.orc_neumann_T.restype = ctypes.c_double
-        _lib_handle = L
+        _lib_handle = _load(LIB_PATH)
     return _lib_handle
+
+
+def _load(path):
+    """the library at path with the signatures of its entry points"""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    P = ctypes.POINTER(Params)
+    S = ctypes.POINTER(Stats)
+    sig = {
+        "orc_lattice": [ctypes.c_int, ctypes.c_int, ip, ip, dp, ip],
+        "orc_newton": [ctypes.c_double] * 6 + [ctypes.c_int, ctypes.c_int,
+                                               dp, ip, ip],
+        "orc_init": [P, dp, dp],
+        "orc_step": [P, dp, dp, S],
+        "orc_run": [P, dp, ctypes.c_long, S, dp, dp],
+        "orc_temperature": [P, dp, dp],
+        "orc_energy": [P, dp, dp],
+        "orc_front": [P, dp, ctypes.c_int, dp],
+        "orc_stefan_lambda": [ctypes.c_double, ctypes.c_double, dp],
+        "orc_front_loss": [P, dp, ctypes.c_long, dp, dp],
+        "orc_front_loss_grad": [P, dp, ctypes.c_long, dp, dp, dp, dp, dp],
+        "orc_adjoint_step": [P, dp, dp, dp, dp, dp, dp],
+        "orc_cs_step": [P, dp, dp, ctypes.c_double, ctypes.c_double, dp,
+                        dp, dp],
+        "orc_cs_front_loss": [P, dp, ctypes.c_long, dp, ctypes.c_double,
+                              ctypes.c_double, dp, dp, dp],
+        "orc_eebm_init": [P, dp, dp],
+        "orc_eebm_step": [P, dp, dp, S],
+        "orc_eebm_run": [P, dp, ctypes.c_long, S, dp, dp],
+        "orc_eebm_temperature": [P, dp, dp],
+        "orc_eebm_energy": [P, dp, dp],
+        "orc_eebm_front": [P, dp, ctypes.c_int, dp],
+        "orc_eebm_collide": [P, dp, dp],
+        "orc_ilfbm_init": [P, dp, dp],
+        "orc_ilfbm_step": [P, dp, dp, S],
+        "orc_ilfbm_run": [P, dp, ctypes.c_long, S, dp, dp],
+        "orc_ilfbm_temperature": [P, dp, dp],
+        "orc_ilfbm_energy": [P, dp, dp],
+        "orc_ilfbm_front": [P, dp, ctypes.c_int, dp],
+        "orc_ilfbm_collide": [P, dp, dp],
+        "orc_lattice3": [ctypes.c_int, ip, ip, ip, dp, ip],
+        "orc3_init": [P, dp, dp],
+        "orc3_step": [P, dp, dp, S],
+        "orc3_run": [P, dp, ctypes.c_long, S, dp, dp],
+        "orc3_temperature": [P, dp, dp],
+        "orc3_energy": [P, dp, dp],
+        "orc3_front": [P, dp, ctypes.c_int, dp],
+        "orc3_collide": [P, dp, dp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    for name in ("orc_phi", "orc_dphi", "orc_eebm_theta"):
+        fn = getattr(L, name)
+        fn.argtypes = [ctypes.c_double] * 3
+        fn.restype = ctypes.c_double
+    L.orc_neumann_T.argtypes = [ctypes.c_double] * 4
+    L.orc_neumann_T.restype = ctypes.c_double
+    return L
 
 
 def _dp(a):

@@ -13,7 +13,14 @@
 
 #define R double
 #define RN(name) r_##name
+#ifdef ORC_PHI_LOGISTIC
+/* A second rounding of the same function, tanh(z) = 2/(1 + exp(-2z)) - 1,
+   built into a separate library (liboracle_alt.so) only to measure how far
+   two correct FP64 evaluations of the scheme drift apart on an input. */
+#define TANH(z) (2.0 / (1.0 + exp(-2.0 * (z))) - 1.0)
+#else
 #define TANH(z) tanh(z)
+#endif
 #define RE(z) (z)
 #define CS 0
 #include "irebm_body.h"
