@@ -113,18 +113,45 @@ def measured_traffic3(workload, variant_name):
     return None if v is None else v.get("bytes_per_launch")
 
 
+# Kernel variants the bench times unless --autotune is given: the fastest
+# of the autotuner's sweeps on these lattices, fixed so that a run and the
+# committed rocprofv3 summaries name the same kernel.
+DEFAULT_VARIANTS = {
+    "cavity": "128x4/t2/r32/nt",
+    "cavity_eebm": "256x2/t2/r32/nt",
+    "planar": "256x4/npt4",
+    "planar_eebm": "256x4/npt4",
+    "stefan1d": "resident2048",
+    "batched": "128x4/npt2/r16/nt",
+    "adjoint": "256x1/npt1",
+    "cube3d_19": "256x1/npt2/z4/nt",
+    "cube3d_7": "256x1/npt2/z8/nt",
+}
+
+
+def variant_id(q, storage, name):
+    """index of a kernel variant by its name"""
+    from paper_2505_13097_amd import variant_names
+    names = variant_names(q, storage)
+    if name not in names:
+        raise SystemExit(f"no kernel variant {name} for q = {q}")
+    return names.index(name)
+
+
 def bytes_per_node(prob):
     s = 8 if prob.storage == "f64" else 4
     return 2 * prob.q * s
 
 
-def time_plain(prob, steps, warmup, variant=-1, autotune=True):
+def time_plain(prob, steps, warmup, variant=-1, autotune=False):
+    """W untimed steps, then K steps timed with HIP events on the stream
+    the kernels run on (torch's current stream, which the handle uses)."""
     import torch
     from paper_2505_13097_amd import Stefan
     g = Stefan(prob, variant=variant)
     stream = torch.cuda.current_stream()
     tuned = None
-    if autotune and variant < 0:
+    if autotune:
         v, ms = g.autotune(steps=10)
         tuned = {"variant": v, "ms_per_step": round(ms, 4)}
         variant = v
@@ -148,7 +175,7 @@ def time_plain(prob, steps, warmup, variant=-1, autotune=True):
             "tuned": tuned}
 
 
-def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
+def time_batched(probs, steps, warmup, autotune=False, graph_steps=100,
                  variant=-1, bpc=0):
     """The batched form: all instances advanced by one persistent launch
     per step, replayed from a captured hipGraph of graph_steps launches."""
@@ -157,6 +184,8 @@ def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
     b = StefanBatch(probs)
     tuned = None
     v = variant
+    if v < 0 and not autotune:
+        v = variant_id(probs[0].q, probs[0].storage, DEFAULT_VARIANTS["batched"])
     if autotune:
         v, bpc, ms = b.autotune(steps=3)
         tuned = {"variant": variant_names(probs[0].q, probs[0].storage)[v],
@@ -193,12 +222,16 @@ def time_batched(probs, steps, warmup, autotune=True, graph_steps=100,
     }
 
 
-def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1):
+def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1,
+              key=None):
     """The explicit enthalpy based method (Algorithm 2) on the same
     lattice, same kernels and state layout, no Newton solve; the paper's
     timing tables report the IREBM/EEBM time ratio."""
     from paper_2505_13097_amd import variant_names
     pe = prob.with_(scheme="eebm", name=prob.name + "_eebm")
+    dflt = DEFAULT_VARIANTS.get(f"{key}_eebm")
+    if variant < 0 and not autotune and dflt:
+        variant = variant_id(pe.q, pe.storage, dflt)
     r = time_plain(pe, steps, warmup, variant, autotune=autotune)
     v = r["variant"] if r["variant"] >= 0 else (0 if pe.q == 3 else 3)
     vname = variant_names(pe.q, pe.storage)[v]
@@ -217,7 +250,7 @@ def time_eebm(prob, steps, warmup, autotune, irebm_ms_per_step, variant=-1):
     }
 
 
-def time_planar(steps=10000, warmup=20, autotune=True):
+def time_planar(steps=10000, warmup=20, autotune=False):
     """The plain step on the 2048^2 planar-front lattice (D2Q5, FP32
     storage, 10,000 steps): both state buffers (2 x 84 MB) fit in the
     memory-side cache, so the algorithmic rate can exceed what HBM alone
@@ -230,7 +263,10 @@ def time_planar(steps=10000, warmup=20, autotune=True):
         prob = synth.planar_2d(nsteps=steps)
         if scheme == "eebm":
             prob = prob.with_(scheme="eebm", name=prob.name + "_eebm")
-        r = time_plain(prob, steps, warmup, -1, autotune=autotune)
+        v = -1 if autotune else variant_id(
+            prob.q, prob.storage,
+            DEFAULT_VARIANTS["planar" if scheme == "irebm" else "planar_eebm"])
+        r = time_plain(prob, steps, warmup, v, autotune=autotune)
         v = r["variant"] if r["variant"] >= 0 else 3
         vname = variant_names(prob.q, prob.storage)[v]
         spl = steps_per_launch(vname)
@@ -258,7 +294,7 @@ def time_planar(steps=10000, warmup=20, autotune=True):
 CUBE3D_N = 512
 
 
-def time_cube3d(steps=50, warmup=5, autotune=True, variant=-1, n=CUBE3D_N):
+def time_cube3d(steps=50, warmup=5, autotune=False, variant=-1, n=CUBE3D_N):
     """The 3D lattices (the enthalpy model holds in 3D, Section 2): the
     n^3 cube heated at one face (Dirichlet x faces, bounce-back y and z
     faces), D3Q19 and D3Q7, FP32 populations, IREBM and then EEBM on the
@@ -269,7 +305,10 @@ def time_cube3d(steps=50, warmup=5, autotune=True, variant=-1, n=CUBE3D_N):
     for q in (19, 7):
         p = S.cavity_3d(n=n, q=q)
         print(f"[bench] cube3d D3Q{q} {n}^3", file=sys.stderr, flush=True)
-        r = time_plain(p, steps, warmup, variant, autotune=autotune)
+        v = variant
+        if v < 0 and not autotune:
+            v = variant_id(q, p.storage, DEFAULT_VARIANTS[f"cube3d_{q}"])
+        r = time_plain(p, steps, warmup, v, autotune=autotune)
         v = r["variant"] if r["variant"] >= 0 else 0
         vname = variant_names(q, p.storage)[v]
         launch_ms = r["gpu_ms"] / steps
@@ -562,7 +601,7 @@ def time_freezing3d(sizes=(101, 201)):
             "unit": "s per run to 20 h", "runs": rows}
 
 
-def time_adjoint(prob, interval, autotune=True):
+def time_adjoint(prob, interval, autotune=False):
     """The reverse mode: forward run keeping a checkpoint tape, then the
     reverse sweep (segment recompute + reverse steps) giving dL/dT_wall
     (512 values), dL/dSte and dL/ddelta for L = 1/2 sum (xf - xf*)^2,
@@ -577,10 +616,12 @@ def time_adjoint(prob, interval, autotune=True):
     target = twin.front("integral")
     twin.close()
     s = Stefan(prob, flags=_lib.FLAG_ADJOINT)
-    tuned = None
     if autotune:
         v, ms = s.autotune(steps=20)
-        tuned = variant_names(prob.q, prob.storage)[v]
+    else:
+        v = variant_id(prob.q, prob.storage, DEFAULT_VARIANTS["adjoint"])
+        s.set_variant(v)
+    tuned = variant_names(prob.q, prob.storage)[v]
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
@@ -599,12 +640,28 @@ def time_adjoint(prob, interval, autotune=True):
     fwd_ms = ev[0].elapsed_time(ev[1])
     bwd_ms = ev[1].elapsed_time(ev[2])
     lups = prob.nodes * prob.nsteps
+    # algorithmic bytes per node-step of the reverse sweep: the reverse
+    # step reads the forward state (q s) and the adjoint arrays of the step
+    # after it (q + 1 FP64) and writes them for this step (q + 1 FP64);
+    # with checkpoints, the segment recompute adds one forward step (2 q s)
+    s_b = 8 if prob.storage == "f64" else 4
+    rev_b = prob.q * s_b + 2 * (prob.q + 1) * 8
+    bwd_b = rev_b + (2 * prob.q * s_b if interval > 1 else 0)
+    bwd_gbps = lups * bwd_b / (bwd_ms * 1e-3) / 1e9
+    fwd_gbps = lups * bytes_per_node(prob) / (fwd_ms * 1e-3) / 1e9
     return {
         "workload": prob.name, "steps": prob.nsteps,
         "checkpoint_interval": interval, "forward_variant": tuned,
         "value": round(lups / (bwd_ms * 1e-3) / 1e6, 1),
         "unit": "MLUPS (reverse sweep: recompute + reverse steps)",
         "forward_tape_mlups": round(lups / (fwd_ms * 1e-3) / 1e6, 1),
+        "bytes_per_node_step": bwd_b,
+        "hbm_gbps_algorithmic": round(bwd_gbps, 1),
+        "frac_of_peak": round(bwd_gbps / HBM_PEAK_GBPS, 4),
+        "forward_tape_gbps_algorithmic": round(fwd_gbps, 1),
+        "note": "both states and adjoint arrays (5.2 MB and 10.5 MB) sit in "
+                "the memory-side cache: launch latency, not HBM, bounds "
+                "this form",
         "total_s": round(t1 - t0, 4),
         "loss": float(0.5 * np.sum((xf - target) ** 2)),
         "grad_norms": {"wall": float(np.linalg.norm(walls["x-"])),
@@ -839,19 +896,116 @@ def summarize_profiles(run, args):
           f"{os.path.relpath(TRAFFIC_JSON, ROOT)}")
 
 
-def cpu_baseline(prob, steps=1):
+def cpu_baseline(prob, steps=1, threads=None):
     """The oracle, as it stands, on `steps` steps of the same lattice from
-    the same initial state (single thread)."""
+    the same initial state: once on one thread, then on every core this
+    process may use (at most 16), the lattice cut into row strips with
+    `steps` halo rows each, run side by side (the oracle's C code runs
+    outside the GIL).  The strips' own rows must equal the single-thread
+    result bit for bit."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle as O
+    model, ncores, nproc = host_cpu()
+    threads = min(16, ncores) if threads is None else threads
+    threads = max(1, min(threads, prob.ny // max(1, 2 * steps)))
     f = O.init(prob, prob.T0)
     t0 = time.perf_counter()
-    O.run(prob, f, steps)
-    dt = time.perf_counter() - t0
-    return {"value": prob.nodes * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": 1, "kind": "oracle",
+    f1, _ = O.run(prob, f, steps)
+    dt1 = time.perf_counter() - t0
+    T1 = O.temperature(prob, f1)
+    del f, f1
+    cuts = np.linspace(0, prob.ny, threads + 1).astype(int)
+
+    def strip(k):
+        sub, a = strip_problem(prob, cuts[k], cuts[k + 1], steps)
+        g, _ = O.run(sub, O.init(sub, sub.T0), steps)
+        T = O.temperature(sub, g)
+        return T[cuts[k] - a:cuts[k + 1] - a]
+
+    # the parallel leg times the steps and the strips' set-up alike
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(strip, range(threads)))
+    dtn = time.perf_counter() - t0
+    same = all(np.array_equal(parts[k], T1[cuts[k]:cuts[k + 1]])
+               for k in range(threads))
+    return {"value": round(prob.nodes * steps / dtn / 1e6, 2),
+            "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{steps} step(s) of the full {prob.nx}x{prob.ny} "
-                      f"{prob.name} lattice from its initial state, "
-                      f"single-threaded C oracle, {dt:.1f} s"}
+                      f"{prob.name} lattice from its initial state: "
+                      f"{threads} row strips ({steps} halo rows each) on "
+                      f"{threads} threads, {dtn:.1f} s; one thread on the "
+                      f"whole lattice {dt1:.1f} s",
+            "single_thread_mlups": round(prob.nodes * steps / dt1 / 1e6, 2),
+            "strips_equal_single_thread": bool(same),
+            "cpu_model": model, "nproc": nproc, "usable_cores": ncores}
+
+
+def copy_gbps(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (torch's copy kernel) on the current
+    stream, timed with HIP events: 2 nbytes per copy (read and write)."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
+def host_cpu():
+    """CPU model (lscpu) and the cores this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True,
+                             timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return model, len(os.sched_getaffinity(0)), os.cpu_count()
+
+
+def strip_problem(prob, y0, y1, halo):
+    """rows [y0, y1) of prob with `halo` rows around them as a lattice of
+    their own (cut sides bounce back; after k <= halo steps the own rows
+    equal those of the whole lattice)"""
+    import numpy as np
+    T0 = np.broadcast_to(-0.5 if prob.T0 is None else prob.T0,
+                         (prob.ny, prob.nx))
+    if prob.bc[2] == "periodic" and (y0 > 0 or y1 < prob.ny):
+        # the halo rows wrap around the periodic axis; both cut sides
+        # bounce back
+        a, b = y0 - halo, y1 + halo
+        rows = np.arange(a, b) % prob.ny
+        return prob.with_(ny=b - a, bc=prob.bc[:2] + ("bounceback",) * 2,
+                          T0=T0[rows], dx=prob.dx), a
+    a, b = max(0, y0 - halo), min(prob.ny, y1 + halo)
+    bc = (prob.bc[0], prob.bc[1],
+          prob.bc[2] if a == 0 else "bounceback",
+          prob.bc[3] if b == prob.ny else "bounceback")
+    return prob.with_(ny=b - a, bc=bc, T0=T0[a:b], dx=prob.dx), a
 
 
 def main():
@@ -863,13 +1017,16 @@ def main():
                     choices=["cavity", "planar", "stefan1d"])
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the autotuners pick the kernel variants "
+                         "(default: the fixed variants of DEFAULT_VARIANTS)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="the default; kept for older profile commands")
     ap.add_argument("--forms",
-                    default="plain,batched,adjoint,eebm,planar,freezing,"
-                            "paper1d,cube3d,freezing3d",
+                    default="batched,adjoint,eebm,planar,cube3d",
                     help="comma list of extra forms to time: batched, "
-                         "adjoint, eebm, planar, freezing, paper1d, cube3d, "
-                         "freezing3d")
+                         "adjoint, eebm, planar, cube3d; and the paper's "
+                         "experiments: freezing, paper1d, freezing3d")
     ap.add_argument("--cube3d-only", action="store_true",
                     help="time the 3D form alone (profile runs)")
     ap.add_argument("--cube3d-n", type=int, default=CUBE3D_N)
@@ -912,7 +1069,7 @@ def main():
     torch.cuda.set_device(0)
 
     if args.cube3d_only:
-        r = time_cube3d(args.steps3d, 5, not args.no_autotune,
+        r = time_cube3d(args.steps3d, 5, args.autotune,
                         args.variant3d, args.cube3d_n)
         print(json.dumps({"cube3d": r}), flush=True)
         return
@@ -946,8 +1103,11 @@ def main():
     print(f"[bench] workload {prob.name}: {prob.nx}x{prob.ny} D{prob.dim}Q{prob.q} "
           f"steps {args.steps} warmup {args.warmup}", file=sys.stderr,
           flush=True)
+    if args.variant < 0 and not args.autotune:
+        args.variant = variant_id(prob.q, prob.storage,
+                                  DEFAULT_VARIANTS[args.workload])
     r = time_plain(prob, args.steps, args.warmup, args.variant,
-                   autotune=not args.no_autotune)
+                   autotune=args.autotune)
     print(f"[bench] timed region done: {r['gpu_ms']:.1f} ms", file=sys.stderr,
           flush=True)
     ms_per_step = r["wall_s"] * 1e3 / args.steps
@@ -971,6 +1131,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
 
     out = {
         "metric": METRIC,
@@ -1018,6 +1179,16 @@ def main():
             "max_residual": r["stats"]["max_residual"],
         },
     }
+    traffic = out["roofline"]["traffic"]
+    if traffic:
+        # what HBM actually moved: the counter bytes of one launch of this
+        # variant over the same launch time (a two-step launch moves about
+        # half of its algorithmic bytes)
+        dram = traffic / (launch_ms * 1e-3) / 1e9
+        out["roofline"]["dram_gbps"] = round(dram, 1)
+        out["roofline"]["dram_frac"] = round(dram / HBM_PEAK_GBPS, 4)
+    print("[bench] copy kernel", file=sys.stderr, flush=True)
+    out["roofline"]["copy_kernel_gbps"] = copy_gbps()
     if resident:
         out["roofline"]["note"] = (
             "the state stays in LDS between steps: the rate is the "
@@ -1030,26 +1201,26 @@ def main():
               f"{args.batch_steps} steps", file=sys.stderr, flush=True)
         probs = S.batch_table(count=args.batch_count, nsteps=args.batch_steps)
         forms["batched"] = time_batched(
-            probs, args.batch_steps, 10, autotune=not args.no_autotune,
+            probs, args.batch_steps, 10, autotune=args.autotune,
             variant=args.batch_variant, bpc=args.batch_bpc)
         print("[bench] batched done", file=sys.stderr, flush=True)
     if "adjoint" in args.forms.split(","):
         import synth as S
         print("[bench] adjoint form", file=sys.stderr, flush=True)
         adj = S.adjoint_2d()
-        forms["adjoint"] = time_adjoint(adj, 64, not args.no_autotune)
+        forms["adjoint"] = time_adjoint(adj, 64, args.autotune)
         # every state kept (no recompute): 4097 states of 5.2 MB fit in HBM
-        forms["adjoint_all_states"] = time_adjoint(adj, 1, not args.no_autotune)
+        forms["adjoint_all_states"] = time_adjoint(adj, 1, args.autotune)
         print("[bench] adjoint done", file=sys.stderr, flush=True)
     if "eebm" in args.forms.split(","):
         print("[bench] eebm form", file=sys.stderr, flush=True)
         forms["eebm"] = time_eebm(prob, args.steps, args.warmup,
-                                  not args.no_autotune, ms_per_step,
-                                  variant=args.variant)
+                                  args.autotune, ms_per_step,
+                                  key=args.workload)
         print("[bench] eebm done", file=sys.stderr, flush=True)
     if "planar" in args.forms.split(","):
         print("[bench] planar form", file=sys.stderr, flush=True)
-        forms["planar"] = time_planar(autotune=not args.no_autotune)
+        forms["planar"] = time_planar(autotune=args.autotune)
         print("[bench] planar done", file=sys.stderr, flush=True)
     if "freezing" in args.forms.split(","):
         print("[bench] freezing form", file=sys.stderr, flush=True)
@@ -1066,14 +1237,14 @@ def main():
     if "cube3d" in args.forms.split(","):
         print("[bench] cube3d form", file=sys.stderr, flush=True)
         forms["cube3d"] = time_cube3d(
-            args.steps3d, 5, not args.no_autotune, args.variant3d,
+            args.steps3d, 5, args.autotune, args.variant3d,
             args.cube3d_n)
         print("[bench] cube3d done", file=sys.stderr, flush=True)
     if forms:
         out["forms"] = forms
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)...", file=sys.stderr, flush=True)
-        # about 10-30 s of single-threaded oracle work
+        # about 10-30 s of oracle work: one thread, then all usable cores
         out["cpu_baseline"] = cpu_baseline(prob, 3 if prob.nodes > 1e6 else 200)
     print(json.dumps(out), flush=True)
 

@@ -42,3 +42,27 @@ def test_bytes_per_lattice_update():
 def test_traffic_of_an_unmeasured_variant_is_null():
     assert bench.measured_traffic("cavity2d_d2q9_f32_8192x8192",
                                   "no/such/variant") is None
+
+
+def test_default_variants_exist():
+    """Every fixed variant the bench times is in the library's table of
+    its lattice (the names the profiles in profiles/ are taken under)."""
+    lattice = {"cavity": (9, "f32"), "cavity_eebm": (9, "f32"),
+               "planar": (5, "f32"), "planar_eebm": (5, "f32"),
+               "stefan1d": (3, "f64"), "batched": (5, "f32"),
+               "adjoint": (5, "f32"), "cube3d_19": (19, "f32"),
+               "cube3d_7": (7, "f32")}
+    assert set(lattice) == set(bench.DEFAULT_VARIANTS)
+    for key, name in bench.DEFAULT_VARIANTS.items():
+        q, s = lattice[key]
+        assert bench.variant_id(q, s, name) >= 0, key
+
+
+def test_cpu_baseline_strips_equal_single_thread():
+    """The multi-core oracle leg cuts the lattice into row strips with halo
+    rows; their own rows equal the single-thread run bit for bit."""
+    r = bench.cpu_baseline(synth.cavity_2d(n=96, ny=80), steps=3, threads=4)
+    assert r["strips_equal_single_thread"] is True
+    assert r["cores"] == 4 and r["kind"] == "oracle" and r["value"] > 0
+    r = bench.cpu_baseline(synth.planar_2d(n=64, ny=50), steps=5, threads=3)
+    assert r["strips_equal_single_thread"] is True

@@ -203,3 +203,60 @@ def test_batch_two_step_variants_equal_single_steps(name):
     a.close()
     ref.close()
 
+
+
+@pytest.mark.parametrize("schedule", ["bench", "autotune"])
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_full_table_of_512_instances_against_oracle(storage, schedule):
+    """The batched workload itself: the 512-instance table of the bench
+    (sizes 64^2 to 1024^2, about 2.1e8 nodes, a workspace above 8 GB in
+    FP32) in the bench's schedule (its fixed kernel variant, one block per
+    work item, hipGraph replays of two steps) or the autotuner's pick, six
+    steps; the 8 smallest and the 2 largest instances against the oracle
+    in full (T, both fronts, energy, Newton counters)."""
+    import bench
+    from paper_2505_13097_amd import StefanBatch, variant_names
+    probs = synth.batch_table(count=512, storage=storage)
+    nodes = np.array([p.nodes for p in probs])
+    order = np.argsort(nodes, kind="stable")
+    picks = list(order[:8]) + list(order[-2:])
+    b = StefanBatch(probs)
+    ws = b.workspace.numel()
+    names = variant_names(5, storage)
+    if schedule == "bench":
+        v, bpc = names.index(bench.DEFAULT_VARIANTS["batched"]), 0
+    else:
+        v, bpc, _ = b.autotune(steps=2)
+    b.set_schedule(v, bpc, 2)
+    print(f"batch512 {storage}: {nodes.sum()} nodes, workspace "
+          f"{ws / 2**30:.2f} GiB, variant {names[v]}, blocks per CU {bpc}",
+          flush=True)
+    assert ws > (8 if storage == "f32" else 16) * 10**9 * 0.95
+    steps = 6
+    b.step(steps)
+    st = b.stats()
+    tol = 1e-12 if storage == "f64" else 1e-5
+    worst = 0.0
+    for k in picks:
+        p = probs[k]
+        f, ost = O.run(p, O.init(p, p.T0), steps)
+        To = O.temperature(p, f)
+        T = b.temperature(k)
+        err = np.abs(T - To).max()
+        worst = max(worst, err)
+        assert err <= tol * max(1.0, np.abs(To).max()), (k, p.nx, err)
+        cr = np.abs(b.front(k, "crossing") - O.front(p, f, O.FRONT_CROSSING))
+        fr = np.abs(b.front(k, "integral") - O.front(p, f, O.FRONT_INTEGRAL))
+        assert cr.max() <= (1e-12 if storage == "f64" else p.dx)
+        assert fr.max() <= tol * p.nx * p.dx / p.delta + 1e-13
+        E = O.energy(p, f)
+        assert abs(b.energy(k) - E) <= (1e-11 if storage == "f64" else 1e-5
+                                        ) * max(1.0, abs(E))
+        assert st[k]["nonconverged"] == 0 and ost["nonconverged"] == 0
+        # FP32 states round the temperatures the solves start from
+        assert abs(st[k]["max_newton_it"] - ost["max_it"]) <= \
+            (1 if storage == "f64" else 2)
+    print(f"batch512 {storage} [{names[v]}]: instances {picks} "
+          f"(sizes {[probs[k].nx for k in picks]}), max|dT| {worst:.3e}",
+          flush=True)
+    b.close()
