@@ -108,14 +108,25 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
                                          y, L[k], st);
   } else {
     // boundary tiles: one node at a time keeps the register count of the
-    // interior path; the loads of a node are still issued together
+    // interior path; the loads of a node are still issued together.  At
+    // the x = 0 wall (where the workloads heat, so where their melting
+    // front starts) the first bx columns of the tile are dealt out column
+    // by column: the by nodes of a column side by side in a wave, 64 / by
+    // columns per wave.  The front then falls into the first wave of the
+    // tile instead of into one wave per row, so by times fewer waves run
+    // the Newton solve of the nodes in and near the band.  Other nodes
+    // keep one row per wave (whole-row loads).  (by is a power of two.)
+    const int tid = (int)threadIdx.x + (int)threadIdx.y * bx;
+    const int lb = __builtin_ctz((unsigned)by);
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      const int x = x0 + (int)threadIdx.x + k * bx;
-      if (x < A.nx && y < A.ny) {
+      const bool cm = k == 0 && x0 == 0;
+      const int x = cm ? (tid >> lb) : x0 + (int)threadIdx.x + k * bx;
+      const int yj = cm ? y0 + (tid & (by - 1)) : y;
+      if (x < A.nx && yj < A.ny) {
         NodeLoad<Q, S> L;
-        load_node<Q, S, false, neumann_mode(MODE)>(A, src, x, y, L);
-        update_node<Q, S, MODE, false, NT>(A, dst, x, y, L, st);
+        load_node<Q, S, false, neumann_mode(MODE)>(A, src, x, yj, L);
+        update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, st);
       }
     }
   }
