@@ -802,7 +802,7 @@ def summarize_profiles(run, args):
 
     trace_cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof_all -o all"
                  f" -- python bench.py --steps {args.steps} --warmup 5 --variant {V}"
-                 f" --no-autotune --no-cpu-baseline --forms plain,batched,adjoint,eebm"
+                 f" --no-cpu-baseline --forms batched,adjoint,eebm"
                  f" --batch-steps {args.batch_steps}"
                  f" --batch-variant {BV} --batch-bpc {BB}")
     pmc_cmd = ("rocprofv3 --pmc {C} -d gpurun_out/{D} -o {O} -- python bench.py"
@@ -855,9 +855,10 @@ def summarize_profiles(run, args):
             f.write("\n".join([
                 f"# {eebm_k[0]} — {prob.nx} x {prob.ny} D2Q{prob.q} "
                 f"{args.workload}, explicit scheme (Algorithm 2), FP32 "
-                f"populations (variant {vname})", "",
+                f"populations (variant "
+                f"{DEFAULT_VARIANTS.get(args.workload + '_eebm', vname)})", "",
                 f"Same kernel trace as {fn} (the bench's eebm form, same "
-                "variant, same step count).", "",
+                "step count).", "",
                 f"The {launches} timed launches ({spl} step(s) each) average "
                 f"{eebm_avg:.1f} us, against {cav:.1f} us for the IREBM "
                 f"kernel (time ratio IREBM/EEBM {cav / eebm_avg:.3f}); "
@@ -894,6 +895,62 @@ def summarize_profiles(run, args):
                    "source": "profiles/" + fn}, f, indent=1)
     print(f"wrote profiles/{fn}, batch and adjoint summaries, "
           f"{os.path.relpath(TRAFFIC_JSON, ROOT)}")
+    if os.path.isdir(os.path.join(run, "pmc_sq")):
+        summarize_sq(run, args, db, short)
+
+
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+               "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES")
+
+
+def summarize_sq(run, args, db, short):
+    """profiles/ summary of the SQ counter run (run/pmc_sq, bench
+    --traffic-sweep): instructions and wave cycles per dispatch of the
+    batched kernel in IREBM and EEBM, and of the timed cavity kernel."""
+    import collections
+    from paper_2505_13097_amd import variant_names
+    rows = db("pmc_sq").execute(
+        "select dispatch_id, kernel_name, counter_name, value from "
+        "counters_collection order by dispatch_id").fetchall()
+    per = collections.OrderedDict()
+    for d, k, cn, v in rows:
+        per.setdefault((d, short(k)), {})[cn] = v
+    bnames = variant_names(5, "f32")
+    kinds = [("batched IREBM", "batch_step_kernel<5, float, 2, 0,"),
+             ("batched EEBM", "batch_step_kernel<5, float, 2, 2,")]
+    lines = ["# SQ counters — batched form (512 D2Q5 instances, FP32, variant "
+             f"{bnames[args.batch_variant]}) in IREBM and EEBM", "",
+             "    rocprofv3 --pmc " + " ".join(SQ_COUNTERS) +
+             " -d gpurun_out/pmc_sq -o sq -- python bench.py --traffic-sweep"
+             f" --batch-steps 4 --batch-variant {args.batch_variant}"
+             f" --batch-bpc {args.batch_bpc}", "",
+             "Averages per dispatch (the sweep's 4 steps of each).", "",
+             "| kernel | dispatches | " + " | ".join(SQ_COUNTERS) +
+             " | VALU per wave | wave cycles per wave |",
+             "|---|---|" + "---|" * (len(SQ_COUNTERS) + 2)]
+    avg = {}
+    for label, pre in kinds:
+        ds = [c for (d, k), c in per.items() if k.startswith(pre)]
+        if not ds:
+            continue
+        a = {cn: sum(c.get(cn, 0.0) for c in ds) / len(ds)
+             for cn in SQ_COUNTERS}
+        avg[label] = a
+        lines.append(f"| {label} | {len(ds)} | " +
+                     " | ".join(f"{a[cn]:.4g}" for cn in SQ_COUNTERS) +
+                     f" | {a['SQ_INSTS_VALU'] / max(a['SQ_WAVES'], 1):.1f} |"
+                     f" {a['SQ_WAVE_CYCLES'] / max(a['SQ_WAVES'], 1):.0f} |")
+    if len(avg) == 2:
+        i, e = avg["batched IREBM"], avg["batched EEBM"]
+        lines += ["", f"IREBM / EEBM: VALU instructions "
+                  f"{i['SQ_INSTS_VALU'] / e['SQ_INSTS_VALU']:.2f}x, wave cycles "
+                  f"{i['SQ_WAVE_CYCLES'] / e['SQ_WAVE_CYCLES']:.2f}x, busy "
+                  f"cycles {i['SQ_BUSY_CYCLES'] / e['SQ_BUSY_CYCLES']:.2f}x."]
+    lines.append("")
+    fn = "batch_step_kernel_sq_counters_batch512_d2q5_f32.md"
+    with open(os.path.join(ROOT, "profiles", fn), "w") as f:
+        f.write("\n".join(lines))
+    print(f"wrote profiles/{fn}")
 
 
 def cpu_baseline(prob, steps=1, threads=None):
@@ -1094,9 +1151,12 @@ def main():
         names = traffic_sweep(prob)
         import synth as S
         probs = S.batch_table(count=args.batch_count, nsteps=args.batch_steps)
-        time_batched(probs, args.batch_steps, 0, autotune=False,
-                     graph_steps=0, variant=args.batch_variant,
-                     bpc=args.batch_bpc)
+        # the batched form in IREBM, then in EEBM (instruction counts of the
+        # Newton path against the no-Newton scheme in the SQ counter runs)
+        for pr in (probs, [p.with_(scheme="eebm") for p in probs]):
+            time_batched(pr, args.batch_steps, 0, autotune=False,
+                         graph_steps=0, variant=args.batch_variant,
+                         bpc=args.batch_bpc)
         print(json.dumps({"traffic_sweep": prob.name, "variants": names,
                           "steps_each": SWEEP_STEPS}), flush=True)
         return
