@@ -12,8 +12,13 @@
 // the single-lattice step (step_item), so a batch member evolves exactly
 // as the same lattice run alone, IREBM or EEBM alike.  Steps can be
 // captured in a hipGraph; the autotuner picks the tile variant and the
-// grid size.  This unit is the host side; the kernels and their launches
-// are in launch.hpp (instantiated by k_batch_<mode>.hip).
+// grid size.  Under a split two-step variant (tb = 2, IREBM) a launch of
+// two steps is four kernels: the front strips (strip 0 of each instance
+// heated at x = 0) by two column-limited one-step passes through a third
+// state, the quiet pass over the other items, and the full pass over the
+// items the quiet pass flagged (see batch_step2_kernel).  This unit is the
+// host side; the kernels and their launches are in launch.hpp
+// (instantiated by k_batch_<mode>.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,13 +41,23 @@ struct lbm_stefan_batch {
   int mode = kSafeguarded;  // node-update mode shared by the instances
   int device = 0, cus = 0;
   hipStream_t stream = nullptr, cap_stream = nullptr;
+  // split schedule: the front passes run on a stream of their own, forked
+  // from and joined back into the launching stream by two events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   char *ws = nullptr;
   StepArgs *descs = nullptr;
   int2 *items = nullptr;
   StatSlot *slots = nullptr;
+  int *flags = nullptr;        // split schedule: one flag per work item
+  StepArgs *fdescs = nullptr;  // split schedule: front pass descriptors
+  int2 *fitems = nullptr;      // split schedule: front pass work items
   double *profs = nullptr, *partials = nullptr, *small = nullptr;
   char *state[2] = {nullptr, nullptr};
+  char *mid = nullptr;         // split schedule: step n + 1 of the fronts
   size_t state_bytes = 0;
+  bool split_ok = false;       // a split two-step schedule can run
+  int64_t nslots = 0, nfitems = 0;
   std::vector<size_t> off;          // instance offset in a state region
   std::vector<size_t> prof_off;     // instance offset in the profiles
   std::vector<int64_t> first_item, nitems_inst;
@@ -57,11 +72,50 @@ struct lbm_stefan_batch {
 namespace {
 
 struct BLayout {
-  size_t descs, items, slots, profs, partials, small, stateA, stateB, total;
+  size_t descs, items, slots, flags, fdescs, fitems, profs, partials, small,
+      stateA, stateB, mid, total;
   size_t state_bytes;
-  int64_t max_items, max_parts, small_len;
+  int64_t max_items, max_fitems, nslots, max_parts, small_len;
+  bool split_ok;
   std::vector<size_t> off, prof_off;
 };
+
+// a split two-step schedule needs Newton solves to split off (not EEBM)
+// and 2D lattices
+bool split_applies(const lbm_stefan_params &p) {
+  return p.q != 3 && p.scheme != LBM_SCHEME_EEBM;
+}
+
+// instances whose strip 0 runs the front pass: heated through a Dirichlet
+// wall at x = 0 (a profile, or a temperature not on phi's lower plateau)
+bool front_strip(const lbm_stefan_params &p) {
+  return p.bc[0] == LBM_BC_DIRICHLET &&
+         (p.wall_profile[0] || p.wall_T[0] >= p.t_m - 20.0 * p.delta);
+}
+
+// front pass items of an nx x ny lattice whose front strip is w columns
+// wide: the one-step tiling fv over columns [0, min(w + 1, nx))
+int64_t front_tiles_x(const Variant &fv, int64_t nx, int w) {
+  return tiles_x_for(fv, std::min<int64_t>(w + 1, nx));
+}
+int64_t front_items(const Variant &fv, int64_t nx, int64_t ny, int w) {
+  return front_tiles_x(fv, nx, w) *
+         ((tiles_y_for(fv, ny) + fv.rows - 1) / fv.rows);
+}
+
+// columns of the front strip of an instance under two-step variant v: the
+// whole lattice when it fits one strip, else the first kFrontColumns
+int front_cols(const Variant &v, int64_t nx) {
+  return nx <= v.bx - 4 ? (int)nx : kFrontColumns;
+}
+
+// two-step work items of an instance with a front strip: strips shifted
+// by (bx - 4) - front_cols columns, so one more strip column at most
+int64_t shifted_items(const Variant &v, int64_t nx, int64_t ny) {
+  const int64_t w = v.bx - 4;
+  return ((nx + w - front_cols(v, nx) + w - 1) / w) *
+         ((ny + v.rows - 1) / v.rows);
+}
 
 int bfail(lbm_stefan_batch_t *b, int code, const std::string &msg) {
   if (b) b->err = msg;
@@ -106,11 +160,26 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   int nv;
   const Variant *v = variants(ps[0].q, &nv);
   L.max_items = 0;
+  L.split_ok = split_applies(ps[0]);
   for (int i = 0; i < nv; ++i) {
     int64_t t = 0;
-    for (int k = 0; k < count; ++k) t += items_for(v[i], ps[k].nx, ps[k].ny);
+    for (int k = 0; k < count; ++k)
+      t += v[i].tb == 2 && L.split_ok && front_strip(ps[k])
+               ? shifted_items(v[i], ps[k].nx, ps[k].ny)
+               : items_for(v[i], ps[k].nx, ps[k].ny);
     L.max_items = std::max(L.max_items, t);
   }
+  L.max_fitems = 0;
+  for (int i = 0; i < nv && L.split_ok; ++i) {
+    if (v[i].tb != 2) continue;
+    int64_t t = 0;
+    for (int k = 0; k < count; ++k)
+      if (front_strip(ps[k]))
+        t += front_items(v[kFrontVariant2D], ps[k].nx, ps[k].ny,
+                         front_cols(v[i], ps[k].nx));
+    L.max_fitems = std::max(L.max_fitems, t);
+  }
+  L.nslots = L.max_items + 2 * L.max_fitems;
   L.state_bytes = 0;
   L.off.resize(count);
   L.prof_off.resize(count);
@@ -133,7 +202,13 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   L.items = o;
   o += align256(L.max_items * sizeof(int2));
   L.slots = o;
-  o += align256(L.max_items * sizeof(StatSlot));
+  o += align256(L.nslots * sizeof(StatSlot));
+  L.flags = o;
+  o += L.split_ok ? align256(L.max_items * sizeof(int)) : 0;
+  L.fdescs = o;
+  o += L.split_ok ? align256(4 * (size_t)count * sizeof(StepArgs)) : 0;
+  L.fitems = o;
+  o += align256(L.max_fitems * sizeof(int2));
   L.profs = o;
   o += align256(prof_total * 8);
   L.partials = o;
@@ -144,8 +219,18 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   o += L.state_bytes;
   L.stateB = o;
   o += L.state_bytes;
+  L.mid = o;
+  o += L.split_ok ? L.state_bytes : 0;
   L.total = o;
   return L;
+}
+
+void drop_side(lbm_stefan_batch_t *b) {
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  b->fork = b->join = nullptr;
+  b->side = nullptr;
 }
 
 void drop_graphs(lbm_stefan_batch_t *b) {
@@ -157,15 +242,22 @@ void drop_graphs(lbm_stefan_batch_t *b) {
 }
 
 // descriptors and item table for the current variant; uploads both and
-// zeroes the statistics (the item -> slot map changes with the items)
+// zeroes the statistics (the item -> slot map changes with the items).
+// The statistics slots of instance k are contiguous: its work items, then
+// (split schedule) its items of the two front passes.
 int build_schedule(lbm_stefan_batch_t *b) {
   int nv;
-  const Variant &v = variants(b->q, &nv)[b->variant];
-  std::vector<StepArgs> d(b->count);
-  std::vector<int2> t;
+  const Variant *vt = variants(b->q, &nv);
+  const Variant &v = vt[b->variant];
+  const Variant &fv = vt[kFrontVariant2D];
+  const bool split = v.tb == 2 && b->split_ok;
+  std::vector<StepArgs> d(b->count), fd(split ? 4 * (size_t)b->count : 0);
+  std::vector<int2> t, ft;
+  std::vector<int> fl;
   t.reserve(b->max_items);
   b->first_item.assign(b->count, 0);
   b->nitems_inst.assign(b->count, 0);
+  int64_t sbase = 0;
   for (int k = 0; k < b->count; ++k) {
     const lbm_stefan_params &p = b->ps[k];
     double *prof[4];
@@ -176,30 +268,89 @@ int build_schedule(lbm_stefan_batch_t *b) {
     fill_args(p, prof, &d[k]);
     d[k].src = b->state[0] + b->off[k];
     d[k].dst = b->state[1] + b->off[k];
+    StepArgs base = d[k];
     set_tiling(&d[k], v);
+    const bool front = split && front_strip(p);
+    const int w = split ? front_cols(v, p.nx) : 0;  // front strip columns
+    if (front) {
+      // strip 0 narrowed to the front strip's w columns
+      d[k].x_shift = v.bx - 4 - w;
+      d[k].tiles_x = (int32_t)((p.nx + d[k].x_shift + v.bx - 5) / (v.bx - 4));
+      d[k].nitems = (int32_t)shifted_items(v, p.nx, p.ny);
+      d[k].per_xcd = (d[k].nitems + 7) / 8;
+    }
     const int64_t nt = d[k].nitems;
-    d[k].slots = b->slots + t.size();
-    b->first_item[k] = (int64_t)t.size();
-    b->nitems_inst[k] = nt;
-    for (int64_t i = 0; i < nt; ++i) t.push_back(make_int2(k, (int)i));
+    d[k].slots = b->slots + sbase;
+    b->first_item[k] = sbase;
+    for (int64_t i = 0; i < nt; ++i) {
+      t.push_back(make_int2(k, (int)i));
+      if (split) fl.push_back(front && i % d[k].tiles_x == 0 ? 1 : 0);
+    }
+    int64_t nf = 0;
+    if (split) {
+      // pass 1: step n + 1 on columns [0, w + 1) into mid (columns below w
+      // counted); pass 2: step n + 2 on columns [0, w) from mid
+      set_tiling(&base, fv);
+      base.tiles_x = (int32_t)front_tiles_x(fv, p.nx, w);
+      base.nitems = (int32_t)front_items(fv, p.nx, p.ny, w);
+      base.per_xcd = (base.nitems + 7) / 8;
+      nf = front ? base.nitems : 0;
+      const int32_t lim1 = (int32_t)std::min<int64_t>(w + 1, p.nx);
+      const int32_t lim2 = (int32_t)std::min<int64_t>(w, p.nx);
+      char *mid = b->mid + b->off[k];
+      for (int par = 0; par < 2; ++par) {
+        StepArgs &f1 = fd[(size_t)par * b->count + k];
+        StepArgs &f2 = fd[(size_t)(2 + par) * b->count + k];
+        f1 = f2 = base;
+        f1.src = b->state[par] + b->off[k];
+        f1.dst = mid;
+        f1.x_lim = lim1;
+        f1.x_cnt = lim2;
+        f1.slots = b->slots + sbase + nt;
+        f2.src = mid;
+        f2.dst = b->state[par ^ 1] + b->off[k];
+        f2.x_lim = f2.x_cnt = lim2;
+        f2.slots = b->slots + sbase + nt + nf;
+      }
+      for (int64_t i = 0; i < nf; ++i) ft.push_back(make_int2(k, (int)i));
+    }
+    b->nitems_inst[k] = nt + 2 * nf;
+    sbase += nt + 2 * nf;
   }
   b->nitems = (int64_t)t.size();
+  b->nfitems = (int64_t)ft.size();
   BCHK(b, hipMemcpyAsync(b->descs, d.data(), d.size() * sizeof(StepArgs),
                          hipMemcpyHostToDevice, b->stream));
   BCHK(b, hipMemcpyAsync(b->items, t.data(), t.size() * sizeof(int2),
                          hipMemcpyHostToDevice, b->stream));
-  BCHK(b, zero_async(b->slots, b->max_items * sizeof(StatSlot), b->stream));
+  if (split) {
+    BCHK(b, hipMemcpyAsync(b->flags, fl.data(), fl.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipMemcpyAsync(b->fdescs, fd.data(), fd.size() * sizeof(StepArgs),
+                           hipMemcpyHostToDevice, b->stream));
+    if (!ft.empty())
+      BCHK(b, hipMemcpyAsync(b->fitems, ft.data(), ft.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, b->stream));
+  }
+  BCHK(b, zero_async(b->slots, b->nslots * sizeof(StatSlot), b->stream));
+  if (split && !b->side) {
+    BCHK(b, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    BCHK(b, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    BCHK(b, hipEventCreateWithFlags(&b->join, hipEventDisableTiming));
+  }
   BCHK(b, hipStreamSynchronize(b->stream));
   drop_graphs(b);
   return LBM_STEFAN_OK;
 }
 
 // one launch from buffer `parity`: one step, or two under a two-step
-// variant (one if two = false)
+// variant (one if two = false); two steps of a split schedule are the
+// front passes, the quiet pass and the full pass over flagged items
 hipError_t launch_batch(const lbm_stefan_batch_t *b, hipStream_t stream,
                         int parity, bool two = true) {
   int nv;
-  const Variant &v = variants(b->q, &nv)[b->variant];
+  const Variant *vt = variants(b->q, &nv);
+  const Variant &v = vt[b->variant];
   BatchLaunch L;
   L.descs = b->descs;
   L.items = b->items;
@@ -208,6 +359,38 @@ hipError_t launch_batch(const lbm_stefan_batch_t *b, hipStream_t stream,
   L.blocks_per_cu = b->blocks_per_cu;
   L.parity = parity;
   L.two = two;
+  if (!(v.tb == 2 && b->split_ok && two))
+    return batch_launch(b->mode, b->q, b->storage, L, v, stream);
+  // the front passes (F1 then F2, latency-bound) on the side stream, the
+  // quiet pass (bandwidth-bound) beside them; the full pass over flagged
+  // items after both
+  const bool fr = b->nfitems > 0;
+  if (fr) {
+    hipError_t e = hipEventRecord(b->fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->fork, 0);
+    if (e != hipSuccess) return e;
+    BatchLaunch F;
+    F.items = b->fitems;
+    F.nitems = b->nfitems;
+    F.cus = b->cus;
+    F.blocks_per_cu = 0;
+    F.parity = 0;  // the descriptors of each parity name src and dst
+    F.two = false;
+    F.lim = true;
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      F.descs = b->fdescs + (size_t)(2 * pass + parity) * b->count;
+      e = batch_launch(b->mode, b->q, b->storage, F, vt[kFrontVariant2D],
+                       b->side);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->join, b->side);
+    if (e != hipSuccess) return e;
+  }
+  L.flags = b->flags;
+  L.split = 1;
+  hipError_t e = batch_launch(b->mode, b->q, b->storage, L, v, stream);
+  if (e == hipSuccess && fr) e = hipStreamWaitEvent(stream, b->join, 0);
+  if (e != hipSuccess) return e;
+  L.split = 2;
   return batch_launch(b->mode, b->q, b->storage, L, v, stream);
 }
 
@@ -281,6 +464,7 @@ int lbm_stefan_batch_init(const lbm_stefan_params *ps, int32_t count,
   auto bail = [&](int code) {
     set_global_error(b->err);
     drop_graphs(b);
+    drop_side(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return code;
@@ -301,6 +485,14 @@ int lbm_stefan_batch_init(const lbm_stefan_params *ps, int32_t count,
   b->descs = (StepArgs *)(ws + L.descs);
   b->items = (int2 *)(ws + L.items);
   b->slots = (StatSlot *)(ws + L.slots);
+  b->split_ok = L.split_ok;
+  b->nslots = L.nslots;
+  if (L.split_ok) {
+    b->flags = (int *)(ws + L.flags);
+    b->fdescs = (StepArgs *)(ws + L.fdescs);
+    b->fitems = (int2 *)(ws + L.fitems);
+    b->mid = ws + L.mid;
+  }
   b->profs = (double *)(ws + L.profs);
   b->partials = (double *)(ws + L.partials);
   b->small = (double *)(ws + L.small);
@@ -410,7 +602,7 @@ int lbm_stefan_batch_step(lbm_stefan_batch_t *b, int64_t nsteps) {
 int lbm_stefan_batch_reset_stats(lbm_stefan_batch_t *b) {
   if (!b) return bfail(nullptr, LBM_STEFAN_EINVAL, "batch is NULL");
   DeviceGuard g(b->device);
-  BCHK(b, zero_async(b->slots, b->max_items * sizeof(StatSlot), b->stream));
+  BCHK(b, zero_async(b->slots, b->nslots * sizeof(StatSlot), b->stream));
   return LBM_STEFAN_OK;
 }
 
@@ -584,7 +776,7 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
     rc = build_schedule(b);
     if (rc) return rc;
   } else {
-    BCHK(b, zero_async(b->slots, b->max_items * sizeof(StatSlot), b->stream));
+    BCHK(b, zero_async(b->slots, b->nslots * sizeof(StatSlot), b->stream));
   }
   drop_graphs(b);
   BCHK(b, hipStreamSynchronize(b->stream));
@@ -597,8 +789,10 @@ int lbm_stefan_batch_autotune(lbm_stefan_batch_t *b, void *scratch,
 int lbm_stefan_batch_destroy(lbm_stefan_batch_t *b) {
   if (!b) return LBM_STEFAN_OK;
   DeviceGuard g(b->device);
-  const hipError_t e = hipStreamSynchronize(b->stream);
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess && b->side) e = hipStreamSynchronize(b->side);
   drop_graphs(b);
+  drop_side(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
   if (e != hipSuccess) return bfail(nullptr, LBM_STEFAN_EDEVICE, hipGetErrorString(e));

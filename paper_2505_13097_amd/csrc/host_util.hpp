@@ -22,7 +22,9 @@ namespace irebm {
 // (bx - 4 written), by rows per pass, `rows` rows per block, non-temporal
 // stores.  res: D1Q3 lattices of at most kResident1D nodes run many steps
 // per launch in one workgroup (resident1d_kernel); others take the default
-// one-step tiling.
+// one-step tiling.  tb = 2: the same two-step kernel, run in the batched
+// form with the front split (batch_step2_kernel: quiet pass, front strips,
+// full pass over flagged items); single lattices run it as tb = 1.
 struct Variant {
   int bx, by, npt, nt, rev, rows, tb, res;
 };
@@ -43,7 +45,11 @@ inline const Variant *variants(int q, int *n) {
       {256, 2, 1, 1, 0, 32, 1},  {256, 2, 1, 1, 0, 64, 1},
       {128, 2, 1, 1, 0, 16, 1},  {128, 2, 1, 1, 0, 24, 1},
       {128, 2, 1, 1, 0, 32, 1},  {128, 2, 1, 1, 0, 64, 1},
-      {128, 4, 1, 1, 0, 32, 1},  {128, 4, 1, 1, 0, 64, 1}};
+      {128, 4, 1, 1, 0, 32, 1},  {128, 4, 1, 1, 0, 64, 1},
+      {128, 2, 1, 1, 0, 16, 2},  {128, 2, 1, 1, 0, 24, 2},
+      {128, 2, 1, 1, 0, 32, 2},  {128, 2, 1, 1, 0, 64, 2},
+      {128, 4, 1, 1, 0, 32, 2},  {128, 2, 1, 1, 0, 96, 2},
+      {128, 2, 1, 1, 0, 128, 2}};
   if (q == 3) {
     *n = (int)(sizeof(v1) / sizeof(Variant));
     return v1;
@@ -54,6 +60,12 @@ inline const Variant *variants(int q, int *n) {
 constexpr int kDefaultVariant1D = 0;
 constexpr int kResidentVariant1D = 4;
 constexpr int kDefaultVariant2D = 3;
+// split two-step schedule: the front strip of an instance heated at x = 0
+// is its first kFrontColumns columns, advanced by the one-step variant
+// kFrontVariant2D (64 x 4 tiles, one node per thread, 4 tile rows per
+// block, non-temporal stores)
+constexpr int kFrontVariant2D = 16;
+constexpr int kFrontColumns = 60;
 
 inline int64_t tiles_x_for(const Variant &v, int64_t nx) {
   const int64_t tw = (int64_t)v.bx * v.npt;

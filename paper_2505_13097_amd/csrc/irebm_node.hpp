@@ -101,6 +101,9 @@ struct StepArgs {
   const void *src;      // current state planes
   void *dst;            // next state planes
   int32_t nx, ny;
+  int32_t x_lim, x_cnt; // kernels built with LIM (the batched two-step
+                        // front pass): columns x < x_lim are computed, and
+                        // those with x < x_cnt counted in the statistics
   int64_t plane;        // nx * ny
   int32_t tiles_x, tiles_y;  // tile grid
   int32_t group;             // tile rows per work item (one block each)
@@ -109,6 +112,8 @@ struct StepArgs {
   int32_t periodic_x, periodic_y;
   int32_t scheme;       // SCHEME_IREBM or SCHEME_EEBM
   int32_t neu;          // bit k: wall k (x-, x+, y-, y+) is a Neumann wall
+  int32_t x_shift;      // two-step kernels: strip s covers the columns from
+                        // s (bx - 4) - x_shift on (a narrow first strip)
   double a;             // 1 - 1/tau
   double inv_tau;       // 1/tau
   double wtau[9];       // w_i / tau
@@ -264,6 +269,7 @@ struct NodeStats {
   double max_res = 0.0;
   double flux_in = 0.0;
   double flux_out = 0.0;
+  int solves = 0;  // node updates that took the Newton path (not quiet)
 };
 
 // Raw loads of one node: own populations (for T) and pulled ones.
@@ -438,11 +444,17 @@ struct CloseInfo {
   double TD = 0.0, wu = 0.0;
 };
 
-template <int Q, int SCH = SCHEME_IREBM, bool NEU = true>
+// PLATEAU (quiet-only kernels): phi is taken only where it is exactly 0
+// or 1 (|T - T_m| > 20 delta), with no exp in the code; a Dirichlet node
+// whose wall or own temperature lies nearer the band sets *near instead
+// (its update is then left to a full kernel).
+template <int Q, int SCH = SCHEME_IREBM, bool NEU = true,
+          bool PLATEAU = false>
 __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
                                     double th, const double *om, double *q,
                                     uint32_t known, double mirror,
-                                    CloseInfo *ci = nullptr) {
+                                    CloseInfo *ci = nullptr,
+                                    int *near = nullptr) {
   uint32_t set = known;
   double fill = 0.0;
 #pragma unroll
@@ -460,11 +472,20 @@ __device__ __forceinline__ double close_node(const StepArgs &A, int x, int y,
   if (ci) ci->wall = wall;
   if (wall >= 0) {
     const double TD = wall_value(A, wall, x, y);
-    double D = SCH == SCHEME_EEBM    ? TD + (TD > A.tm ? A.inv_ste : 0.0)
-               : SCH == SCHEME_ILFBM ? TD
-                                     : TD + (phi_only(TD, A.tm, A.inv_delta) -
-                                             phi_only(th, A.tm, A.inv_delta)) *
-                                                A.inv_ste;
+    double D;
+    if constexpr (PLATEAU && SCH == SCHEME_IREBM) {
+      const double ud = (TD - A.tm) * A.inv_delta;
+      const double ut = (th - A.tm) * A.inv_delta;
+      if (!(fabs(ud) > 20.0 && fabs(ut) > 20.0)) *near = 1;
+      D = TD + ((ud > 20.0 ? 1.0 : 0.0) - (ut > 20.0 ? 1.0 : 0.0)) *
+                   A.inv_ste;
+    } else {
+      D = SCH == SCHEME_EEBM    ? TD + (TD > A.tm ? A.inv_ste : 0.0)
+          : SCH == SCHEME_ILFBM ? TD
+                                : TD + (phi_only(TD, A.tm, A.inv_delta) -
+                                        phi_only(th, A.tm, A.inv_delta)) *
+                                           A.inv_ste;
+    }
     double wu = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -536,8 +557,11 @@ __device__ __forceinline__ void node_masks(const StepArgs &A, int x, int y,
 }
 
 // The update of one node from its loads: the next state's populations
-// into v (rounded to the storage type).
-template <int Q, typename S, int MODE, bool FAST>
+// into v (rounded to the storage type).  QUIET: a kernel built for quiet
+// nodes only (no Newton code, so fewer registers); a node that is not
+// quiet is counted in st.solves, v is left meaningless, and the caller
+// hands its work item to a full kernel.
+template <int Q, typename S, int MODE, bool FAST, bool QUIET = false>
 __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
                                               const NodeLoad<Q, S> &L,
                                               NodeStats &st, S v[Q]) {
@@ -553,10 +577,12 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
+  int near = 0;
   if (!FAST) {
     if (L.known != (1u << Q) - 1u)
-      st.flux_in += close_node<Q, EEBM ? SCHEME_EEBM : SCHEME_IREBM, NEU>(
-          A, x, y, th, om, q, L.known, L.mirror);
+      st.flux_in +=
+          close_node<Q, EEBM ? SCHEME_EEBM : SCHEME_IREBM, NEU, QUIET>(
+              A, x, y, th, om, q, L.known, L.mirror, nullptr, &near);
     if (L.out) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
@@ -585,7 +611,7 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
     const double um = (m0 - A.tm) * A.inv_delta;
     const double d = th - m0;
     const double dx0 = m0 - (m0 - A.inv_ste);
-    if (u < -20.0 && um < -20.0 && th - d == m0 &&
+    if (u < -20.0 && um < -20.0 && th - d == m0 && !near &&
         (PLAIN || 2.0 * fabs(d) <= fabs(dx0))) {
       const bool one = fabs(d) <= A.tol;
       const int it = (one || A.max_it < 2) ? 1 : 2;
@@ -596,6 +622,12 @@ __device__ __forceinline__ void update_values(const StepArgs &A, int x, int y,
         v[i] = (S)(A.a * q[i] + A.wtau[wclass<Q>(i)] * m0);
       return;
     }
+  }
+  ++st.solves;
+  if constexpr (QUIET) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = (S)q[i];
+    return;
   }
   double pth, dpth;
   phi_dphi(th, A.tm, A.inv_delta, pth, dpth);

@@ -84,8 +84,10 @@ __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
 // One tile (tx, ty) of the lattice described by A, from state src to
 // state dst: on interior tiles all loads of the thread's nodes first
 // (memory-level parallelism), then the updates.  Statistics go into st;
-// returns whether the tile took the interior path.
-template <int Q, typename S, int NPT, int MODE, bool NT>
+// returns whether the tile took the interior path.  LIM (the front strips
+// of the split two-step schedule): only columns x < A.x_lim are computed
+// and only those with x < A.x_cnt counted.
+template <int Q, typename S, int NPT, int MODE, bool NT, bool LIM = false>
 __device__ __forceinline__ bool step_tile(const StepArgs &A,
                                           gptr<const S> __restrict__ src,
                                           gptr<S> __restrict__ dst, int tx,
@@ -94,6 +96,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
   const int TW = bx * NPT;
   const int x0 = tx * TW, y0 = ty * by;
   const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
+                    (!LIM || x0 + TW <= A.x_cnt) &&
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
   // a wave lies in one row of the tile (bx is a multiple of 64)
   const int y = y0 + __builtin_amdgcn_readfirstlane((int)threadIdx.y);
@@ -123,10 +126,22 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
       const bool cm = k == 0 && x0 == 0;
       const int x = cm ? (tid >> lb) : x0 + (int)threadIdx.x + k * bx;
       const int yj = cm ? y0 + (tid & (by - 1)) : y;
-      if (x < A.nx && yj < A.ny) {
+      if (x < (LIM ? A.x_lim : A.nx) && yj < A.ny) {
         NodeLoad<Q, S> L;
         load_node<Q, S, false, neumann_mode(MODE)>(A, src, x, yj, L);
-        update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, st);
+        if constexpr (LIM) {
+          NodeStats one;
+          update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, one);
+          if (x < A.x_cnt) {
+            st.max_it = max(st.max_it, one.max_it);
+            st.nonconv += one.nonconv;
+            st.max_res = fmax(st.max_res, one.max_res);
+            st.flux_in += one.flux_in;
+            st.flux_out += one.flux_out;
+          }
+        } else {
+          update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, st);
+        }
       }
     }
   }
@@ -139,7 +154,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
 // block's start-up (descriptor and slot reads) and statistics reduction
 // are paid once per item.  One statistics slot per item.
 template <int Q, typename S, int NPT, int MODE, bool NT = false,
-          bool LOOP = false>
+          bool LOOP = false, bool LIM = false>
 __device__ __forceinline__ void step_item(const StepArgs &A,
                                           gptr<const S> __restrict__ src,
                                           gptr<S> __restrict__ dst, int item,
@@ -156,8 +171,8 @@ __device__ __forceinline__ void step_item(const StepArgs &A,
     // spill them into vector registers (lower occupancy).
     int z = 0;
     asm volatile("" : "+s"(z));
-    fast &= step_tile<Q, S, NPT, MODE, NT>((&A)[z], src, dst, tx, ty0 + r,
-                                           st);
+    fast &= step_tile<Q, S, NPT, MODE, NT, LIM>((&A)[z], src, dst, tx,
+                                                ty0 + r, st);
   }
   // read after the loop: a prefetched slot would stay live across it
   StatSlot pre{};
@@ -239,7 +254,7 @@ __device__ __forceinline__ void load_ring(const StepArgs &A,
 
 // the update of node (x, y) of a window from a ring: the interior form
 // (no masks, no closures) when every neighbour is a lattice node
-template <int Q, typename S, int MODE, int RING, int WIN>
+template <int Q, typename S, int MODE, int RING, int WIN, bool QUIET = false>
 __device__ __forceinline__ void ring_update(const StepArgs &A,
                                             const S (*ring)[Q][WIN], int x,
                                             int y, int t, int r, int base,
@@ -247,18 +262,24 @@ __device__ __forceinline__ void ring_update(const StepArgs &A,
   NodeLoad<Q, S> L;
   if (inner) {
     load_ring<Q, S, RING, WIN, true>(A, ring, x, y, t, r, base, L);
-    update_values<Q, S, MODE, true>(A, x, y, L, st, v);
+    update_values<Q, S, MODE, true, QUIET>(A, x, y, L, st, v);
   } else {
     load_ring<Q, S, RING, WIN, false>(A, ring, x, y, t, r, base, L);
-    update_values<Q, S, MODE, false>(A, x, y, L, st, v);
+    update_values<Q, S, MODE, false, QUIET>(A, x, y, L, st, v);
   }
 }
 
 // One block: strip `strip` of segment `seg` (seg_rows rows) of the lattice
 // described by A, from state src to state dst, two steps (two = true) or
 // one (the rows of step n + 1 are then written out directly).
-template <int Q, typename S, int MODE, bool NT, int BY, int WIN>
-__device__ __forceinline__ void step2_body(const StepArgs &A,
+// QUIET: node updates of quiet nodes only (no Newton code); when any node
+// of the window, halo included, is not quiet, the item's statistics are
+// not added (its outputs are then rewritten by a full kernel).  Returns,
+// for QUIET and FLAGGED (a full kernel over flagged items), whether any
+// node of the window took (or needed) the Newton path.
+template <int Q, typename S, int MODE, bool NT, int BY, int WIN,
+          bool QUIET = false, bool FLAGGED = false>
+__device__ __forceinline__ bool step2_body(const StepArgs &A,
                                            gptr<const S> __restrict__ src,
                                            gptr<S> __restrict__ dst, int strip,
                                            int seg, int seg_rows, bool two,
@@ -271,7 +292,7 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
   const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
   const int s0 = seg * seg_rows;
   const int s1 = min(s0 + seg_rows, A.ny);       // output rows [s0, s1)
-  const int x = strip * (WIN - 4) - 2 + t;        // window column
+  const int x = strip * (WIN - 4) - 2 + t - A.x_shift;  // window column
   const int nx = A.nx, ny = A.ny;
   const int64_t P = A.plane;
   const bool px = A.periodic_x != 0, py = A.periodic_y != 0;
@@ -335,8 +356,8 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
       const int b = a - 1 + ty;
       if (own_col && b >= s0 && b < s1) {
         const bool inner = inner_x && (py || (b >= 1 && b <= ny - 2));
-        ring_update<Q, S, MODE, RING, WIN>(Ai, l0, x, b, t, b, base, inner,
-                                            st, w);
+        ring_update<Q, S, MODE, RING, WIN, QUIET>(Ai, l0, x, b, t, b, base,
+                                                   inner, st, w);
         wo = (int64_t)b * nx + x;
       }
     } else {
@@ -346,8 +367,8 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
         S v[Q];
         NodeStats one;
         const bool inner = inner_x && (py || (gb >= 1 && gb <= ny - 2));
-        ring_update<Q, S, MODE, RING, WIN>(Ai, l0, gx, gb, t, b, base, inner,
-                                            one, v);
+        ring_update<Q, S, MODE, RING, WIN, QUIET>(Ai, l0, gx, gb, t, b, base,
+                                                   inner, one, v);
         if (own_col && b >= s0 && b < s1) {
           st.max_it = max(st.max_it, one.max_it);
           st.nonconv += one.nonconv;
@@ -355,6 +376,7 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
           st.flux_in += one.flux_in;
           st.flux_out += one.flux_out;
         }
+        st.solves += one.solves;   // halo nodes too: own nodes use them
 #pragma unroll
         for (int j = 0; j < Q; ++j) l1[(unsigned)(b - base) % RING][j][t] = v[j];
       }
@@ -365,8 +387,8 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
       const int c = a - 2 + ty;
       if (own_col && c >= s0 && c < s1) {
         const bool inner = inner_x && (py || (c >= 1 && c <= ny - 2));
-        ring_update<Q, S, MODE, RING, WIN>(Ai, l1, x, c, t, c, base, inner,
-                                            st, w);
+        ring_update<Q, S, MODE, RING, WIN, QUIET>(Ai, l1, x, c, t, c, base,
+                                                   inner, st, w);
         wo = (int64_t)c * nx + x;
       }
     }
@@ -378,9 +400,15 @@ __device__ __forceinline__ void step2_body(const StepArgs &A,
       else dst[j * P + wo] = w[j];
     }
   }
-  StatSlot pre{};
-  if (t == 0 && ty == 0) pre = *slot;
-  block_stats_to_slot<false>(st, false, pre, slot);
+  bool any = false;
+  if constexpr (QUIET || FLAGGED)
+    any = __syncthreads_or(st.solves > 0) != 0;
+  if (!QUIET || !any) {
+    StatSlot pre{};
+    if (t == 0 && ty == 0) pre = *slot;
+    block_stats_to_slot<false>(st, false, pre, slot);
+  }
+  return any;
 }
 
 // Blocks are numbered strip-fastest within a segment of rows, and each

@@ -23,7 +23,8 @@ namespace {
 
 // one work item of the table: items[t] = (instance, item index within
 // it); the descriptor is block-uniform and read in place with scalar loads
-template <int Q, typename S, int NPT, int MODE, bool NT, bool LOOP>
+template <int Q, typename S, int NPT, int MODE, bool NT, bool LOOP,
+          bool LIM = false>
 __device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
                                            const int2 *__restrict__ items,
                                            int t, int parity) {
@@ -33,19 +34,21 @@ __device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
   const StepArgs &A = descs[inst];
   const auto src = to_global((const S *)(parity ? A.dst : A.src));
   const auto dst = to_global((S *)(parity ? A.src : A.dst));
-  step_item<Q, S, NPT, MODE, NT, LOOP>(A, src, dst, item, A.slots + item);
+  step_item<Q, S, NPT, MODE, NT, LOOP, LIM>(A, src, dst, item,
+                                            A.slots + item);
 }
 
 // one block per work item, the blocks of XCD k taking the k-th contiguous
-// chunk of the table
-template <int Q, typename S, int NPT, int MODE, bool NT>
+// chunk of the table (LIM: the column-limited front strips of the split
+// two-step schedule, see batch_step2_kernel)
+template <int Q, typename S, int NPT, int MODE, bool NT, bool LIM = false>
 __global__ __launch_bounds__(256) void batch_step_kernel(
     const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
     int32_t nitems, int32_t parity, int32_t reverse) {
   const int chunk = (nitems + 7) >> 3;
   const int b = (int)blockIdx.x;
   if ((b & 7) * chunk + (b >> 3) >= nitems) return;
-  batch_item<Q, S, NPT, MODE, NT, false>(
+  batch_item<Q, S, NPT, MODE, NT, false, LIM>(
       descs, items, xcd_item(b, chunk, nitems, reverse), parity);
 }
 
@@ -65,25 +68,50 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(
 }
 
 // two steps (or one) per launch: one block per item of the two-step
-// tiling (a strip of one segment of one instance), XCD-contiguous chunks
-template <int Q, typename S, int MODE, int BY, int WIN>
+// tiling (a strip of one segment of one instance), XCD-contiguous chunks.
+//
+// Split schedule (SPLIT > 0, IREBM): the Newton solve is what keeps the
+// two-step kernel from its memory bound (its registers cap the waves per
+// SIMD, and the front's solves hold every wave of a block at the barriers
+// of each pass), while nearly every node of a melting problem is quiet
+// (far below the band: a closed form).  So a two-step launch is split by
+// work item, with flags[t] per item of the table:
+//   flags 1: a front strip, advanced by two column-limited one-step
+//            passes of batch_step_kernel (LIM) through a third state;
+//   flags 0: SPLIT = 1, the kernel built for quiet nodes only (no Newton
+//            code, 6 waves per SIMD in FP32 D2Q5); an item with a node
+//            (halo included) that is not quiet is set to flags 2;
+//   flags 2: SPLIT = 2, the full kernel, run after the quiet pass, which
+//            rewrites the item's outputs and returns it to flags 0 when
+//            all of its nodes were quiet.
+// Every node is updated by the same arithmetic as in the one-pass kernel.
+template <int Q, typename S, int MODE, int BY, int WIN, int SPLIT = 0>
 __global__ __launch_bounds__(WIN * BY)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 4 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(
+    sizeof(S) == 4 ? (SPLIT == 1 && Q == 5 ? 6 : 4) : 1)))
 void batch_step2_kernel(const StepArgs *__restrict__ descs,
                         const int2 *__restrict__ items, int32_t nitems,
-                        int32_t parity, int32_t two) {
+                        int32_t parity, int32_t two, int *__restrict__ flags) {
   const int per_xcd = (nitems + 7) >> 3;
   const int t = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (t >= nitems) return;
+  if (SPLIT > 0 &&
+      __builtin_amdgcn_readfirstlane(flags[t]) != (SPLIT == 1 ? 0 : 2))
+    return;
   const int2 e = items[t];
   const int inst = __builtin_amdgcn_readfirstlane(e.x);
   const int item = __builtin_amdgcn_readfirstlane(e.y);
   const StepArgs &A = descs[inst];
   const auto src = to_global((const S *)(parity ? A.dst : A.src));
   const auto dst = to_global((S *)(parity ? A.src : A.dst));
-  step2_body<Q, S, MODE, true, BY, WIN>(A, src, dst, item % A.tiles_x,
-                                        item / A.tiles_x, A.group, two != 0,
-                                        A.slots + item);
+  const bool any = step2_body<Q, S, MODE, true, BY, WIN, SPLIT == 1,
+                              SPLIT == 2>(A, src, dst, item % A.tiles_x,
+                                          item / A.tiles_x, A.group, two != 0,
+                                          A.slots + item);
+  if (SPLIT > 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    if (SPLIT == 1 && any) flags[t] = 2;
+    if (SPLIT == 2 && !any) flags[t] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -140,19 +168,43 @@ hipError_t launch_batch_t(const BatchLaunch &b, const Variant &v,
                           hipStream_t stream) {
   const int64_t chunk = (b.nitems + 7) / 8;
   const int32_t nt = (int32_t)b.nitems;
+  if (b.lim) {
+    // front strips of the split schedule: one block per item, the front
+    // variant's shape only
+    if (v.tb || v.npt > 2 || !v.nt || b.blocks_per_cu > 0)
+      return hipErrorInvalidValue;
+    dim3 grid((unsigned)(8 * std::max<int64_t>(chunk, 1))), block(v.bx, v.by);
+    if (v.npt == 1)
+      batch_step_kernel<Q, S, 1, MODE, true, true>
+          <<<grid, block, 0, stream>>>(b.descs, b.items, nt, b.parity, 0);
+    else
+      batch_step_kernel<Q, S, 2, MODE, true, true>
+          <<<grid, block, 0, stream>>>(b.descs, b.items, nt, b.parity, 0);
+    return hipGetLastError();
+  }
   if (v.tb) {
     if constexpr (Q == 3) {
       return hipErrorInvalidValue;
     } else {
       dim3 grid((unsigned)(8 * std::max<int64_t>(chunk, 1))), block(v.bx, v.by);
       const int32_t tw = b.two ? 1 : 0;
+      if (b.split && (MODE == kEebm || !b.flags || !b.two))
+        return hipErrorInvalidValue;
+#define B2LAUNCH_S(BY, WIN, SP)                                            \
+  batch_step2_kernel<Q, S, MODE, BY, WIN, SP><<<grid, block, 0, stream>>>( \
+      b.descs, b.items, nt, b.parity, tw, b.flags)
 #define B2LAUNCH(BY, WIN)                                                  \
-  batch_step2_kernel<Q, S, MODE, BY, WIN><<<grid, block, 0, stream>>>(    \
-      b.descs, b.items, nt, b.parity, tw)
+  do {                                                                     \
+    if constexpr (MODE == kEebm) B2LAUNCH_S(BY, WIN, 0);                   \
+    else if (b.split == 1) B2LAUNCH_S(BY, WIN, 1);                         \
+    else if (b.split == 2) B2LAUNCH_S(BY, WIN, 2);                         \
+    else B2LAUNCH_S(BY, WIN, 0);                                           \
+  } while (0)
       if (v.bx == 256) B2LAUNCH(2, 256);
       else if (v.by == 2) B2LAUNCH(2, 128);
       else B2LAUNCH(4, 128);
 #undef B2LAUNCH
+#undef B2LAUNCH_S
       return hipGetLastError();
     }
   }

@@ -167,6 +167,7 @@ void irebm::fill_args(const lbm_stefan_params &p, double *const prof[4],
   std::memset(A, 0, sizeof(*A));
   A->nx = (int32_t)p.nx;
   A->ny = (int32_t)p.ny;
+  A->x_lim = A->x_cnt = (int32_t)p.nx;
   A->plane = p.nx * p.ny;
   A->periodic_x = p.bc[0] == LBM_BC_PERIODIC;
   A->periodic_y = p.dim == 2 && p.bc[2] == LBM_BC_PERIODIC;
@@ -625,8 +626,8 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
   if (w.res)
     std::snprintf(buf, sizeof(buf), "resident%d", (int)kResident1D);
   else if (w.tb)
-    std::snprintf(buf, sizeof(buf), "%dx%d/t2%s%s", w.bx, w.by, rows,
-                  w.nt ? "/nt" : "");
+    std::snprintf(buf, sizeof(buf), "%dx%d/t2%s%s%s", w.bx, w.by,
+                  w.tb == 2 ? "s" : "", rows, w.nt ? "/nt" : "");
   else
     std::snprintf(buf, sizeof(buf), "%dx%d/npt%d%s%s%s", w.bx * w.npt, w.by,
                   w.npt, rows, w.nt ? "/nt" : "", w.rev ? "/rev" : "");
@@ -686,6 +687,7 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
     // lattice the resident kernel does not take runs that variant so too
     if (vt && vt[v].tb && has_neumann(p)) continue;
     if (vt && vt[v].res && !resident_ok(p)) continue;
+    if (vt && vt[v].tb == 2) continue;  // single lattices: same as tb = 1
     h->variant = v;
     // two untimed steps, then the timed trial (an even count, so that a
     // two-step variant runs its own kernel only)

@@ -110,6 +110,11 @@ struct BatchLaunch {
                           // when blocks_per_cu > 0, else one per item
   int parity;             // 0: src -> dst of each descriptor, 1: dst -> src
   bool two;               // two steps under a two-step variant (else one)
+  int split = 0;          // two-step kernels: 0 every item, 1 the quiet
+                          // pass over items flagged 0, 2 the full pass over
+                          // items flagged 2 (batch_step2_kernel)
+  int *flags = nullptr;   // device: one flag per work item (split > 0)
+  bool lim = false;       // the column-limited one-step front pass
 };
 
 template <int MODE>

@@ -119,7 +119,7 @@ def test_variants_listed(L):
     for q in (3, 5, 9):
         names = variant_names(q)
         assert len(names) >= 3
-        assert all(re.fullmatch(r"\d+x\d+(/npt\d|/t2)(/r\d+)?(/nt)?(/rev)?", n)
+        assert all(re.fullmatch(r"\d+x\d+(/npt\d|/t2s?)(/r\d+)?(/nt)?(/rev)?", n)
                    or (q == 3 and n == "resident2048") for n in names)
     # D1Q3 only: the resident variant, last in its list
     assert variant_names(3)[-1] == "resident2048"

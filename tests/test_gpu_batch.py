@@ -205,6 +205,57 @@ def test_batch_two_step_variants_equal_single_steps(name):
 
 
 
+def _split_mix(storage):
+    """Instances for the split two-step schedule: heated at x = 0 (front
+    strip), heated at x = 1 only (its front in the last strip: the quiet
+    pass flags those items), heated at both walls, a field just below
+    melting everywhere (every item flagged), a wall profile, a non-square
+    lattice, and sizes from one strip (64) to three (300)."""
+    probs = synth.batch_table(count=6, seed=23, sizes=[64, 192, 300],
+                              storage=storage, nsteps=40)
+    p = probs
+    p[1] = p[1].with_(wall_T=(-0.5, 1.0, 0.0, 0.0))
+    p[2] = p[2].with_(wall_T=(1.0, 1.0, 0.0, 0.0))
+    p[3] = p[3].with_(T0=np.full((p[3].ny, p[3].nx), -2.0 * p[3].delta))
+    p[4] = p[4].with_(wall_profile=(
+        0.8 + 0.4 * np.sin(np.arange(p[4].ny) / 5.0), None, None, None))
+    ny5 = p[5].nx // 2 + 9
+    p[5] = p[5].with_(ny=ny5, T0=p[5].T0[:ny5])
+    return p
+
+
+@pytest.mark.parametrize("name", ["128x2/t2s/r16/nt", "128x4/t2s/r32/nt",
+                                  "128x2/t2s/r64/nt"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_split_two_step_schedule_equals_single_steps(name, storage):
+    """The split two-step schedule (front strips by two column-limited
+    one-step passes, quiet pass, full pass over flagged items) gives the
+    states of one-step launches bit for bit, in eager launches and graph
+    replays, with odd step counts, and the same statistics."""
+    from paper_2505_13097_amd import StefanBatch, variant_names
+    probs = _split_mix(storage)
+    v = variant_names(5, storage).index(name)
+    a = StefanBatch(probs)
+    ref = StefanBatch(probs)
+    a.set_schedule(v, 0, 6)
+    done = 0
+    for n in (6, 7, 1, 12, 3, 2):
+        a.step(n)
+        ref.step(n)
+        done += n
+        for k in range(len(probs)):
+            assert np.array_equal(a.temperature(k), ref.temperature(k)), (n, k)
+    for k, (sa, sr) in enumerate(zip(a.stats(), ref.stats())):
+        assert sa["steps"] == sr["steps"] == done
+        assert sa["max_newton_it"] == sr["max_newton_it"], k
+        assert sa["nonconverged"] == sr["nonconverged"], k
+        assert sa["max_residual"] == sr["max_residual"], k
+        for f in ("flux_in", "flux_out"):
+            assert abs(sa[f] - sr[f]) <= 1e-12 * max(1.0, abs(sr[f])), (k, f)
+    a.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("schedule", ["bench", "autotune"])
 @pytest.mark.parametrize("storage", ["f32", "f64"])
 def test_full_table_of_512_instances_against_oracle(storage, schedule):

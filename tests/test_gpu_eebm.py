@@ -212,7 +212,7 @@ def test_variants_bitwise_identical():
 
 def _two_step_variants(q, storage):
     from paper_2505_13097_amd import variant_names
-    return [i for i, n in enumerate(variant_names(q, storage)) if "/t2" in n]
+    return [i for i, n in enumerate(variant_names(q, storage)) if "/t2/" in n]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])

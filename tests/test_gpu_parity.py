@@ -166,7 +166,7 @@ def test_variants_bitwise_identical():
 
 def _two_step_variants(q, storage):
     from paper_2505_13097_amd import variant_names
-    return [i for i, n in enumerate(variant_names(q, storage)) if "/t2" in n]
+    return [i for i, n in enumerate(variant_names(q, storage)) if "/t2/" in n]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -285,7 +285,7 @@ def _full_size_variants(q):
     autotuner's pick"""
     from paper_2505_13097_amd import variant_names
     names = variant_names(q, "f32")
-    return [-1] + [i for i, n in enumerate(names) if "/t2" in n] + \
+    return [-1] + [i for i, n in enumerate(names) if "/t2/" in n] + \
         ["autotune"]
 
 

@@ -184,17 +184,21 @@ def test_3d_replay_detects_an_overrun():
 # 2D two-step kernel: step2_body
 
 def _parse_t2(name):
-    m = re.fullmatch(r"(\d+)x(\d+)/t2(/r(\d+))?(/nt)?", name)
+    m = re.fullmatch(r"(\d+)x(\d+)/t2s?(/r(\d+))?(/nt)?", name)
     return int(m.group(1)), int(m.group(2)), int(m.group(4) or 1)
 
 
-def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None):
+def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None,
+              shift=0, skip_strip0=False, out=None):
     """Every offset and LDS row step2_body touches; returns the number of
     global accesses checked.  ring_rows: ring size other than the kernel's
-    BY + 2 (a planted mistake)."""
+    BY + 2 (a planted mistake).  shift: the descriptor's x_shift (a narrow
+    first strip); skip_strip0: the blocks of strip 0 exit (the split
+    schedule's front strips), and out, if given, receives the count of
+    stores per node instead of the every-node-once check."""
     P = nx * ny
     ring = by + 2 if ring_rows is None else ring_rows
-    nstrips = (nx + win - 5) // (win - 4)
+    nstrips = (nx + shift + win - 5) // (win - 4)
     nseg = -(-ny // rows)
     nitems = nstrips * nseg
     per_xcd = (nitems + 7) // 8
@@ -221,6 +225,8 @@ def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None):
             continue
         seen[item] += 1
         strip, seg = item % nstrips, item // nstrips
+        if skip_strip0 and strip == 0:
+            continue
         s0 = seg * rows
         s1 = min(s0 + rows, ny)
         base = s0 - 12
@@ -229,11 +235,11 @@ def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None):
         l0 = [None] * ring
         l1 = [None] * ring
         for t in range(win):
-            x = strip * (win - 4) - 2 + t
-            assert -2 <= x <= nx + win       # the window may overhang
+            x = strip * (win - 4) - 2 + t - shift
+            assert -2 - shift <= x <= nx + win   # the window may overhang
         cols = []
         for t in range(win):
-            x = strip * (win - 4) - 2 + t
+            x = strip * (win - 4) - 2 + t - shift
             gx, col = x, 0 <= x < nx
             if not col and px:
                 gx, col = x % nx, True
@@ -311,8 +317,94 @@ def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None):
             for j in range(q):
                 gcheck(j, wx, wy)
     assert np.all(seen == 1)
-    assert np.all(written == 1)          # every node stored exactly once
+    if out is not None:
+        out += written
+    else:
+        assert np.all(written == 1)      # every node stored exactly once
     return checked
+
+
+# the split two-step schedule of the batched form: front strips of
+# FRONT_COLUMNS columns (the whole lattice if it fits one strip) advanced
+# by the one-step tiling FRONT (bx, by, npt, tile rows per block) with
+# column limits (kFrontColumns and kFrontVariant2D of host_util.hpp)
+FRONT_COLUMNS = 60
+FRONT = (64, 4, 1, 4)
+
+
+def replay_front(q, nx, ny, bx, by, npt, rows, x_lim, x_cnt):
+    """The column-limited one-step pass (step_tile with LIM): returns the
+    count of stores and of statistics contributions per node; every node
+    inside the lattice."""
+    tw = bx * npt
+    tiles_x = -(-x_lim // tw)
+    tiles_y = -(-ny // by)
+    nitems = tiles_x * (-(-tiles_y // rows))
+    stored = np.zeros((ny, nx), dtype=int)
+    counted = np.zeros((ny, nx), dtype=int)
+    lb = by.bit_length() - 1
+    assert 1 << lb == by and bx % 64 == 0 and bx * by <= 256
+    for item in range(nitems):
+        tx, ty0 = item % tiles_x, (item // tiles_x) * rows
+        for r in range(min(rows, tiles_y - ty0)):
+            x0, y0 = tx * tw, (ty0 + r) * by
+            fast = (x0 >= 1 and x0 + tw <= nx - 1 and x0 + tw <= x_cnt and
+                    y0 >= 1 and y0 + by <= ny - 1)
+            for ty in range(by):
+                for t in range(bx):
+                    for k in range(npt):
+                        if fast:
+                            x, y = x0 + t + k * bx, y0 + ty
+                        else:
+                            # the x = 0 tile deals its first bx columns
+                            # out column by column
+                            tid = t + ty * bx
+                            cm = k == 0 and x0 == 0
+                            x = tid >> lb if cm else x0 + t + k * bx
+                            y = y0 + (tid & (by - 1)) if cm else y0 + ty
+                            if not (x < x_lim and y < ny):
+                                continue
+                        assert 0 <= x < nx and 0 <= y < ny
+                        stored[y, x] += 1
+                        counted[y, x] += 1 if (fast or x < x_cnt) else 0
+    return stored, counted
+
+
+@pytest.mark.parametrize("q", [5, 9])
+def test_split_schedule_updates_every_node_once(names, q):
+    """Front passes plus the shifted two-step strips (the quiet and full
+    passes skip strip 0) store every node of step n + 2 exactly once and
+    count it once per step; pass 1 computes every step n + 1 node pass 2
+    pulls from."""
+    t2s = [n for n in names[q] if "/t2s" in n]
+    assert t2s
+    fb, fby, fnpt, frows = FRONT
+    for name in t2s:
+        win, by, rows = _parse_t2(name)
+        for (nx, ny) in SHAPES2 + [(59, 7), (60, 9), (61, 5), (62, 66),
+                                   (183, 10), (184, 3), (185, 33)]:
+            # a lattice that fits one strip is all front strip
+            wf = nx if nx <= win - 4 else FRONT_COLUMNS
+            shift = win - 4 - wf
+            for py in (False, True):
+                lim1, lim2 = min(wf + 1, nx), min(wf, nx)
+                s1, c1 = replay_front(q, nx, ny, fb, fby, fnpt, frows,
+                                      lim1, lim2)
+                s2, c2 = replay_front(q, nx, ny, fb, fby, fnpt, frows,
+                                      lim2, lim2)
+                assert np.all(s1[:, :lim1] == 1) and not s1[:, lim1:].any()
+                assert np.all(c1[:, :lim2] == 1) and not c1[:, lim2:].any()
+                # pass 2's pulls (x - 1 .. x + 1) inside what pass 1 wrote
+                assert lim2 + 1 <= lim1 or lim1 == nx
+                out = np.zeros((ny, nx), dtype=int)
+                replay_t2(q, nx, ny, win, by, rows, False, py, True,
+                          shift=shift, skip_strip0=True, out=out)
+                assert not out[:, :lim2].any()
+                assert np.all(out + s2 == 1), (name, nx, ny)
+                assert np.all(out + c2 == 1)
+                # odd single steps: the full kernel over every strip
+                replay_t2(q, nx, ny, win, by, rows, False, py, False,
+                          shift=shift)
 
 
 SHAPES2 = [(3, 3), (5, 4), (3, 40), (124, 5), (125, 6), (126, 3), (252, 9),
