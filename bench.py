@@ -28,6 +28,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -122,7 +123,7 @@ DEFAULT_VARIANTS = {
     "planar": "256x4/npt4",
     "planar_eebm": "256x4/npt4",
     "stefan1d": "resident2048",
-    "batched": "128x4/npt2/r16/nt",
+    "batched": "128x2/t2s/r96/nt",
     "adjoint": "256x1/npt1",
     "cube3d_19": "256x1/npt2/z4/nt",
     "cube3d_7": "256x1/npt2/z8/nt",
@@ -701,6 +702,39 @@ def traffic_sweep(prob):
     return names
 
 
+BATCH_PROFILE = "batch_step2_kernel_batch512_d2q5_f32.md"
+
+
+def batch_kernels(vname, mode=0):
+    """Trace names of the kernels one batched launch runs under variant
+    vname (IREBM mode 0, EEBM mode 2), by role."""
+    if "/t2" in vname:
+        m = re.fullmatch(r"(\d+)x(\d+)/t2s?(/r\d+)?(/nt)?", vname)
+        win, by = int(m.group(1)), int(m.group(2))
+        base = f"batch_step2_kernel<5, float, {mode}, {by}, {win}"
+        if "/t2s" in vname and mode != 2:
+            return {"front": f"batch_front_kernel<5, float, {mode}>",
+                    "quiet": base + ", 1>", "full": base + ", 2>"}
+        return {"two-step": base + ", 0>"}
+    m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+).*", vname)
+    npt = int(m.group(3))
+    nt = "true" if "/nt" in vname else "false"
+    return {"one-step": f"batch_step_kernel<5, float, {npt}, {mode}, {nt}>"}
+
+
+def batch_walls(c, short, bkern):
+    """Wall time (us) of each batched launch in a kernel trace: from the
+    first start to the last end of the launch's kernels (one of each role
+    per launch, in order)."""
+    rows = c.execute("select name, start, end from kernels "
+                     "order by start").fetchall()
+    per = {role: [(s_, e) for n, s_, e in rows if short(n) == k]
+           for role, k in bkern.items()}
+    n = min(len(v) for v in per.values())
+    return [(max(v[i][1] for v in per.values()) -
+             min(v[i][0] for v in per.values())) / 1000.0 for i in range(n)]
+
+
 def summarize_profiles(run, args):
     """Write the profiles/ summaries from the rocprofv3 databases of a
     GPU run: run/prof_all (kernel trace of the bench with a fixed plain
@@ -753,9 +787,12 @@ def summarize_profiles(run, args):
               k.startswith(kname + "<")]
     eebm_avg = (sum(by[eebm_k[0]][-launches:]) / launches
                 if eebm_k and len(by[eebm_k[0]]) >= launches else None)
-    bat = [k for k in by if k.startswith("batch_step_kernel<5, float") or
-           k.startswith("batch_persistent_kernel<5, float")][0]
-    bat_avg = sum(by[bat][-args.batch_steps:]) / args.batch_steps
+    bkern = batch_kernels(bvname)
+    blaunch = args.batch_steps // steps_per_launch(bvname)
+    bwall = batch_walls(c, short, bkern)[-blaunch:]
+    bat_avg = sum(bwall) / len(bwall)          # wall time per launch
+    bk_avg = {role: sum(by[k][-blaunch:]) / blaunch
+              for role, k in bkern.items() if by.get(k)}
 
     def counters(sub, cn):
         rows = db(sub).execute(
@@ -792,11 +829,20 @@ def summarize_profiles(run, args):
                            b / prob.nodes / steps_per_launch(nm), 3),
                        "ratio_to_algorithmic": round(
                            b / (alg * steps_per_launch(nm)), 4)}
-    bf = [v for k, v in F if k == bat][-1]
-    bw = [v for k, v in W if k == bat][-1]
+    # counters of the batch's last launch in the sweep (IREBM comes first)
+    def last_launch(C):
+        out = {}
+        for role, k in bkern.items():
+            vs = [v for kk, v in C if kk == k]
+            if vs:
+                out[role] = vs[-1]
+        return out
+    bF, bW = last_launch(F), last_launch(W)
+    bf, bw = sum(bF.values()), sum(bW.values())
     bprobs = synth.batch_table(count=args.batch_count, nsteps=args.batch_steps)
     bnodes = sum(p.nodes for p in bprobs)
-    balg = bnodes * 40
+    bspl = steps_per_launch(bvname)
+    balg = bnodes * 40 * bspl
     bfb, bwb = bf * 1024 * fs, bw * 1024 * ws
     src = kernel_source_hash()
 
@@ -864,20 +910,38 @@ def summarize_profiles(run, args):
                 f"kernel (time ratio IREBM/EEBM {cav / eebm_avg:.3f}); "
                 f"algorithmic bytes per launch {alg * spl / 1e9:.4f} GB -> "
                 f"{alg * spl / (eebm_avg * 1e-6) / 1e9:.0f} GB/s.", ""]))
-    with open(os.path.join(out, "batch_step_kernel_batch512_d2q5_f32.md"), "w") as f:
-        f.write("\n".join([
-            f"# {bat.split('<')[0]} — {args.batch_count} D2Q5 instances "
-            f"(64^2 ... 1024^2), FP32 (variant {bvname}, blocks per CU {BB})", "",
-            f"Same kernel trace as {fn} (the bench's batched form:",
-            f"{args.batch_steps} steps replayed from hipGraphs of 100 launches).", "",
-            f"Average {bat_avg:.1f} us per launch over the timed launches; "
-            f"{bnodes:,} nodes x 40 B = {balg / 1e9:.3f} GB",
-            f"algorithmic per launch -> {balg / (bat_avg * 1e-6) / 1e9:.0f} GB/s.", "",
-            "| counter | KiB/dispatch | scale | bytes |", "|---|---|---|---|",
-            f"| FETCH_SIZE | {bf:.0f} | {fs:.4f} | {bfb / 1e9:.4f} GB |",
-            f"| WRITE_SIZE | {bw:.0f} | {ws:.4f} | {bwb / 1e9:.4f} GB |", "",
-            f"Total {(bfb + bwb) / 1e9:.4f} GB per launch "
-            f"({(bfb + bwb) / balg:.4f}x the algorithmic bytes).", ""]))
+    blines = [
+        f"# Batched form — {args.batch_count} D2Q5 instances (64^2 ... "
+        f"1024^2), FP32, variant {bvname} (blocks per CU {BB})", "",
+        f"Same kernel trace as {fn} (the bench's batched form:",
+        f"{args.batch_steps} steps replayed from hipGraphs of 100 steps).", ""]
+    if "front" in bkern:
+        blines += [
+            "Split two-step schedule, per launch of two steps: the front "
+            "strips (batch_front_kernel, on a stream of its own) beside the "
+            "quiet pass (batch_step2_kernel<..., 1>), then the full pass over "
+            "flagged items (batch_step2_kernel<..., 2>).", ""]
+    blines += ["| kernel | role | average us per launch |", "|---|---|---|"]
+    for role, k in bkern.items():
+        if role in bk_avg:
+            blines.append(f"| {k} | {role} | {bk_avg[role]:.1f} |")
+    blines += [
+        "", f"Wall time per launch (first kernel start to last kernel end, "
+        f"from the trace's timestamps), average over the {len(bwall)} timed "
+        f"launches: {bat_avg:.1f} us ({bat_avg / bspl:.1f} us per step); "
+        f"{bnodes:,} nodes x 40 B x {bspl} step(s) = {balg / 1e9:.3f} GB "
+        f"algorithmic per launch -> {balg / (bat_avg * 1e-6) / 1e9:.0f} GB/s.",
+        "", "| kernel | FETCH KiB | WRITE KiB | bytes |", "|---|---|---|---|"]
+    for role, k in bkern.items():
+        if role in bF and role in bW:
+            blines.append(f"| {k} | {bF[role]:.0f} | {bW[role]:.0f} | "
+                          f"{(bF[role] * fs + bW[role] * ws) * 1024 / 1e9:.4f}"
+                          " GB |")
+    blines += ["", f"Counter scale as above (FETCH_SIZE x{fs:.4f}, WRITE_SIZE "
+               f"x{ws:.4f}); total {(bfb + bwb) / 1e9:.4f} GB per launch "
+               f"({(bfb + bwb) / balg:.4f}x the algorithmic bytes).", ""]
+    with open(os.path.join(out, BATCH_PROFILE), "w") as f:
+        f.write("\n".join(blines))
     adj = [r for r in trace if "adj_" in r[0] or "front_vjp" in r[0] or
            "init_term" in r[0]]
     with open(os.path.join(out, "adjoint_kernels_adjoint512_d2q5_f32.md"), "w") as f:
@@ -916,10 +980,13 @@ def summarize_sq(run, args, db, short):
     for d, k, cn, v in rows:
         per.setdefault((d, short(k)), {})[cn] = v
     bnames = variant_names(5, "f32")
-    kinds = [("batched IREBM", "batch_step_kernel<5, float, 2, 0,"),
-             ("batched EEBM", "batch_step_kernel<5, float, 2, 2,")]
+    bv = bnames[args.batch_variant]
+    kinds = [(f"batched IREBM, {role}", k)
+             for role, k in batch_kernels(bv, 0).items()]
+    kinds += [(f"batched EEBM, {role}", k)
+              for role, k in batch_kernels(bv, 2).items()]
     lines = ["# SQ counters — batched form (512 D2Q5 instances, FP32, variant "
-             f"{bnames[args.batch_variant]}) in IREBM and EEBM", "",
+             f"{bv}) in IREBM and EEBM", "",
              "    rocprofv3 --pmc " + " ".join(SQ_COUNTERS) +
              " -d gpurun_out/pmc_sq -o sq -- python bench.py --traffic-sweep"
              f" --batch-steps 4 --batch-variant {args.batch_variant}"
@@ -930,7 +997,7 @@ def summarize_sq(run, args, db, short):
              "|---|---|" + "---|" * (len(SQ_COUNTERS) + 2)]
     avg = {}
     for label, pre in kinds:
-        ds = [c for (d, k), c in per.items() if k.startswith(pre)]
+        ds = [c for (d, k), c in per.items() if k == pre]
         if not ds:
             continue
         a = {cn: sum(c.get(cn, 0.0) for c in ds) / len(ds)
@@ -940,14 +1007,20 @@ def summarize_sq(run, args, db, short):
                      " | ".join(f"{a[cn]:.4g}" for cn in SQ_COUNTERS) +
                      f" | {a['SQ_INSTS_VALU'] / max(a['SQ_WAVES'], 1):.1f} |"
                      f" {a['SQ_WAVE_CYCLES'] / max(a['SQ_WAVES'], 1):.0f} |")
-    if len(avg) == 2:
-        i, e = avg["batched IREBM"], avg["batched EEBM"]
-        lines += ["", f"IREBM / EEBM: VALU instructions "
-                  f"{i['SQ_INSTS_VALU'] / e['SQ_INSTS_VALU']:.2f}x, wave cycles "
-                  f"{i['SQ_WAVE_CYCLES'] / e['SQ_WAVE_CYCLES']:.2f}x, busy "
-                  f"cycles {i['SQ_BUSY_CYCLES'] / e['SQ_BUSY_CYCLES']:.2f}x."]
+    irebm = [a for lab, a in avg.items() if lab.startswith("batched IREBM")]
+    eebm = [a for lab, a in avg.items() if lab.startswith("batched EEBM")]
+    if irebm and eebm:
+        tot = {cn: (sum(a[cn] for a in irebm), sum(a[cn] for a in eebm))
+               for cn in SQ_COUNTERS}
+        lines += ["", "IREBM (all kernels of a launch) / EEBM: VALU "
+                  "instructions "
+                  f"{tot['SQ_INSTS_VALU'][0] / tot['SQ_INSTS_VALU'][1]:.2f}x,"
+                  " wave cycles "
+                  f"{tot['SQ_WAVE_CYCLES'][0] / tot['SQ_WAVE_CYCLES'][1]:.2f}x,"
+                  " busy cycles "
+                  f"{tot['SQ_BUSY_CYCLES'][0] / tot['SQ_BUSY_CYCLES'][1]:.2f}x."]
     lines.append("")
-    fn = "batch_step_kernel_sq_counters_batch512_d2q5_f32.md"
+    fn = "batch_step2_kernel_sq_counters_batch512_d2q5_f32.md"
     with open(os.path.join(ROOT, "profiles", fn), "w") as f:
         f.write("\n".join(lines))
     print(f"wrote profiles/{fn}")

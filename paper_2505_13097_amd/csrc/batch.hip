@@ -13,10 +13,10 @@
 // as the same lattice run alone, IREBM or EEBM alike.  Steps can be
 // captured in a hipGraph; the autotuner picks the tile variant and the
 // grid size.  Under a split two-step variant (tb = 2, IREBM) a launch of
-// two steps is four kernels: the front strips (strip 0 of each instance
-// heated at x = 0) by two column-limited one-step passes through a third
-// state, the quiet pass over the other items, and the full pass over the
-// items the quiet pass flagged (see batch_step2_kernel).  This unit is the
+// two steps is three kernels: the front strips (the first columns of each
+// instance heated at x = 0) on a stream of their own, beside the quiet
+// pass over the other items, then the full pass over the items the quiet
+// pass flagged (see batch_step2_kernel).  This unit is the
 // host side; the kernels and their launches are in launch.hpp
 // (instantiated by k_batch_<mode>.hip).
 #include <hip/hip_runtime.h>
@@ -50,11 +50,9 @@ struct lbm_stefan_batch {
   int2 *items = nullptr;
   StatSlot *slots = nullptr;
   int *flags = nullptr;        // split schedule: one flag per work item
-  StepArgs *fdescs = nullptr;  // split schedule: front pass descriptors
-  int2 *fitems = nullptr;      // split schedule: front pass work items
+  int2 *fitems = nullptr;      // split schedule: front segments
   double *profs = nullptr, *partials = nullptr, *small = nullptr;
   char *state[2] = {nullptr, nullptr};
-  char *mid = nullptr;         // split schedule: step n + 1 of the fronts
   size_t state_bytes = 0;
   bool split_ok = false;       // a split two-step schedule can run
   int64_t nslots = 0, nfitems = 0;
@@ -72,8 +70,8 @@ struct lbm_stefan_batch {
 namespace {
 
 struct BLayout {
-  size_t descs, items, slots, flags, fdescs, fitems, profs, partials, small,
-      stateA, stateB, mid, total;
+  size_t descs, items, slots, flags, fitems, profs, partials, small, stateA,
+      stateB, total;
   size_t state_bytes;
   int64_t max_items, max_fitems, nslots, max_parts, small_len;
   bool split_ok;
@@ -93,20 +91,19 @@ bool front_strip(const lbm_stefan_params &p) {
          (p.wall_profile[0] || p.wall_T[0] >= p.t_m - 20.0 * p.delta);
 }
 
-// front pass items of an nx x ny lattice whose front strip is w columns
-// wide: the one-step tiling fv over columns [0, min(w + 1, nx))
-int64_t front_tiles_x(const Variant &fv, int64_t nx, int w) {
-  return tiles_x_for(fv, std::min<int64_t>(w + 1, nx));
-}
-int64_t front_items(const Variant &fv, int64_t nx, int64_t ny, int w) {
-  return front_tiles_x(fv, nx, w) *
-         ((tiles_y_for(fv, ny) + fv.rows - 1) / fv.rows);
+// front segments (batch_front_kernel items) of a lattice of ny rows
+int64_t front_items(const lbm_stefan_params &p) {
+  const int r = p.storage == LBM_STORE_F64 ? front_rows<double>()
+                                           : front_rows<float>();
+  return (p.ny + r - 1) / r;
 }
 
-// columns of the front strip of an instance under two-step variant v: the
-// whole lattice when it fits one strip, else the first kFrontColumns
+// columns of the front strip of an instance: the whole lattice when it is
+// at most 64 columns wide (the front kernel's window), else the first
+// kFrontColumns
 int front_cols(const Variant &v, int64_t nx) {
-  return nx <= v.bx - 4 ? (int)nx : kFrontColumns;
+  (void)v;
+  return nx <= 64 ? (int)nx : kFrontColumns;
 }
 
 // two-step work items of an instance with a front strip: strips shifted
@@ -170,16 +167,9 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
     L.max_items = std::max(L.max_items, t);
   }
   L.max_fitems = 0;
-  for (int i = 0; i < nv && L.split_ok; ++i) {
-    if (v[i].tb != 2) continue;
-    int64_t t = 0;
-    for (int k = 0; k < count; ++k)
-      if (front_strip(ps[k]))
-        t += front_items(v[kFrontVariant2D], ps[k].nx, ps[k].ny,
-                         front_cols(v[i], ps[k].nx));
-    L.max_fitems = std::max(L.max_fitems, t);
-  }
-  L.nslots = L.max_items + 2 * L.max_fitems;
+  for (int k = 0; k < count && L.split_ok; ++k)
+    if (front_strip(ps[k])) L.max_fitems += front_items(ps[k]);
+  L.nslots = L.max_items + L.max_fitems;
   L.state_bytes = 0;
   L.off.resize(count);
   L.prof_off.resize(count);
@@ -205,8 +195,6 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   o += align256(L.nslots * sizeof(StatSlot));
   L.flags = o;
   o += L.split_ok ? align256(L.max_items * sizeof(int)) : 0;
-  L.fdescs = o;
-  o += L.split_ok ? align256(4 * (size_t)count * sizeof(StepArgs)) : 0;
   L.fitems = o;
   o += align256(L.max_fitems * sizeof(int2));
   L.profs = o;
@@ -219,8 +207,6 @@ BLayout batch_layout(const lbm_stefan_params *ps, int32_t count) {
   o += L.state_bytes;
   L.stateB = o;
   o += L.state_bytes;
-  L.mid = o;
-  o += L.split_ok ? L.state_bytes : 0;
   L.total = o;
   return L;
 }
@@ -244,14 +230,13 @@ void drop_graphs(lbm_stefan_batch_t *b) {
 // descriptors and item table for the current variant; uploads both and
 // zeroes the statistics (the item -> slot map changes with the items).
 // The statistics slots of instance k are contiguous: its work items, then
-// (split schedule) its items of the two front passes.
+// (split schedule) its front segments.
 int build_schedule(lbm_stefan_batch_t *b) {
   int nv;
   const Variant *vt = variants(b->q, &nv);
   const Variant &v = vt[b->variant];
-  const Variant &fv = vt[kFrontVariant2D];
   const bool split = v.tb == 2 && b->split_ok;
-  std::vector<StepArgs> d(b->count), fd(split ? 4 * (size_t)b->count : 0);
+  std::vector<StepArgs> d(b->count);
   std::vector<int2> t, ft;
   std::vector<int> fl;
   t.reserve(b->max_items);
@@ -268,12 +253,14 @@ int build_schedule(lbm_stefan_batch_t *b) {
     fill_args(p, prof, &d[k]);
     d[k].src = b->state[0] + b->off[k];
     d[k].dst = b->state[1] + b->off[k];
-    StepArgs base = d[k];
     set_tiling(&d[k], v);
     const bool front = split && front_strip(p);
     const int w = split ? front_cols(v, p.nx) : 0;  // front strip columns
     if (front) {
-      // strip 0 narrowed to the front strip's w columns
+      // strip 0 narrowed to the front strip's w columns: step n + 1 on
+      // columns [0, w + 1), step n + 2 (and the statistics) on [0, w)
+      d[k].x_lim = (int32_t)std::min<int64_t>(w + 1, p.nx);
+      d[k].x_cnt = (int32_t)std::min<int64_t>(w, p.nx);
       d[k].x_shift = v.bx - 4 - w;
       d[k].tiles_x = (int32_t)((p.nx + d[k].x_shift + v.bx - 5) / (v.bx - 4));
       d[k].nitems = (int32_t)shifted_items(v, p.nx, p.ny);
@@ -286,36 +273,10 @@ int build_schedule(lbm_stefan_batch_t *b) {
       t.push_back(make_int2(k, (int)i));
       if (split) fl.push_back(front && i % d[k].tiles_x == 0 ? 1 : 0);
     }
-    int64_t nf = 0;
-    if (split) {
-      // pass 1: step n + 1 on columns [0, w + 1) into mid (columns below w
-      // counted); pass 2: step n + 2 on columns [0, w) from mid
-      set_tiling(&base, fv);
-      base.tiles_x = (int32_t)front_tiles_x(fv, p.nx, w);
-      base.nitems = (int32_t)front_items(fv, p.nx, p.ny, w);
-      base.per_xcd = (base.nitems + 7) / 8;
-      nf = front ? base.nitems : 0;
-      const int32_t lim1 = (int32_t)std::min<int64_t>(w + 1, p.nx);
-      const int32_t lim2 = (int32_t)std::min<int64_t>(w, p.nx);
-      char *mid = b->mid + b->off[k];
-      for (int par = 0; par < 2; ++par) {
-        StepArgs &f1 = fd[(size_t)par * b->count + k];
-        StepArgs &f2 = fd[(size_t)(2 + par) * b->count + k];
-        f1 = f2 = base;
-        f1.src = b->state[par] + b->off[k];
-        f1.dst = mid;
-        f1.x_lim = lim1;
-        f1.x_cnt = lim2;
-        f1.slots = b->slots + sbase + nt;
-        f2.src = mid;
-        f2.dst = b->state[par ^ 1] + b->off[k];
-        f2.x_lim = f2.x_cnt = lim2;
-        f2.slots = b->slots + sbase + nt + nf;
-      }
-      for (int64_t i = 0; i < nf; ++i) ft.push_back(make_int2(k, (int)i));
-    }
-    b->nitems_inst[k] = nt + 2 * nf;
-    sbase += nt + 2 * nf;
+    const int64_t nf = front ? front_items(p) : 0;
+    for (int64_t i = 0; i < nf; ++i) ft.push_back(make_int2(k, (int)i));
+    b->nitems_inst[k] = nt + nf;
+    sbase += nt + nf;
   }
   b->nitems = (int64_t)t.size();
   b->nfitems = (int64_t)ft.size();
@@ -325,8 +286,6 @@ int build_schedule(lbm_stefan_batch_t *b) {
                          hipMemcpyHostToDevice, b->stream));
   if (split) {
     BCHK(b, hipMemcpyAsync(b->flags, fl.data(), fl.size() * sizeof(int),
-                           hipMemcpyHostToDevice, b->stream));
-    BCHK(b, hipMemcpyAsync(b->fdescs, fd.data(), fd.size() * sizeof(StepArgs),
                            hipMemcpyHostToDevice, b->stream));
     if (!ft.empty())
       BCHK(b, hipMemcpyAsync(b->fitems, ft.data(), ft.size() * sizeof(int2),
@@ -345,7 +304,7 @@ int build_schedule(lbm_stefan_batch_t *b) {
 
 // one launch from buffer `parity`: one step, or two under a two-step
 // variant (one if two = false); two steps of a split schedule are the
-// front passes, the quiet pass and the full pass over flagged items
+// front kernel, the quiet pass and the full pass over flagged items
 hipError_t launch_batch(const lbm_stefan_batch_t *b, hipStream_t stream,
                         int parity, bool two = true) {
   int nv;
@@ -361,27 +320,19 @@ hipError_t launch_batch(const lbm_stefan_batch_t *b, hipStream_t stream,
   L.two = two;
   if (!(v.tb == 2 && b->split_ok && two))
     return batch_launch(b->mode, b->q, b->storage, L, v, stream);
-  // the front passes (F1 then F2, latency-bound) on the side stream, the
-  // quiet pass (bandwidth-bound) beside them; the full pass over flagged
-  // items after both
+  // the front kernel (latency-bound: the Newton solves) on the side
+  // stream, the quiet pass (bandwidth-bound) beside it; the full pass over
+  // flagged items after both
   const bool fr = b->nfitems > 0;
   if (fr) {
     hipError_t e = hipEventRecord(b->fork, stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->fork, 0);
     if (e != hipSuccess) return e;
-    BatchLaunch F;
+    BatchLaunch F = L;
     F.items = b->fitems;
     F.nitems = b->nfitems;
-    F.cus = b->cus;
-    F.blocks_per_cu = 0;
-    F.parity = 0;  // the descriptors of each parity name src and dst
-    F.two = false;
-    F.lim = true;
-    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-      F.descs = b->fdescs + (size_t)(2 * pass + parity) * b->count;
-      e = batch_launch(b->mode, b->q, b->storage, F, vt[kFrontVariant2D],
-                       b->side);
-    }
+    F.front = true;
+    e = batch_launch(b->mode, b->q, b->storage, F, v, b->side);
     if (e == hipSuccess) e = hipEventRecord(b->join, b->side);
     if (e != hipSuccess) return e;
   }
@@ -489,9 +440,7 @@ int lbm_stefan_batch_init(const lbm_stefan_params *ps, int32_t count,
   b->nslots = L.nslots;
   if (L.split_ok) {
     b->flags = (int *)(ws + L.flags);
-    b->fdescs = (StepArgs *)(ws + L.fdescs);
     b->fitems = (int2 *)(ws + L.fitems);
-    b->mid = ws + L.mid;
   }
   b->profs = (double *)(ws + L.profs);
   b->partials = (double *)(ws + L.partials);

@@ -61,10 +61,7 @@ constexpr int kDefaultVariant1D = 0;
 constexpr int kResidentVariant1D = 4;
 constexpr int kDefaultVariant2D = 3;
 // split two-step schedule: the front strip of an instance heated at x = 0
-// is its first kFrontColumns columns, advanced by the one-step variant
-// kFrontVariant2D (64 x 4 tiles, one node per thread, 4 tile rows per
-// block, non-temporal stores)
-constexpr int kFrontVariant2D = 16;
+// is its first kFrontColumns columns (batch_front_kernel: at most 63)
 constexpr int kFrontColumns = 60;
 
 inline int64_t tiles_x_for(const Variant &v, int64_t nx) {

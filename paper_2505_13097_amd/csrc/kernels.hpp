@@ -84,10 +84,8 @@ __device__ __forceinline__ void block_stats_to_slot(const NodeStats &st,
 // One tile (tx, ty) of the lattice described by A, from state src to
 // state dst: on interior tiles all loads of the thread's nodes first
 // (memory-level parallelism), then the updates.  Statistics go into st;
-// returns whether the tile took the interior path.  LIM (the front strips
-// of the split two-step schedule): only columns x < A.x_lim are computed
-// and only those with x < A.x_cnt counted.
-template <int Q, typename S, int NPT, int MODE, bool NT, bool LIM = false>
+// returns whether the tile took the interior path.
+template <int Q, typename S, int NPT, int MODE, bool NT>
 __device__ __forceinline__ bool step_tile(const StepArgs &A,
                                           gptr<const S> __restrict__ src,
                                           gptr<S> __restrict__ dst, int tx,
@@ -96,7 +94,6 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
   const int TW = bx * NPT;
   const int x0 = tx * TW, y0 = ty * by;
   const bool fast = x0 >= 1 && x0 + TW <= A.nx - 1 &&
-                    (!LIM || x0 + TW <= A.x_cnt) &&
                     (Q == 3 || (y0 >= 1 && y0 + by <= A.ny - 1));
   // a wave lies in one row of the tile (bx is a multiple of 64)
   const int y = y0 + __builtin_amdgcn_readfirstlane((int)threadIdx.y);
@@ -126,22 +123,10 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
       const bool cm = k == 0 && x0 == 0;
       const int x = cm ? (tid >> lb) : x0 + (int)threadIdx.x + k * bx;
       const int yj = cm ? y0 + (tid & (by - 1)) : y;
-      if (x < (LIM ? A.x_lim : A.nx) && yj < A.ny) {
+      if (x < A.nx && yj < A.ny) {
         NodeLoad<Q, S> L;
         load_node<Q, S, false, neumann_mode(MODE)>(A, src, x, yj, L);
-        if constexpr (LIM) {
-          NodeStats one;
-          update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, one);
-          if (x < A.x_cnt) {
-            st.max_it = max(st.max_it, one.max_it);
-            st.nonconv += one.nonconv;
-            st.max_res = fmax(st.max_res, one.max_res);
-            st.flux_in += one.flux_in;
-            st.flux_out += one.flux_out;
-          }
-        } else {
-          update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, st);
-        }
+        update_node<Q, S, MODE, false, NT>(A, dst, x, yj, L, st);
       }
     }
   }
@@ -154,7 +139,7 @@ __device__ __forceinline__ bool step_tile(const StepArgs &A,
 // block's start-up (descriptor and slot reads) and statistics reduction
 // are paid once per item.  One statistics slot per item.
 template <int Q, typename S, int NPT, int MODE, bool NT = false,
-          bool LOOP = false, bool LIM = false>
+          bool LOOP = false>
 __device__ __forceinline__ void step_item(const StepArgs &A,
                                           gptr<const S> __restrict__ src,
                                           gptr<S> __restrict__ dst, int item,
@@ -171,8 +156,8 @@ __device__ __forceinline__ void step_item(const StepArgs &A,
     // spill them into vector registers (lower occupancy).
     int z = 0;
     asm volatile("" : "+s"(z));
-    fast &= step_tile<Q, S, NPT, MODE, NT, LIM>((&A)[z], src, dst, tx,
-                                                ty0 + r, st);
+    fast &= step_tile<Q, S, NPT, MODE, NT>((&A)[z], src, dst, tx, ty0 + r,
+                                           st);
   }
   // read after the loop: a prefetched slot would stay live across it
   StatSlot pre{};
@@ -409,6 +394,115 @@ __device__ __forceinline__ bool step2_body(const StepArgs &A,
     block_stats_to_slot<false>(st, false, pre, slot);
   }
   return any;
+}
+
+// ---------------------------------------------------------------------
+// front strips of the split two-step schedule (batched form)
+
+template <int Q, typename S, bool NT>
+__device__ __forceinline__ void store_values(const StepArgs &A,
+                                             gptr<S> __restrict__ dst, int x,
+                                             int y, const S v[Q]) {
+  const gptr<S> row = dst + (int64_t)y * A.nx;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const gptr<S> p = (row + i * A.plane) + (uint32_t)x;
+    if (NT) __builtin_nontemporal_store(v[i], p);
+    else *p = v[i];
+  }
+}
+
+__device__ __forceinline__ void merge_stats(NodeStats &st,
+                                            const NodeStats &one) {
+  st.max_it = max(st.max_it, one.max_it);
+  st.nonconv += one.nonconv;
+  st.max_res = fmax(st.max_res, one.max_res);
+  st.flux_in += one.flux_in;
+  st.flux_out += one.flux_out;
+}
+
+// rows of a front segment: R + 2 rows of step n + 1 fill 256 threads
+// evenly (4 rows of 64 columns per pass)
+template <typename S>
+constexpr int front_rows() { return sizeof(S) == 4 ? 14 : 6; }
+
+// Two steps of segment `seg` (front_rows<S>() rows) of an instance's front
+// strip, one block of 256 threads: step n + 1 of the segment's rows and of
+// one halo row on each side (recomputed by the neighbouring segments as
+// well) on columns [0, A.x_lim), from the global state into LDS, then,
+// after one barrier, step n + 2 of the segment's rows on columns
+// [0, A.x_cnt) from LDS into dst.  One node per thread at a time (the slow
+// path's loads), whole rows per wave.  No third state and no wait for the
+// other segments between the two steps.  The strip lies at the x = 0 wall
+// of a lattice that is not periodic along x and is at most 64 columns
+// wide (both checked by the host), so LDS column x is lattice column x
+// and the masked pulls from x = -1 (and from x = nx when the strip is the
+// whole lattice) are the only reads outside the columns computed.
+// Statistics count each node once per step (own rows, columns below
+// x_cnt).
+template <int Q, typename S, int MODE>
+__device__ __forceinline__ void front2_body(const StepArgs &A,
+                                            gptr<const S> __restrict__ src,
+                                            gptr<S> __restrict__ dst, int seg,
+                                            StatSlot *slot) {
+  constexpr int R = front_rows<S>(), RR = R + 2, W = 64;
+  __shared__ S buf[RR][Q][W];
+  const int tid = (int)threadIdx.x;
+  const int ny = A.ny;
+  const bool py = A.periodic_y != 0;
+  const int y0 = seg * R, y1 = min(y0 + R, ny);
+  NodeStats st;
+  // step n + 1: LDS row r holds lattice row y0 - 1 + r
+  for (int n = tid; n < RR * W; n += 256) {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    const StepArgs &Ai = (&A)[z];
+    const int r = n >> 6, x = n & (W - 1);
+    const int yy = y0 - 1 + r;
+    int gy = yy;
+    if (yy < 0 || yy >= ny) gy = py ? (yy % ny + ny) % ny : -1;
+    if (x < Ai.x_lim && gy >= 0 && yy <= y1) {
+      NodeLoad<Q, S> L;
+      load_node<Q, S, false>(Ai, src, x, gy, L);
+      NodeStats one;
+      S v[Q];
+      update_values<Q, S, MODE, false>(Ai, x, gy, L, one, v);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) buf[r][j][x] = v[j];
+      if (yy >= y0 && yy < y1 && x < Ai.x_cnt) merge_stats(st, one);
+    }
+  }
+  __syncthreads();
+  // step n + 2 from LDS
+  for (int n = tid; n < R * W; n += 256) {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    const StepArgs &Ai = (&A)[z];
+    const int r = n >> 6, x = n & (W - 1);
+    const int y = y0 + r;
+    if (x < Ai.x_cnt && y < y1) {
+      NodeLoad<Q, S> L;
+      node_masks<Q>(Ai, x, y, L.known, L.out);
+      L.mirror = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) L.own[j] = buf[r + 1][j][x];
+      L.pull[0] = L.own[0];
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const int ex = cx<Q>(i), ey = cy<Q>(i);
+        const S v = buf[r + 1 - ey][i][(x - ex) & (W - 1)];
+        L.pull[i] = (L.known >> i & 1u) ? v : (S)0;
+      }
+      NodeStats one;
+      S v[Q];
+      update_values<Q, S, MODE, false>(Ai, x, y, L, one, v);
+      store_values<Q, S, true>(Ai, dst, x, y, v);
+      merge_stats(st, one);
+    }
+  }
+  StatSlot pre{};
+  if (tid == 0) pre = *slot;
+  block_stats_to_slot<false>(st, false, pre, slot);
 }
 
 // Blocks are numbered strip-fastest within a segment of rows, and each

@@ -23,8 +23,7 @@ namespace {
 
 // one work item of the table: items[t] = (instance, item index within
 // it); the descriptor is block-uniform and read in place with scalar loads
-template <int Q, typename S, int NPT, int MODE, bool NT, bool LOOP,
-          bool LIM = false>
+template <int Q, typename S, int NPT, int MODE, bool NT, bool LOOP>
 __device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
                                            const int2 *__restrict__ items,
                                            int t, int parity) {
@@ -34,21 +33,19 @@ __device__ __forceinline__ void batch_item(const StepArgs *__restrict__ descs,
   const StepArgs &A = descs[inst];
   const auto src = to_global((const S *)(parity ? A.dst : A.src));
   const auto dst = to_global((S *)(parity ? A.src : A.dst));
-  step_item<Q, S, NPT, MODE, NT, LOOP, LIM>(A, src, dst, item,
-                                            A.slots + item);
+  step_item<Q, S, NPT, MODE, NT, LOOP>(A, src, dst, item, A.slots + item);
 }
 
 // one block per work item, the blocks of XCD k taking the k-th contiguous
-// chunk of the table (LIM: the column-limited front strips of the split
-// two-step schedule, see batch_step2_kernel)
-template <int Q, typename S, int NPT, int MODE, bool NT, bool LIM = false>
+// chunk of the table
+template <int Q, typename S, int NPT, int MODE, bool NT>
 __global__ __launch_bounds__(256) void batch_step_kernel(
     const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
     int32_t nitems, int32_t parity, int32_t reverse) {
   const int chunk = (nitems + 7) >> 3;
   const int b = (int)blockIdx.x;
   if ((b & 7) * chunk + (b >> 3) >= nitems) return;
-  batch_item<Q, S, NPT, MODE, NT, false, LIM>(
+  batch_item<Q, S, NPT, MODE, NT, false>(
       descs, items, xcd_item(b, chunk, nitems, reverse), parity);
 }
 
@@ -67,6 +64,26 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(
                                           reverse ? nitems - 1 - t : t, parity);
 }
 
+// the front strips of the split schedule (front2_body): one block per
+// segment of an instance's strip, XCD-contiguous chunks; the strip's
+// column limits are the descriptor's x_lim and x_cnt and its statistics
+// slots follow the instance's two-step items
+template <int Q, typename S, int MODE>
+__global__ __launch_bounds__(256) void batch_front_kernel(
+    const StepArgs *__restrict__ descs, const int2 *__restrict__ items,
+    int32_t nitems, int32_t parity) {
+  const int chunk = (nitems + 7) >> 3;
+  const int b = (int)blockIdx.x;
+  if ((b & 7) * chunk + (b >> 3) >= nitems) return;
+  const int2 e = items[xcd_item(b, chunk, nitems, 0)];
+  const int inst = __builtin_amdgcn_readfirstlane(e.x);
+  const int seg = __builtin_amdgcn_readfirstlane(e.y);
+  const StepArgs &A = descs[inst];
+  const auto src = to_global((const S *)(parity ? A.dst : A.src));
+  const auto dst = to_global((S *)(parity ? A.src : A.dst));
+  front2_body<Q, S, MODE>(A, src, dst, seg, A.slots + A.nitems + seg);
+}
+
 // two steps (or one) per launch: one block per item of the two-step
 // tiling (a strip of one segment of one instance), XCD-contiguous chunks.
 //
@@ -76,8 +93,9 @@ __global__ __launch_bounds__(256) void batch_persistent_kernel(
 // of each pass), while nearly every node of a melting problem is quiet
 // (far below the band: a closed form).  So a two-step launch is split by
 // work item, with flags[t] per item of the table:
-//   flags 1: a front strip, advanced by two column-limited one-step
-//            passes of batch_step_kernel (LIM) through a third state;
+//   flags 1: a front strip, advanced by batch_front_kernel (both steps
+//            per segment of rows, the first into LDS) on a stream of its
+//            own, beside the quiet pass;
 //   flags 0: SPLIT = 1, the kernel built for quiet nodes only (no Newton
 //            code, 6 waves per SIMD in FP32 D2Q5); an item with a node
 //            (halo included) that is not quiet is set to flags 2;
@@ -168,19 +186,15 @@ hipError_t launch_batch_t(const BatchLaunch &b, const Variant &v,
                           hipStream_t stream) {
   const int64_t chunk = (b.nitems + 7) / 8;
   const int32_t nt = (int32_t)b.nitems;
-  if (b.lim) {
-    // front strips of the split schedule: one block per item, the front
-    // variant's shape only
-    if (v.tb || v.npt > 2 || !v.nt || b.blocks_per_cu > 0)
+  if (b.front) {
+    if constexpr (Q == 3 || MODE == kEebm) {
       return hipErrorInvalidValue;
-    dim3 grid((unsigned)(8 * std::max<int64_t>(chunk, 1))), block(v.bx, v.by);
-    if (v.npt == 1)
-      batch_step_kernel<Q, S, 1, MODE, true, true>
-          <<<grid, block, 0, stream>>>(b.descs, b.items, nt, b.parity, 0);
-    else
-      batch_step_kernel<Q, S, 2, MODE, true, true>
-          <<<grid, block, 0, stream>>>(b.descs, b.items, nt, b.parity, 0);
-    return hipGetLastError();
+    } else {
+      dim3 grid((unsigned)(8 * std::max<int64_t>(chunk, 1))), block(256);
+      batch_front_kernel<Q, S, MODE>
+          <<<grid, block, 0, stream>>>(b.descs, b.items, nt, b.parity);
+      return hipGetLastError();
+    }
   }
   if (v.tb) {
     if constexpr (Q == 3) {

@@ -114,7 +114,8 @@ struct BatchLaunch {
                           // pass over items flagged 0, 2 the full pass over
                           // items flagged 2 (batch_step2_kernel)
   int *flags = nullptr;   // device: one flag per work item (split > 0)
-  bool lim = false;       // the column-limited one-step front pass
+  bool front = false;     // the front strips' kernel (items: instance,
+                          // segment of front rows)
 };
 
 template <int MODE>

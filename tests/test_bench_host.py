@@ -66,3 +66,34 @@ def test_cpu_baseline_strips_equal_single_thread():
     assert r["cores"] == 4 and r["kind"] == "oracle" and r["value"] > 0
     r = bench.cpu_baseline(synth.planar_2d(n=64, ny=50), steps=5, threads=3)
     assert r["strips_equal_single_thread"] is True
+
+
+def test_batch_kernel_names_by_variant():
+    """The trace names the profile summary looks up for a batched launch:
+    split two-step variants run the front kernel, the quiet pass and the
+    full pass (IREBM) or the plain two-step kernel (EEBM)."""
+    import bench
+    k = bench.batch_kernels("128x2/t2s/r96/nt")
+    assert k == {"front": "batch_front_kernel<5, float, 0>",
+                 "quiet": "batch_step2_kernel<5, float, 0, 2, 128, 1>",
+                 "full": "batch_step2_kernel<5, float, 0, 2, 128, 2>"}
+    assert bench.batch_kernels("128x2/t2s/r96/nt", 2) == {
+        "two-step": "batch_step2_kernel<5, float, 2, 2, 128, 0>"}
+    assert bench.batch_kernels("128x4/t2/r32/nt") == {
+        "two-step": "batch_step2_kernel<5, float, 0, 4, 128, 0>"}
+    assert bench.batch_kernels("128x4/npt2/r16/nt") == {
+        "one-step": "batch_step_kernel<5, float, 2, 0, true>"}
+
+
+def test_batch_walls_from_trace_rows():
+    """Wall time of a launch: first start to last end of its kernels."""
+    import sqlite3
+    import bench
+    c = sqlite3.connect(":memory:")
+    c.execute("create table kernels (name text, start int, end int)")
+    rows = [("f", 0, 900), ("q", 10, 1000), ("x", 1005, 1020),
+            ("f", 2000, 2500), ("q", 2001, 3000), ("x", 3002, 3010)]
+    c.executemany("insert into kernels values (?, ?, ?)", rows)
+    w = bench.batch_walls(c, lambda n: n, {"front": "f", "quiet": "q",
+                                           "full": "x"})
+    assert w == [1.02, 1.01]

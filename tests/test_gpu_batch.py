@@ -225,6 +225,7 @@ def _split_mix(storage):
 
 
 @pytest.mark.parametrize("name", ["128x2/t2s/r16/nt", "128x4/t2s/r32/nt",
+                                  "128x2/t2s/r96/nt",
                                   "128x2/t2s/r64/nt"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_split_two_step_schedule_equals_single_steps(name, storage):

@@ -325,86 +325,116 @@ def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None,
 
 
 # the split two-step schedule of the batched form: front strips of
-# FRONT_COLUMNS columns (the whole lattice if it fits one strip) advanced
-# by the one-step tiling FRONT (bx, by, npt, tile rows per block) with
-# column limits (kFrontColumns and kFrontVariant2D of host_util.hpp)
+# FRONT_COLUMNS columns (the whole lattice if at most 64 columns wide),
+# both steps by batch_front_kernel (front2_body) in segments of
+# FRONT_ROWS[storage bytes] rows (kFrontColumns of host_util.hpp,
+# front_rows of kernels.hpp)
 FRONT_COLUMNS = 60
-FRONT = (64, 4, 1, 4)
+FRONT_ROWS = {4: 14, 8: 6}
 
 
-def replay_front(q, nx, ny, bx, by, npt, rows, x_lim, x_cnt):
-    """The column-limited one-step pass (step_tile with LIM): returns the
-    count of stores and of statistics contributions per node; every node
-    inside the lattice."""
-    tw = bx * npt
-    tiles_x = -(-x_lim // tw)
-    tiles_y = -(-ny // by)
-    nitems = tiles_x * (-(-tiles_y // rows))
+def front_cols(nx):
+    return nx if nx <= 64 else FRONT_COLUMNS
+
+
+def replay_front(q, nx, ny, py, rows, x_lim, x_cnt):
+    """front2_body over every segment: returns the count of step n + 2
+    stores and of statistics contributions per node at each step; checks
+    every global load and store inside the lattice, every LDS index inside
+    the buffer, and that each LDS value a step n + 2 update pulls (and is
+    not masked) was computed at step n + 1 in the same block."""
+    W, RR = 64, rows + 2
+    assert (RR * W) % 256 == 0 and x_lim <= W and x_cnt <= x_lim <= nx
+    dirs = _dirs2(q)
     stored = np.zeros((ny, nx), dtype=int)
-    counted = np.zeros((ny, nx), dtype=int)
-    lb = by.bit_length() - 1
-    assert 1 << lb == by and bx % 64 == 0 and bx * by <= 256
-    for item in range(nitems):
-        tx, ty0 = item % tiles_x, (item // tiles_x) * rows
-        for r in range(min(rows, tiles_y - ty0)):
-            x0, y0 = tx * tw, (ty0 + r) * by
-            fast = (x0 >= 1 and x0 + tw <= nx - 1 and x0 + tw <= x_cnt and
-                    y0 >= 1 and y0 + by <= ny - 1)
-            for ty in range(by):
-                for t in range(bx):
-                    for k in range(npt):
-                        if fast:
-                            x, y = x0 + t + k * bx, y0 + ty
-                        else:
-                            # the x = 0 tile deals its first bx columns
-                            # out column by column
-                            tid = t + ty * bx
-                            cm = k == 0 and x0 == 0
-                            x = tid >> lb if cm else x0 + t + k * bx
-                            y = y0 + (tid & (by - 1)) if cm else y0 + ty
-                            if not (x < x_lim and y < ny):
-                                continue
-                        assert 0 <= x < nx and 0 <= y < ny
-                        stored[y, x] += 1
-                        counted[y, x] += 1 if (fast or x < x_cnt) else 0
-    return stored, counted
+    counted1 = np.zeros((ny, nx), dtype=int)
+    for seg in range(-(-ny // rows)):
+        y0, y1 = seg * rows, min(seg * rows + rows, ny)
+        have = {}
+        for n in range(RR * W):
+            r, x = n >> 6, n & (W - 1)
+            yy = y0 - 1 + r
+            gy = yy if 0 <= yy < ny else (yy % ny if py else -1)
+            if x < x_lim and gy >= 0 and yy <= y1:
+                assert 0 <= x < nx and 0 <= gy < ny     # load_node
+                assert 0 <= r < RR
+                have[(r, x)] = gy
+                if y0 <= yy < y1 and x < x_cnt:
+                    counted1[gy, x] += 1
+        for n in range(rows * W):
+            r, x = n >> 6, n & (W - 1)
+            y = y0 + r
+            if not (x < x_cnt and y < y1):
+                continue
+            for (ex, ey) in dirs:
+                sx, sy = x - ex, y - ey
+                inside = 0 <= sx < nx and (0 <= sy < ny or py)
+                lr, lc = r + 1 - ey, (x - ex) & (W - 1)
+                assert 0 <= lr < RR and 0 <= lc < W
+                if inside:
+                    assert have.get((lr, lc)) == sy % ny, (x, y, ex, ey)
+            assert 0 <= x < nx and 0 <= y < ny             # store
+            stored[y, x] += 1
+    return stored, counted1
 
 
 @pytest.mark.parametrize("q", [5, 9])
 def test_split_schedule_updates_every_node_once(names, q):
-    """Front passes plus the shifted two-step strips (the quiet and full
-    passes skip strip 0) store every node of step n + 2 exactly once and
-    count it once per step; pass 1 computes every step n + 1 node pass 2
-    pulls from."""
+    """The front kernel plus the shifted two-step strips (the quiet and
+    full passes skip strip 0) store every node of step n + 2 exactly once
+    and count it once per step."""
     t2s = [n for n in names[q] if "/t2s" in n]
     assert t2s
-    fb, fby, fnpt, frows = FRONT
     for name in t2s:
         win, by, rows = _parse_t2(name)
         for (nx, ny) in SHAPES2 + [(59, 7), (60, 9), (61, 5), (62, 66),
+                                   (64, 30), (65, 14), (124, 13),
                                    (183, 10), (184, 3), (185, 33)]:
-            # a lattice that fits one strip is all front strip
-            wf = nx if nx <= win - 4 else FRONT_COLUMNS
+            wf = front_cols(nx)
             shift = win - 4 - wf
             for py in (False, True):
-                lim1, lim2 = min(wf + 1, nx), min(wf, nx)
-                s1, c1 = replay_front(q, nx, ny, fb, fby, fnpt, frows,
-                                      lim1, lim2)
-                s2, c2 = replay_front(q, nx, ny, fb, fby, fnpt, frows,
-                                      lim2, lim2)
-                assert np.all(s1[:, :lim1] == 1) and not s1[:, lim1:].any()
-                assert np.all(c1[:, :lim2] == 1) and not c1[:, lim2:].any()
-                # pass 2's pulls (x - 1 .. x + 1) inside what pass 1 wrote
-                assert lim2 + 1 <= lim1 or lim1 == nx
+                for sb in (4, 8):
+                    s2, c1 = replay_front(q, nx, ny, py, FRONT_ROWS[sb],
+                                          min(wf + 1, nx), min(wf, nx))
+                    assert np.all(c1[:, :wf] == 1) and not c1[:, wf:].any()
                 out = np.zeros((ny, nx), dtype=int)
                 replay_t2(q, nx, ny, win, by, rows, False, py, True,
                           shift=shift, skip_strip0=True, out=out)
-                assert not out[:, :lim2].any()
+                assert not out[:, :wf].any()
                 assert np.all(out + s2 == 1), (name, nx, ny)
-                assert np.all(out + c2 == 1)
                 # odd single steps: the full kernel over every strip
                 replay_t2(q, nx, ny, win, by, rows, False, py, False,
                           shift=shift)
+
+
+def test_front_replay_detects_a_short_halo():
+    """The replay itself: without the halo row above, a step n + 2 pull
+    would read a value not computed in the block."""
+    replay_front(5, 40, 20, False, 14, 21, 20)
+    with pytest.raises(AssertionError):
+        replay_front_short(5, 40, 20, False, 14, 21, 20)
+
+
+def replay_front_short(q, nx, ny, py, rows, x_lim, x_cnt):
+    """replay_front with step n + 1 computed for the segment's rows and the
+    row below only (a planted mistake)"""
+    W = 64
+    dirs = _dirs2(q)
+    for seg in range(-(-ny // rows)):
+        y0, y1 = seg * rows, min(seg * rows + rows, ny)
+        have = {}
+        for r in range(rows + 1):
+            for x in range(min(x_lim, W)):
+                yy = y0 - 1 + r
+                if 0 <= yy < ny:
+                    have[(r, x)] = yy
+        for r in range(y1 - y0):
+            for x in range(x_cnt):
+                y = y0 + r
+                for (ex, ey) in dirs:
+                    sx, sy = x - ex, y - ey
+                    if 0 <= sx < nx and 0 <= sy < ny:
+                        assert have.get((r + 1 - ey, (x - ex) & 63)) == sy
 
 
 SHAPES2 = [(3, 3), (5, 4), (3, 40), (124, 5), (125, 6), (126, 3), (252, 9),
