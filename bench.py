@@ -126,7 +126,7 @@ DEFAULT_VARIANTS = {
     "batched": "128x2/t2s/r96/nt",
     "adjoint": "256x1/npt1",
     "cube3d_19": "256x1/npt2/z4/nt",
-    "cube3d_7": "256x1/npt2/z8/nt",
+    "cube3d_7": "64x4/npt1/z8/nt/s",
 }
 
 
@@ -354,6 +354,21 @@ def traffic_sweep3(n=CUBE3D_N):
         torch.cuda.empty_cache()
 
 
+def cube3d_kernels(q, vname, mode=0):
+    """Trace names of the kernels one 3D step runs under variant vname on
+    the cube heated at x = 0 (IREBM mode 0, EEBM mode 2), by role: a split
+    variant runs the front strip (variant 0's tiling), the quiet pass and
+    the full pass (IREBM)."""
+    m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?(/s)?", vname)
+    npt = int(m.group(3))
+    nt = "true" if m.group(5) else "false"
+    base = f"step3_kernel<{q}, float, {npt}, {mode}, {nt}"
+    if m.group(6) and mode != 2:
+        return {"front": f"step3_kernel<{q}, float, 1, {mode}, true, 0>",
+                "quiet": base + ", 1>", "full": base + ", 2>"}
+    return {"step": base + ", 0>"}
+
+
 def summarize_profiles3(run, args):
     """profiles/ summaries of the 3D step kernel from run/prof3d (kernel
     trace of bench.py --cube3d-only with a fixed variant) and
@@ -377,20 +392,28 @@ def summarize_profiles3(run, args):
         m = re.match(r"step3_kernel<(\d+), float, \d, (\d+),", k)
         return (int(m.group(1)), int(m.group(2))) if m else None
 
+    def vdefault(q):
+        if args.variant3d >= 0:
+            return variant_names(q, "f32")[args.variant3d]
+        return DEFAULT_VARIANTS[f"cube3d_{q}"]
+
     c = db("prof3d")
     trace = [(short(r[0]), r[1], r[2], r[3], r[4]) for r in c.execute(
         "select name, total_calls, total_duration, average, percentage "
         "from top_kernels")]
-    by = collections.defaultdict(list)
-    for name, d in c.execute("select name, duration from kernels "
-                             "order by dispatch_id"):
-        by[short(name)].append(d / 1000.0)
     steps = args.steps3d
+    # time per step of the timed launches (the last `steps` of each role;
+    # a split step's kernels overlap on two streams: first start to last
+    # end)
     avg = {}
-    for k, ds in by.items():
-        t = kq(k)
-        if t is not None:
-            avg.setdefault(t, []).append(sum(ds[-steps:]) / steps)
+    roles = {}
+    for q in (19, 7):
+        for mode in (0, 2):
+            ks = cube3d_kernels(q, vdefault(q), mode)
+            w = batch_walls(c, short, ks)[-steps:]
+            if w:
+                avg[(q, mode)] = sum(w) / len(w)
+                roles[(q, mode)] = ks
 
     def counters(sub, cn):
         rows = db(sub).execute(
@@ -410,14 +433,21 @@ def summarize_profiles3(run, args):
         names = variant_names(q, "f32")
         sf = [v for k, v in F if kq(k) == (q, 0)]
         sw = [v for k, v in W if kq(k) == (q, 0)]
-        if len(sf) != SWEEP_STEPS * len(names) or len(sw) != len(sf):
-            raise SystemExit(f"D3Q{q}: expected {SWEEP_STEPS * len(names)} "
+        # dispatches per step: three for a split variant (front strip, quiet
+        # and full pass), else one
+        per = [3 if nm.endswith("/s") else 1 for nm in names]
+        need = SWEEP_STEPS * sum(per)
+        if len(sf) != need or len(sw) != len(sf):
+            raise SystemExit(f"D3Q{q}: expected {need} "
                              f"dispatches, found {len(sf)} / {len(sw)}")
         alg = p.nodes * bytes_per_node(p)
         rec = {}
+        o = 0
         for i, nm in enumerate(names):
-            fk = sum(sf[i * SWEEP_STEPS:(i + 1) * SWEEP_STEPS]) / SWEEP_STEPS
-            wk = sum(sw[i * SWEEP_STEPS:(i + 1) * SWEEP_STEPS]) / SWEEP_STEPS
+            n_ = SWEEP_STEPS * per[i]
+            fk = sum(sf[o:o + n_]) / SWEEP_STEPS
+            wk = sum(sw[o:o + n_]) / SWEEP_STEPS
+            o += n_
             b = fk * 1024 * fs + wk * 1024 * ws
             rec[nm] = {"fetch_kib_per_dispatch": round(fk, 1),
                        "write_kib_per_dispatch": round(wk, 1),
@@ -425,10 +455,11 @@ def summarize_profiles3(run, args):
                        "bytes_per_lattice_update": round(b / p.nodes, 3),
                        "ratio_to_algorithmic": round(b / alg, 4)}
         lattices[p.name] = rec
-    vname = {q: variant_names(q, "f32")[args.variant3d] for q in (19, 7)}
+    vname = {q: vdefault(q) for q in (19, 7)}
     trace_cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof3d -o p3"
-                 f" -- python bench.py --cube3d-only --no-autotune"
-                 f" --variant3d {args.variant3d} --steps3d {steps}")
+                 f" -- python bench.py --cube3d-only"
+                 + (f" --variant3d {args.variant3d}" if args.variant3d >= 0
+                    else "") + f" --steps3d {steps}")
     pmc_cmd = ("rocprofv3 --pmc {C} -d gpurun_out/{D} -o {O} -- python "
                "bench.py --traffic-sweep-3d")
     lines = [f"# step3_kernel — {args.cube3d_n}^3 cube heated at one face, "
@@ -441,14 +472,16 @@ def summarize_profiles3(run, args):
     for r in trace[:12]:
         lines.append(f"| {r[0]} | {r[1]} | {r[2]:.0f} | {r[3]:.1f} | "
                      f"{r[4]:.2f} |")
-    lines += ["", "Timed launches (the last " + str(steps) + " of each "
-              "kernel; mode 0 IREBM, 2 EEBM):", "",
-              "| lattice | mode | variant | average us | algorithmic GB/s |",
-              "|---|---|---|---|---|"]
-    for (q, mode), vals in sorted(avg.items(), reverse=True):
+    lines += ["", "Timed steps (the last " + str(steps) + " of each "
+              "lattice and scheme; mode 0 IREBM, 2 EEBM; a split step's "
+              "time runs from its first kernel's start to its last kernel's "
+              "end, from the trace's timestamps):", "",
+              "| lattice | mode | variant | kernels | us per step | "
+              "algorithmic GB/s |", "|---|---|---|---|---|---|"]
+    for (q, mode), a in sorted(avg.items(), reverse=True):
         p = S.cavity_3d(n=args.cube3d_n, q=q)
-        a = vals[-1]
-        lines.append(f"| D3Q{q} | {mode} | {vname[q]} | {a:.1f} | "
+        ks = ", ".join(f"{r}: {k}" for r, k in roles[(q, mode)].items())
+        lines.append(f"| D3Q{q} | {mode} | {vname[q]} | {ks} | {a:.1f} | "
                      f"{p.nodes * bytes_per_node(p) / (a * 1e-6) / 1e9:.0f} |")
     lines += ["", "HBM traffic per launch of every variant (IREBM, two "
               "counter runs, one counter each):", "",

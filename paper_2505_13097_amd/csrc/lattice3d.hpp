@@ -73,6 +73,10 @@ struct StepArgs3 {
   double wtau[3], wste[3]; // w/tau and w/Ste per weight class
   double inv_ste, tm, inv_delta, tol;
   StatSlot *slots;
+  // split step (quiet and full passes, front strip): tiles start at column
+  // x_off, columns from x_lim on are not updated; flags: one per work item
+  int32_t x_off, x_lim;
+  int32_t *flags;
 };
 
 template <int Q, typename S>
@@ -245,11 +249,13 @@ __device__ __forceinline__ int dirichlet_face3(const StepArgs3 &A, int x,
 // Dir_on_q, EEBM the wall enthalpy) shared by weight; Neumann deficit to
 // M0 of the mirror's pulls (eq. Neu_on_q) shared by weight; own
 // Omega_opp for anything left.  Returns the sum of the closed values.
-template <int Q, bool EEBM, bool NEU>
+// PLATEAU (the quiet pass): phi only where it is exactly 0 or 1, *near set
+// when the wall or the node lies nearer the band (see close_node)
+template <int Q, bool EEBM, bool NEU, bool PLATEAU = false>
 __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
                                          int z, double th, const double *om,
                                          double *q, uint32_t known,
-                                         double mirror) {
+                                         double mirror, int *near = nullptr) {
   // the bounce-back set first, then its values: compiled from the
   // in-place form (test, copy and mark in one loop), the D3Q7 step kernel
   // lost the copies on gfx950 while keeping the marks (the same source was
@@ -273,9 +279,17 @@ __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
   double D = 0.0;
   if (face >= 0) {
     const double TD = A.wall_T[face];
-    D = EEBM ? TD + (TD > A.tm ? A.inv_ste : 0.0)
-             : TD + (phi_only(TD, A.tm, A.inv_delta) -
-                     phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
+    if constexpr (PLATEAU && !EEBM) {
+      const double ud = (TD - A.tm) * A.inv_delta;
+      const double ut = (th - A.tm) * A.inv_delta;
+      if (!(fabs(ud) > 20.0 && fabs(ut) > 20.0)) *near = 1;
+      D = TD + ((ud > 20.0 ? 1.0 : 0.0) - (ut > 20.0 ? 1.0 : 0.0)) *
+                   A.inv_ste;
+    } else {
+      D = EEBM ? TD + (TD > A.tm ? A.inv_ste : 0.0)
+               : TD + (phi_only(TD, A.tm, A.inv_delta) -
+                       phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
+    }
     share = true;
   } else if (NEU) {
     int m[3];
@@ -309,8 +323,10 @@ __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
 }
 
 // The update of one node from its loads into v (storage type): the same
-// arithmetic as update_values (irebm_node.hpp) on the 3D lattice.
-template <int Q, typename S, int MODE, bool FAST>
+// arithmetic as update_values (irebm_node.hpp) on the 3D lattice.  QUIET:
+// the quiet pass's form (no Newton code): a node that is not quiet is
+// counted in st.solves and v is left meaningless.
+template <int Q, typename S, int MODE, bool FAST, bool QUIET = false>
 __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
                                         int z, const NodeLoad3<Q, S> &L,
                                         NodeStats &st, S v[Q]) {
@@ -326,10 +342,11 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
+  int near = 0;
   if (!FAST) {
     if (L.known != (1u << Q) - 1u)
-      st.flux_in += close3<Q, EEBM, NEU>(A, x, y, z, th, om, q, L.known,
-                                         L.mirror);
+      st.flux_in += close3<Q, EEBM, NEU, QUIET>(A, x, y, z, th, om, q,
+                                                L.known, L.mirror, &near);
     if (L.out) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
@@ -355,7 +372,7 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
     const double um = (m0 - A.tm) * A.inv_delta;
     const double d = th - m0;
     const double dx0 = m0 - (m0 - A.inv_ste);
-    if (u < -20.0 && um < -20.0 && th - d == m0 &&
+    if (u < -20.0 && um < -20.0 && th - d == m0 && !near &&
         (PLAIN || 2.0 * fabs(d) <= fabs(dx0))) {
       const bool one = fabs(d) <= A.tol;
       const int it = (one || A.max_it < 2) ? 1 : 2;
@@ -366,6 +383,12 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
         v[i] = (S)(A.a * q[i] + A.wtau[wclass3(i)] * m0);
       return;
     }
+  }
+  ++st.solves;
+  if constexpr (QUIET) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = (S)q[i];
+    return;
   }
   double pth, dpth;
   phi_dphi(th, A.tm, A.inv_delta, pth, dpth);
@@ -391,14 +414,14 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
   st.max_res = res > st.max_res ? res : st.max_res;
 }
 
-template <int Q, typename S, int MODE, bool FAST, bool NT>
+template <int Q, typename S, int MODE, bool FAST, bool NT, bool QUIET = false>
 __device__ __forceinline__ void update_store3(const StepArgs3 &A,
                                               S *__restrict__ dst, int x,
                                               int y, int z,
                                               const NodeLoad3<Q, S> &L,
                                               NodeStats &st) {
   S v[Q];
-  update3<Q, S, MODE, FAST>(A, x, y, z, L, st, v);
+  update3<Q, S, MODE, FAST, QUIET>(A, x, y, z, L, st, v);
   S *row = dst + ((int64_t)z * A.ny + y) * A.nx;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -414,20 +437,36 @@ namespace {
 // cz slices), XCD-contiguous item order; interior slices of interior
 // columns take the path with no bounds checks.  Per-item statistics slots
 // as in step_kernel.
-template <int Q, typename S, int NPT, int MODE, bool NT>
+//
+// Split step (variants ".../s", IREBM, a lattice heated through the x = 0
+// face): the Newton solve is rare (the front lies in the first cells of
+// every x row) but its code sets the register count of every wave and its
+// iterations hold whole 64-lane waves.  So the step is split by columns:
+// the front strip [0, A.x_lim) by this kernel as it stands (SPLIT 0) on a
+// stream of its own, and the rest (tiles from column A.x_off) by SPLIT 1,
+// built for quiet nodes only (no Newton code), beside it; an item of the
+// quiet pass with a node (in or near the band) that is not quiet adds no
+// statistics and sets its flag to 2, and SPLIT 2, after both, redoes the
+// flagged items with the full update and clears the flag of an item with
+// no solve left (the quiet pass skips items flagged 2).  Same per-node
+// arithmetic either way.
+template <int Q, typename S, int NPT, int MODE, bool NT, int SPLIT = 0>
 __global__ __launch_bounds__(256) void step3_kernel(StepArgs3 A) {
   const int b = (int)blockIdx.x;
   if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
   const int t = xcd_item(b, A.per_xcd, A.nitems, 0);
+  if (SPLIT > 0 &&
+      __builtin_amdgcn_readfirstlane(A.flags[t]) != (SPLIT == 1 ? 0 : 2))
+    return;
   const int tx = t % A.tiles_x;
   const int r = t / A.tiles_x;
   const int ty = r % A.tiles_y, tz = r / A.tiles_y;
   const int bx = (int)blockDim.x, by = (int)blockDim.y;
   const int TW = bx * NPT;
-  const int x0 = tx * TW, y0 = ty * by;
+  const int x0 = A.x_off + tx * TW, y0 = ty * by;
   const int z0 = tz * A.cz, z1 = min(z0 + A.cz, A.nz);
-  const bool fxy = x0 >= 1 && x0 + TW <= A.nx - 1 && y0 >= 1 &&
-                   y0 + by <= A.ny - 1;
+  const bool fxy = x0 >= 1 && x0 + TW <= A.nx - 1 && x0 + TW <= A.x_lim &&
+                   y0 >= 1 && y0 + by <= A.ny - 1;
   // a wave lies in one row of the column (bx is a multiple of 64)
   const int y = y0 + __builtin_amdgcn_readfirstlane((int)threadIdx.y);
   const S *src = (const S *)A.src;
@@ -449,23 +488,32 @@ __global__ __launch_bounds__(256) void step3_kernel(StepArgs3 A) {
                                  L[k]);
 #pragma unroll
       for (int k = 0; k < NPT; ++k)
-        update_store3<Q, S, MODE, true, NT>(
+        update_store3<Q, S, MODE, true, NT, SPLIT == 1>(
             B, dst, x0 + (int)threadIdx.x + k * bx, y, z, L[k], st);
     } else {
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
         const int x = x0 + (int)threadIdx.x + k * bx;
-        if (x < B.nx && y < B.ny) {
+        if (x < B.x_lim && y < B.ny) {
           NodeLoad3<Q, S> L;
           load3<Q, S, false, neumann_mode(MODE)>(B, src, x, y, z, L);
-          update_store3<Q, S, MODE, false, NT>(B, dst, x, y, z, L, st);
+          update_store3<Q, S, MODE, false, NT, SPLIT == 1>(B, dst, x, y, z,
+                                                          L, st);
         }
       }
     }
   }
-  StatSlot pre{};
-  if (threadIdx.x == 0 && threadIdx.y == 0) pre = A.slots[t];
-  block_stats_to_slot<false>(st, fast_all, pre, A.slots + t);
+  bool any = false;
+  if constexpr (SPLIT > 0) any = __syncthreads_or(st.solves > 0) != 0;
+  if (SPLIT != 1 || !any) {
+    StatSlot pre{};
+    if (threadIdx.x == 0 && threadIdx.y == 0) pre = A.slots[t];
+    block_stats_to_slot<false>(st, fast_all, pre, A.slots + t);
+  }
+  if (SPLIT > 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    if (SPLIT == 1 && any) A.flags[t] = 2;
+    if (SPLIT == 2 && !any) A.flags[t] = 0;
+  }
 }
 
 // equilibrium initial state (as init_kernel): IREBM Omega_i = w_i T, EEBM
@@ -504,8 +552,10 @@ namespace irebm {
 // A 3D variant: blocks of bx x by threads (bx a multiple of 64, at most
 // 256 threads: the kernel's launch bound), npt nodes per thread bx apart
 // along x, cz z slices per work item; nt: non-temporal stores.
+// split: the split step (see step3_kernel) on lattices heated through the
+// x = 0 face, IREBM; the plain kernel otherwise
 struct Variant3 {
-  int bx, by, npt, cz, nt;
+  int bx, by, npt, cz, nt, split;
 };
 
 inline const Variant3 *variants3(int *n) {
@@ -515,11 +565,17 @@ inline const Variant3 *variants3(int *n) {
       {64, 2, 2, 16, 1}, {64, 4, 2, 8, 1},  {128, 1, 2, 16, 1},
       {64, 2, 1, 8, 1},  {128, 1, 2, 4, 1},  {128, 1, 2, 8, 1},
       {128, 1, 2, 32, 1}, {128, 1, 2, 16, 0}, {64, 1, 2, 16, 1},
-      {64, 2, 2, 8, 1}};
+      {64, 2, 2, 8, 1},
+      {128, 1, 2, 4, 1, 1}, {128, 1, 2, 8, 1, 1}, {64, 4, 1, 8, 1, 1},
+      {64, 2, 2, 8, 1, 1},  {64, 4, 1, 16, 1, 1}};
   *n = (int)(sizeof(v) / sizeof(Variant3));
   return v;
 }
 constexpr int kDefaultVariant3D = 0;
+// split step: the front strip is the first kFront3Columns columns, run
+// with the tiling of variant kFront3Variant (64 x 4, 8 slices per item)
+constexpr int kFront3Columns = 64;
+constexpr int kFront3Variant = 0;
 
 inline int64_t tiles3_x(const Variant3 &v, int64_t nx) {
   return (nx + (int64_t)v.bx * v.npt - 1) / ((int64_t)v.bx * v.npt);
@@ -534,12 +590,14 @@ inline int64_t items3_for(const Variant3 &v, int64_t nx, int64_t ny,
                           int64_t nz) {
   return tiles3_x(v, nx) * tiles3_y(v, ny) * tiles3_z(v, nz);
 }
+// tiles over the columns [x_off, x_lim) (the whole row unless split)
 inline void set_tiling3(StepArgs3 *A, const Variant3 &v) {
+  const int64_t w = (int64_t)A->x_lim - A->x_off;
   A->cz = v.cz;
-  A->tiles_x = (int32_t)tiles3_x(v, A->nx);
+  A->tiles_x = (int32_t)tiles3_x(v, w);
   A->tiles_y = (int32_t)tiles3_y(v, A->ny);
   A->tiles_z = (int32_t)tiles3_z(v, A->nz);
-  A->nitems = (int32_t)items3_for(v, A->nx, A->ny, A->nz);
+  A->nitems = (int32_t)items3_for(v, w, A->ny, A->nz);
   A->per_xcd = (A->nitems + 7) / 8;
 }
 
@@ -547,6 +605,7 @@ inline void set_tiling3(StepArgs3 *A, const Variant3 &v) {
 // k_step3_<mode>.hip units)
 template <int MODE>
 hipError_t step3_launch_mode(int q, int storage, const StepArgs3 &A,
-                             const Variant3 &v, hipStream_t stream);
+                             const Variant3 &v, int split,
+                             hipStream_t stream);
 
 }  // namespace irebm

@@ -117,10 +117,20 @@ irebm::Layout irebm::layout_for(const lbm_stefan_params *p) {
   L.buf_bytes = align256((size_t)p->q * n * s);
   int nv;
   int64_t mt = 0;
+  int64_t mf = 0;
   if (p->dim == 3) {
     const Variant3 *v3 = variants3(&nv);
-    for (int i = 0; i < nv; ++i)
+    for (int i = 0; i < nv; ++i) {
       mt = std::max(mt, items3_for(v3[i], p->nx, p->ny, p->nz));
+      if (v3[i].split && p->nx > 2 * kFront3Columns) {
+        // quiet-pass items, then the front strip's
+        const int64_t nq = items3_for(v3[i], p->nx - kFront3Columns, p->ny,
+                                      p->nz);
+        mf = std::max(mf, nq);
+        mt = std::max(mt, nq + items3_for(v3[kFront3Variant], kFront3Columns,
+                                          p->ny, p->nz));
+      }
+    }
   } else {
     const Variant *v = variants(p->q, &nv);
     for (int i = 0; i < nv; ++i)
@@ -140,6 +150,8 @@ irebm::Layout irebm::layout_for(const lbm_stefan_params *p) {
   }
   L.off_slots = off;
   off += align256((size_t)mt * sizeof(StatSlot));
+  L.off_flags = off;
+  off += align256((size_t)mf * sizeof(int32_t));
   L.off_partials = off;
   off += align256((size_t)L.n_partials * 8);
   L.off_small = off;
@@ -222,6 +234,8 @@ void irebm::fill_args3(const lbm_stefan_params &p, StepArgs3 *A) {
   A->inv_delta = 1.0 / p.delta;
   A->tol = p.newton_tol;
   A->max_it = p.newton_max_it;
+  A->x_off = 0;
+  A->x_lim = (int32_t)p.nx;
 }
 
 void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
@@ -249,6 +263,61 @@ hipError_t irebm::launch_step2(const lbm_stefan_t *h, const void *src,
                       h->stream);
 }
 
+namespace {
+
+// the 3D split step applies: a split variant, IREBM without Neumann faces,
+// a Dirichlet x = 0 face off phi's lower plateau, and more columns than
+// twice the front strip
+bool split3_applies(const lbm_stefan_t *h, const Variant3 &v) {
+  const lbm_stefan_params &p = h->p;
+  return v.split && p.scheme == LBM_SCHEME_IREBM && !has_neumann(p) &&
+         p.bc[0] == LBM_BC_DIRICHLET &&
+         p.wall_T[0] >= p.t_m - 20.0 * p.delta &&
+         p.nx > 2 * kFront3Columns;
+}
+
+// one split step (see step3_kernel): the front strip on the side stream
+// beside the quiet pass, then the full pass over flagged items
+hipError_t split3_step(lbm_stefan_t *h, const StepArgs3 &A,
+                       const Variant3 &v, int mode) {
+  hipError_t e = hipSuccess;
+  if (!h->side) {
+    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  int nv;
+  const Variant3 &fv = variants3(&nv)[kFront3Variant];
+  StepArgs3 Aq = A, Af = A;
+  Aq.x_off = kFront3Columns;
+  Aq.flags = h->flags;
+  StepArgs3 T = Aq;
+  set_tiling3(&T, v);
+  if (h->flags_variant != h->variant) {
+    e = zero_async(h->flags, (size_t)T.nitems * sizeof(int32_t), h->stream);
+    if (e != hipSuccess) return e;
+    h->flags_variant = h->variant;
+  }
+  Af.x_lim = kFront3Columns;
+  Af.slots = A.slots + T.nitems;
+  e = hipEventRecord(h->fork, h->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork, 0);
+  if (e == hipSuccess)
+    e = step3_launch(mode, h->p.q, h->p.storage, Af, fv, h->side, 0);
+  if (e == hipSuccess) e = hipEventRecord(h->join, h->side);
+  if (e == hipSuccess)
+    e = step3_launch(mode, h->p.q, h->p.storage, Aq, v, h->stream, 1);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->join, 0);
+  if (e == hipSuccess)
+    e = step3_launch(mode, h->p.q, h->p.storage, Aq, v, h->stream, 2);
+  return e;
+}
+
+}  // namespace
+
 hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
   if (h->p.scheme == LBM_SCHEME_ILFBM) return ilfbm_advance(h, nsteps);
   if (h->p.dim == 3) {
@@ -258,6 +327,17 @@ hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
     int nv;
     const Variant3 &v = variants3(&nv)[h->variant];
     const int mode = mode_of(h->p);
+    if (split3_applies(h, v)) {
+      for (int64_t s = 0; s < nsteps; ++s) {
+        A.src = h->buf[h->cur];
+        A.dst = h->buf[h->cur ^ 1];
+        const hipError_t e = split3_step(h, A, v, mode);
+        if (e != hipSuccess) return e;
+        h->cur ^= 1;
+        h->steps++;
+      }
+      return hipSuccess;
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
       A.src = h->buf[h->cur];
       A.dst = h->buf[h->cur ^ 1];
@@ -447,6 +527,7 @@ int lbm_stefan_init(const lbm_stefan_params *p, const double *T0,
   h->cur = 0;
   h->slots = (StatSlot *)(ws + L.off_slots);
   h->max_items = L.max_items;
+  h->flags = (int32_t *)(ws + L.off_flags);
   h->partials = (double *)(ws + L.off_partials);
   h->small = (double *)(ws + L.off_small);
   h->adj = ws + L.off_adj;
@@ -613,8 +694,8 @@ const char *lbm_stefan_variant_name(int32_t q, int32_t storage,
     const Variant3 *v3 = variants3(&n);
     if (variant < 0 || variant >= n) return "";
     const Variant3 &w = v3[variant];
-    std::snprintf(buf, sizeof(buf), "%dx%d/npt%d/z%d%s", w.bx * w.npt, w.by,
-                  w.npt, w.cz, w.nt ? "/nt" : "");
+    std::snprintf(buf, sizeof(buf), "%dx%d/npt%d/z%d%s%s", w.bx * w.npt,
+                  w.by, w.npt, w.cz, w.nt ? "/nt" : "", w.split ? "/s" : "");
     return buf;
   }
   if (q != 3 && q != 5 && q != 9) return "";
@@ -729,7 +810,13 @@ int lbm_stefan_autotune(lbm_stefan_t *h, void *scratch, size_t scratch_bytes,
 int lbm_stefan_destroy(lbm_stefan_t *h) {
   if (!h) return LBM_STEFAN_OK;
   DeviceGuard g(h->device);
-  const hipError_t e = hipStreamSynchronize(h->stream);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (h->side) {
+    if (e == hipSuccess) e = hipStreamSynchronize(h->side);
+    (void)hipEventDestroy(h->fork);
+    (void)hipEventDestroy(h->join);
+    (void)hipStreamDestroy(h->side);
+  }
   delete h;
   if (e != hipSuccess)
     return fail(nullptr, LBM_STEFAN_EDEVICE, hipGetErrorString(e));

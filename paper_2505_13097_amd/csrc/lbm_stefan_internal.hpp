@@ -18,6 +18,7 @@ struct Layout {
   size_t off_buf[2] = {0, 0};
   size_t off_prof[4] = {0, 0, 0, 0};
   size_t off_slots = 0, off_partials = 0, off_small = 0, off_adj = 0;
+  size_t off_flags = 0; // 3D split step: one flag per quiet-pass item
   size_t off_lf = 0;    // ILFBM: three liquid fraction planes, the per-
                         // block pending values and the control block
   size_t total = 0;
@@ -44,6 +45,12 @@ struct lbm_stefan {
   bool has_prof[4] = {false, false, false, false};
   irebm::StatSlot *slots = nullptr;
   int64_t max_items = 0;
+  // 3D split step: work-item flags (valid for variant flags_variant), and
+  // the stream of the front strip with the events that fork and join it
+  int32_t *flags = nullptr;
+  int flags_variant = -1;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   double *partials = nullptr;
   double *small = nullptr;
   char *adj = nullptr;
@@ -154,7 +161,7 @@ IREBM_DECLARE_STEP1(kPlain | kNeumann);
 IREBM_DECLARE_STEP1(kEebm | kNeumann);
 #define IREBM_DECLARE_STEP3(M)                                             \
   extern template hipError_t step3_launch_mode<M>(                         \
-      int, int, const StepArgs3 &, const Variant3 &, hipStream_t)
+      int, int, const StepArgs3 &, const Variant3 &, int, hipStream_t)
 IREBM_DECLARE_STEP3(kSafeguarded);
 IREBM_DECLARE_STEP3(kPlain);
 IREBM_DECLARE_STEP3(kEebm);
@@ -244,22 +251,28 @@ inline hipError_t step2_launch(int mode, int q, int storage,
   return step2_launch_mode<kSafeguarded>(q, storage, A, v, two, stream);
 }
 
-// one step of one 3D lattice (3D variant v)
+// one step of one 3D lattice (3D variant v); split: 0 the plain kernel,
+// 1 and 2 the quiet and full passes of the split step (step3_kernel)
 inline hipError_t step3_launch(int mode, int q, int storage,
                                const StepArgs3 &A, const Variant3 &v,
-                               hipStream_t stream) {
+                               hipStream_t stream, int split = 0) {
   switch (mode) {
-    case kEebm: return step3_launch_mode<kEebm>(q, storage, A, v, stream);
-    case kPlain: return step3_launch_mode<kPlain>(q, storage, A, v, stream);
+    case kEebm:
+      return step3_launch_mode<kEebm>(q, storage, A, v, split, stream);
+    case kPlain:
+      return step3_launch_mode<kPlain>(q, storage, A, v, split, stream);
     case kEebm | kNeumann:
-      return step3_launch_mode<kEebm | kNeumann>(q, storage, A, v, stream);
+      return step3_launch_mode<kEebm | kNeumann>(q, storage, A, v, split,
+                                                 stream);
     case kPlain | kNeumann:
-      return step3_launch_mode<kPlain | kNeumann>(q, storage, A, v, stream);
+      return step3_launch_mode<kPlain | kNeumann>(q, storage, A, v, split,
+                                                  stream);
     case kSafeguarded | kNeumann:
       return step3_launch_mode<kSafeguarded | kNeumann>(q, storage, A, v,
-                                                        stream);
+                                                        split, stream);
     default:
-      return step3_launch_mode<kSafeguarded>(q, storage, A, v, stream);
+      return step3_launch_mode<kSafeguarded>(q, storage, A, v, split,
+                                             stream);
   }
 }
 

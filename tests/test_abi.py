@@ -289,7 +289,7 @@ def test_3d_variants_listed(L):
         names = variant_names(q, "f32")
         assert len(names) >= 8
         for n in names:
-            m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?", n)
+            m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?(/s)?", n)
             assert m, n
             tx, ty, npt, cz = (int(m.group(k)) for k in range(1, 5))
             bx = tx // npt

@@ -97,3 +97,17 @@ def test_batch_walls_from_trace_rows():
     w = bench.batch_walls(c, lambda n: n, {"front": "f", "quiet": "q",
                                            "full": "x"})
     assert w == [1.02, 1.01]
+
+
+def test_cube3d_kernel_names_by_variant():
+    """The trace names of a 3D step: a split variant runs the front strip
+    with variant 0's kernel, the quiet pass and the full pass (IREBM)."""
+    import bench
+    assert bench.cube3d_kernels(7, "64x4/npt1/z8/nt/s") == {
+        "front": "step3_kernel<7, float, 1, 0, true, 0>",
+        "quiet": "step3_kernel<7, float, 1, 0, true, 1>",
+        "full": "step3_kernel<7, float, 1, 0, true, 2>"}
+    assert bench.cube3d_kernels(7, "64x4/npt1/z8/nt/s", 2) == {
+        "step": "step3_kernel<7, float, 1, 2, true, 0>"}
+    assert bench.cube3d_kernels(19, "256x1/npt2/z4/nt") == {
+        "step": "step3_kernel<19, float, 2, 0, true, 0>"}

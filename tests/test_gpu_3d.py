@@ -406,3 +406,43 @@ def test_freezing_octant_isotherms_coincide_and_converge(q):
     d1 = abs(pos[201, "irebm"] - pos[101, "irebm"])
     d2 = abs(pos[401, "irebm"] - pos[201, "irebm"])
     assert d2 < d1
+
+
+def _split_cases(q, storage):
+    """Lattices wider than two front strips (the split step applies):
+    the cube heated at x = 0; heated at both x faces (the quiet pass meets
+    the front at x = 1 and flags those items); a field just below melting
+    everywhere (every item flagged)."""
+    base = synth.cavity_3d(n=200, ny=21, nz=13, q=q, storage=storage).with_(
+        ste=0.3, delta=0.03)
+    both = base.with_(wall_T=(1.0, 1.0) + tuple(base.wall_T[2:]),
+                      name=base.name + "_both_hot")
+    near = base.with_(T0=np.full(base.T0.shape, -2.0 * base.delta),
+                      name=base.name + "_near_band")
+    return [base, both, near]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("q", [7, 19])
+def test_split_step_equals_plain_step(q, storage):
+    """The split step (front strip on a second stream, quiet pass without
+    Newton code, full pass over flagged items) gives the plain kernel's
+    states bit for bit, and the same Newton counters; boundary fluxes to
+    rounding (summation order)."""
+    from paper_2505_13097_amd import variant_names
+    names = variant_names(q, storage)
+    split = [i for i, n in enumerate(names) if n.endswith("/s")]
+    assert split
+    for prob in _split_cases(q, storage):
+        ref = _gpu_run(prob, 7, variant=names.index(
+            names[split[0]][:-2]))
+        for v in split:
+            g = _gpu_run(prob, 7, variant=v)
+            assert np.array_equal(g["state"], ref["state"]), (prob.name, v)
+            for k in ("max_newton_it", "nonconverged"):
+                assert g["stats"][k] == ref["stats"][k], (prob.name, v, k)
+            for k in ("flux_in", "flux_out"):
+                a, b = g["stats"][k], ref["stats"][k]
+                assert abs(a - b) <= 1e-12 * max(1.0, abs(b)), (k, a, b)
+        print(f"{prob.name}: split variants {[names[v] for v in split]} "
+              f"equal the plain kernel", flush=True)

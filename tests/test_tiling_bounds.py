@@ -56,19 +56,24 @@ def _dirs2(q):
 # 3D: step3_kernel
 
 def _parse3(name):
-    m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?", name)
+    m = re.fullmatch(r"(\d+)x(\d+)/npt(\d+)/z(\d+)(/nt)?(/s)?", name)
     tw, by, npt, cz = (int(m.group(k)) for k in range(1, 5))
     return tw // npt, by, npt, cz
 
 
 def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
-            neu=(0, 0, 0, 0, 0, 0), bad_fast=False):
+            neu=(0, 0, 0, 0, 0, 0), bad_fast=False, x_off=0, x_lim=None,
+            out=None):
     """Every offset step3_kernel touches; returns the number checked.
-    bad_fast: widen the fast path's x guard by one (a planted mistake)."""
+    bad_fast: widen the fast path's x guard by one (a planted mistake).
+    x_off, x_lim: the split step's column range (tiles from x_off, no
+    update from x_lim on); out, if given, receives the stores per node
+    ([z][y][x])."""
     P = nx * ny * nz
     n = (nx, ny, nz)
     tw = bx * npt
-    tiles = (-(-nx // tw), -(-ny // by), -(-nz // cz))
+    x_lim = nx if x_lim is None else x_lim
+    tiles = (-(-(x_lim - x_off) // tw), -(-ny // by), -(-nz // cz))
     nitems = tiles[0] * tiles[1] * tiles[2]
     per_xcd = (nitems + 7) // 8
     dirs = _dirs3(q)
@@ -96,20 +101,22 @@ def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
         tx = t % tiles[0]
         r = t // tiles[0]
         ty, tz = r % tiles[1], r // tiles[1]
-        x0, y0 = tx * tw, ty * by
+        x0, y0 = x_off + tx * tw, ty * by
         z0, z1 = tz * cz, min(tz * cz + cz, nz)
         fxy = (x0 >= 1 and x0 + tw <= nx - (0 if bad_fast else 1) and
-               y0 >= 1 and y0 + by <= ny - 1)
+               x0 + tw <= x_lim and y0 >= 1 and y0 + by <= ny - 1)
         for z in range(z0, z1):
             fast = fxy and 1 <= z <= nz - 2
             for k in range(npt):
                 x = (x0 + txx + k * bx).ravel()
                 y = (y0 + tyy).ravel()
                 if not fast:
-                    keep = (x < nx) & (y < ny)
+                    keep = (x < x_lim) & (y < ny)
                     x, y = x[keep], y[keep]
                 if x.size == 0:
                     continue
+                if out is not None:
+                    np.add.at(out, (np.full_like(x, z), y, x), 1)
                 c = (x, y, np.full_like(x, z))
                 # neighbours: unclamped on the fast path, wrapped or
                 # clamped elsewhere (neighbours3)
@@ -169,6 +176,33 @@ def test_3d_kernel_offsets_inside_planes(names, q):
             # the freezing octant's Neumann faces (x+, y+, z+)
             replay3(q, *shape, bx, by, npt, cz, (0, 0, 0),
                     (0, 1, 0, 1, 0, 1))
+
+
+# the 3D split step: front strip of FRONT3_COLUMNS columns with the tiling
+# of FRONT3 (kFront3Columns, kFront3Variant of lattice3d.hpp)
+FRONT3_COLUMNS = 64
+FRONT3 = (64, 4, 1, 8)
+
+
+@pytest.mark.parametrize("q", [7, 19])
+def test_3d_split_step_stores_every_node_once(names, q):
+    """Split variants: the front strip (columns below 64) and the quiet
+    and full passes (tiles from column 64) store every node once, every
+    access inside the planes."""
+    split = [n for n in names[q] if n.endswith("/s")]
+    assert split
+    for name in split:
+        bx, by, npt, cz = _parse3(name)
+        for shape in [(129, 6, 10), (200, 5, 7), (130, 3, 3), (320, 9, 4)]:
+            nx, ny, nz = shape
+            assert nx > 2 * FRONT3_COLUMNS
+            for per in ((0, 0, 0), (0, 1, 1)):
+                out = np.zeros((nz, ny, nx), dtype=int)
+                replay3(q, *shape, *FRONT3, per, x_lim=FRONT3_COLUMNS,
+                        out=out)
+                replay3(q, *shape, bx, by, npt, cz, per,
+                        x_off=FRONT3_COLUMNS, out=out)
+                assert np.all(out == 1), (name, shape)
 
 
 def test_3d_replay_detects_an_overrun():
