@@ -135,16 +135,39 @@ CASES = [
 ]
 
 
+def _fp32_spread(prob, steps, o, seed=31):
+    """How far one FP32 rounding step apart can move this case: the oracle
+    rerun from T0 perturbed by one FP32 unit in the last place (random
+    sign per node), the largest change of l, T and the state planes after
+    the same steps.  The GPU and the oracle store the same FP32 state but
+    may round a value on either side of a tie-near boundary, which is a
+    perturbation of that size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T0 = np.asarray(prob.T0, dtype=np.float64)
+    ulp = np.spacing(np.abs(T0).astype(np.float32)).astype(np.float64)
+    Tp = T0 + rng.choice([-1.0, 1.0], size=T0.shape) * ulp
+    p = _oracle_run(prob.with_(T0=Tp), steps)
+    return max(float(np.max(np.abs(p[k] - o[k]))) for k in ("l", "T",
+                                                            "state"))
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_ilfbm_against_oracle(case, storage):
     name, make, steps = CASES[case]
-    if name.endswith("_capped") and storage == "f32":
-        pytest.skip("non-converged iterates amplify the FP32 rounding of "
-                    "the stored state (growth 4/3 per D2Q5 iteration)")
     prob = make(storage).with_(name=f"ilfbm_{name}_{storage}")
-    _compare(prob, _gpu_run(prob, steps), _oracle_run(prob, steps),
-             TOL64 if storage == "f64" else TOL32)
+    o = _oracle_run(prob, steps)
+    tol = TOL64 if storage == "f64" else TOL32
+    if name.endswith("_capped") and storage == "f32":
+        # the capped inner loop amplifies FP32-level differences (growth
+        # up to 4/3 per D2Q5 iteration): the bar is ten times what one
+        # FP32 unit of T0 grows to in the oracle itself, and never below
+        # the FP32 bar
+        sp = _fp32_spread(prob, steps, o)
+        tol = max(tol, 10.0 * sp)
+        print(f"{prob.name}: oracle spread from one FP32 ulp of T0 "
+              f"{sp:.3e}, bar {tol:.3e}", flush=True)
+    _compare(prob, _gpu_run(prob, steps), o, tol)
 
 
 def test_ilfbm_energy_balance():
