@@ -1059,6 +1059,84 @@ def summarize_sq(run, args, db, short):
     print(f"wrote profiles/{fn}")
 
 
+RDREQ_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_128B_sum",
+                  "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_32B_sum")
+
+
+def summarize_rdreq(run):
+    """profiles/ summary of the read requests by size (run/pmc_rdreq, bench
+    --traffic-sweep): bytes read from HBM as 128 x (128-byte requests) +
+    64 x (64-byte) + 32 x (32-byte), per dispatch of each kernel, beside
+    FETCH_SIZE of the same kernels (run/pmc_fetch) and the 1 GiB copy.
+    This counts the bytes with no calibration; FETCH_SIZE, whose formula
+    counts a 128-byte request as 64 bytes, is scaled by the copy."""
+    import collections
+    import sqlite3
+
+    def db(sub):
+        d = os.path.join(run, sub)
+        f = [x for x in os.listdir(d) if x.endswith("_results.db")]
+        return sqlite3.connect(os.path.join(d, f[0]))
+
+    def short(n):
+        n = n.replace("(anonymous namespace)::", "").replace("irebm::", "")
+        return n.split("(")[0].replace("void ", "")
+
+    per = collections.OrderedDict()
+    for d, k, cn, v in db("pmc_rdreq").execute(
+            "select dispatch_id, kernel_name, counter_name, value from "
+            "counters_collection order by dispatch_id"):
+        e = per.setdefault((d, short(k)), {})
+        e[cn] = e.get(cn, 0.0) + v
+    fetch = collections.defaultdict(list)
+    for k, v in db("pmc_fetch").execute(
+            "select kernel_name, value from counters_collection where "
+            "counter_name='FETCH_SIZE' order by dispatch_id"):
+        fetch[short(k)].append(v)
+    by = collections.OrderedDict()
+    for (d, k), c in per.items():
+        b = (128 * c.get(RDREQ_COUNTERS[1], 0) + 64 * c.get(RDREQ_COUNTERS[2], 0)
+             + 32 * c.get(RDREQ_COUNTERS[3], 0))
+        other = c.get(RDREQ_COUNTERS[0], 0) - sum(
+            c.get(x, 0) for x in RDREQ_COUNTERS[1:])
+        by.setdefault(k, []).append((b, c.get(RDREQ_COUNTERS[1], 0) /
+                                     max(c.get(RDREQ_COUNTERS[0], 0), 1),
+                                     other))
+    copy_kib = max(fetch["__amd_rocclr_copyBuffer"])
+    lines = ["# HBM read bytes by request size — the counter sweep of the "
+             "2D step kernels and the batched form", "",
+             "    rocprofv3 --pmc " + " ".join(RDREQ_COUNTERS) +
+             " -d gpurun_out/pmc_rdreq -o rdreq -- python bench.py "
+             "--traffic-sweep --batch-steps 4 --batch-variant 35 "
+             "--batch-bpc 0", "",
+             "Bytes read = 128 x (128-byte requests) + 64 x (64-byte) + 32 "
+             "x (32-byte), no calibration; beside it FETCH_SIZE (same "
+             "sweep, its own run) scaled by the 1 GiB copy "
+             f"(x{1048576.0 / copy_kib:.4f}).", "",
+             "| kernel | dispatches | GB read by request size | 128-byte "
+             "share | other requests | FETCH_SIZE x scale, GB | ratio |",
+             "|---|---|---|---|---|---|---|"]
+    for k, rs in by.items():
+        if not (k.startswith("step") or k.startswith("batch") or
+                "copyBuffer" in k):
+            continue
+        b = sum(r[0] for r in rs) / len(rs)
+        if b < 1e6:
+            continue
+        share = sum(r[1] for r in rs) / len(rs)
+        oth = sum(r[2] for r in rs) / len(rs)
+        fs = fetch.get(k)
+        fb = (sum(fs) / len(fs)) * 1024 * 1048576.0 / copy_kib if fs else None
+        lines.append(f"| {k} | {len(rs)} | {b / 1e9:.4f} | {share:.4f} | "
+                     f"{oth:.0f} | " + (f"{fb / 1e9:.4f} | {fb / b:.4f} |"
+                                        if fb else "— | — |"))
+    lines.append("")
+    fn = "hbm_read_requests_by_size_cavity8192_batch512.md"
+    with open(os.path.join(ROOT, "profiles", fn), "w") as f:
+        f.write("\n".join(lines))
+    print(f"wrote profiles/{fn}")
+
+
 def cpu_baseline(prob, steps=1, threads=None):
     """The oracle, as it stands, on `steps` steps of the same lattice from
     the same initial state: once on one thread, then on every core this
@@ -1210,6 +1288,9 @@ def main():
     ap.add_argument("--traffic-sweep", action="store_true",
                     help="counter runs: 1 GiB copy, every variant for "
                          f"{SWEEP_STEPS} steps, the batched form; no timing")
+    ap.add_argument("--summarize-rdreq", metavar="RUN_DIR",
+                    help="write the read-requests-by-size summary from "
+                         "RUN_DIR/pmc_rdreq and RUN_DIR/pmc_fetch (CPU only)")
     ap.add_argument("--summarize-profiles", metavar="RUN_DIR",
                     help="write profiles/ from the rocprofv3 output of a run "
                          "(CPU only; --variant, --batch-variant, --batch-bpc, "
@@ -1217,6 +1298,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args)
+        return
+    if args.summarize_rdreq:
+        summarize_rdreq(args.summarize_rdreq)
         return
     if args.summarize_profiles3:
         summarize_profiles3(args.summarize_profiles3, args)
