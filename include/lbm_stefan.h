@@ -402,7 +402,9 @@ int lbm_stefan_adjoint_buffers(lbm_stefan_t *h, double **abar0,
  * recomputation); the reverse sweep recomputes each segment from its
  * checkpoint, then runs its reverse steps.
  *   lbm_stefan_tape_bytes: device bytes of a tape for (p, nsteps,
- *     interval): (ceil(nsteps/interval) + 1 + interval) states.
+ *     interval): (ceil(nsteps/interval) + 1 + 2 interval) states (the
+ *     checkpoints, then two segments: the reverse sweep of one segment
+ *     overlaps the recomputation of the next on a second stream).
  *   lbm_stefan_forward_tape: advance the handle nsteps from its current
  *     state (the state the gradient is taken at: normally the initial state
  *     built by lbm_stefan_init), storing checkpoints in `tape` (device,

@@ -579,7 +579,9 @@ int lbm_stefan_tape_bytes(const lbm_stefan_params *p, int64_t nsteps,
     return fail(nullptr, LBM_STEFAN_EINVAL, "nsteps and interval must be >= 1");
   const int64_t I = std::min(interval, nsteps);
   const int64_t K = (nsteps + I - 1) / I;
-  *bytes = (size_t)(K + 1 + I) * align256(state_bytes(*p));
+  // checkpoints 0..K, then two segments' recomputed states (the reverse
+  // sweep of one segment overlaps the recomputation of the next)
+  *bytes = (size_t)(K + 1 + 2 * I) * align256(state_bytes(*p));
   return LBM_STEFAN_OK;
 }
 
@@ -629,15 +631,37 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
   const int64_t N = h->tape_steps, I = h->tape_interval;
   const int64_t K = (N + I - 1) / I;
   const size_t sb = state_bytes(h->p), slot = align256(sb);
-  if (bytes < (size_t)(K + 1 + I) * slot)
+  if (bytes < (size_t)(K + 1 + 2 * I) * slot)
     return fail(h, LBM_STEFAN_EINVAL, "tape too small");
   DeviceGuard g(h->device);
+  HIPCHK(h, handle_side(h));
   const AdjLayout L = adj_layout(&h->p);
   double *ab[2] = {(double *)(h->adj + L.abar0), (double *)(h->adj + L.abar1)};
   char *t = (char *)tape;
-  char *seg = t + (K + 1) * slot;
+  char *seg[2] = {t + (K + 1) * slot, t + (K + 1 + I) * slot};
   HIPCHK(h, reset_async(h));
   HIPCHK(h, front_vjp_async(h, t + K * slot, dL_dfront, ab[0]));
+  // Segment k's states are recomputed from checkpoint k into seg[k & 1] on
+  // the handle's second stream, while this stream runs the reverse sweep
+  // of segment k + 1 from seg[(k + 1) & 1]: both are chains of small,
+  // latency-bound launches, so they overlap.  Event `join` (recorded on the
+  // second stream) marks a segment recomputed, event `fork` (recorded
+  // here) a sweep done, after which its buffer may be overwritten.
+  auto states_of = [&](int64_t k) -> const void * {
+    return (const void *)(t + k * slot);
+  };
+  auto recompute = [&](int64_t k) -> hipError_t {
+    const int64_t n = std::min(I, N - k * I);
+    char *sg = seg[k & 1];
+    hipError_t e = hipStreamWaitEvent(h->side, h->fork, 0);
+    for (int64_t j = 1; j < n && e == hipSuccess; ++j)
+      e = launch_step(h, j == 1 ? states_of(k) : sg + (j - 1) * slot,
+                      sg + j * slot, h->side);
+    if (e == hipSuccess) e = hipEventRecord(h->join, h->side);
+    return e;
+  };
+  HIPCHK(h, hipEventRecord(h->fork, h->stream));
+  HIPCHK(h, recompute(K - 1));
   // reverse steps N-1 .. 0: the last one node-local only (its Omega'bar is
   // the front seed), then gather-of-(n+1) fused with local-of-n, then the
   // final gather; qbar/Tbar alternate between two buffers
@@ -646,10 +670,10 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
     const int64_t n = std::min(I, N - k * I);
     // states of segment k: the checkpoint itself, then recomputed ones
     auto state = [&](int64_t j) -> const void * {
-      return j == 0 ? (const void *)(t + k * slot) : (const void *)(seg + j * slot);
+      return j == 0 ? states_of(k) : (const void *)(seg[k & 1] + j * slot);
     };
-    for (int64_t j = 1; j < n; ++j)
-      HIPCHK(h, launch_step(h, state(j - 1), seg + j * slot));
+    HIPCHK(h, hipStreamWaitEvent(h->stream, h->join, 0));
+    if (k >= 1) HIPCHK(h, recompute(k - 1));
     for (int64_t j = n - 1; j >= 0; --j) {
       if (c < 0) {
         HIPCHK(h, local_async(h, state(j), ab[0], 0));
@@ -659,6 +683,7 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
         c ^= 1;
       }
     }
+    HIPCHK(h, hipEventRecord(h->fork, h->stream));
   }
   HIPCHK(h, pull_async(h, c, ab[1]));
   HIPCHK(h, init_term_async(h, ab[1]));

@@ -280,15 +280,8 @@ bool split3_applies(const lbm_stefan_t *h, const Variant3 &v) {
 // beside the quiet pass, then the full pass over flagged items
 hipError_t split3_step(lbm_stefan_t *h, const StepArgs3 &A,
                        const Variant3 &v, int mode) {
-  hipError_t e = hipSuccess;
-  if (!h->side) {
-    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-    if (e == hipSuccess)
-      e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
-    if (e == hipSuccess)
-      e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-  }
+  hipError_t e = irebm::handle_side(h);
+  if (e != hipSuccess) return e;
   int nv;
   const Variant3 &fv = variants3(&nv)[kFront3Variant];
   StepArgs3 Aq = A, Af = A;
@@ -317,6 +310,18 @@ hipError_t split3_step(lbm_stefan_t *h, const StepArgs3 &A,
 }
 
 }  // namespace
+
+hipError_t irebm::handle_side(lbm_stefan_t *h) {
+  hipError_t e = hipSuccess;
+  if (!h->side) {
+    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+      e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+  }
+  return e;
+}
 
 hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
   if (h->p.scheme == LBM_SCHEME_ILFBM) return ilfbm_advance(h, nsteps);
@@ -389,7 +394,7 @@ hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
 }
 
 hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
-                              void *dst) {
+                              void *dst, hipStream_t stream) {
   StepArgs A;
   fill_step_args(h, &A);
   A.src = src;
@@ -402,7 +407,7 @@ hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
                         : vt[h->variant].res ? kDefaultVariant1D
                                              : h->variant];
   return step_launch(mode_of(h->p), h->p.q, h->p.storage, A, v,
-                     v.rev && (h->steps & 1), h->stream);
+                     v.rev && (h->steps & 1), stream ? stream : h->stream);
 }
 
 namespace {

@@ -81,7 +81,11 @@ void set_global_error(const std::string &msg);
 void fill_args(const lbm_stefan_params &p, double *const prof[4],
                StepArgs *A);
 void fill_step_args(const lbm_stefan_t *h, StepArgs *A);
-hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst);
+hipError_t launch_step(const lbm_stefan_t *h, const void *src, void *dst,
+                       hipStream_t stream = nullptr);
+// the handle's second stream (split steps, the reverse sweep's
+// recomputation) and its two events, created on first use
+hipError_t handle_side(lbm_stefan_t *h);
 // StepArgs3 of a 3D lattice from its params; src, dst and the tile fields
 // are left zero
 void fill_args3(const lbm_stefan_params &p, StepArgs3 *A);
