@@ -109,6 +109,7 @@ struct StepArgs {
   int32_t group;             // tile rows per work item (one block each)
   int32_t nitems, per_xcd;   // work items; items per XCD chunk
   int32_t reverse;      // sweep the tiles in reverse order
+  int32_t front_first;  // each XCD takes the x = 0 tiles of its chunk first
   int32_t periodic_x, periodic_y;
   int32_t scheme;       // SCHEME_IREBM or SCHEME_EEBM
   int32_t neu;          // bit k: wall k (x-, x+, y-, y+) is a Neumann wall

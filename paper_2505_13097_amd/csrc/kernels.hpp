@@ -173,6 +173,26 @@ __device__ __forceinline__ int xcd_item(int b, int per_xcd, int nitems,
   return reverse ? nitems - 1 - t : t;
 }
 
+// The same chunks, each XCD taking the x = 0 tiles of its chunk first (the
+// items t with t mod tiles_x = 0, where a heated x = 0 wall puts the
+// melting front), then the others in order: the tiles whose Newton solves
+// make them the longest start first, and their latency hides under the
+// rest of the chunk instead of ending it.  A permutation of the items
+// within each chunk (the caller has checked that block b has an item).
+__device__ __forceinline__ int xcd_item_front_first(int b, int per_xcd,
+                                                    int nitems, int tiles_x) {
+  const int c0 = (b & 7) * per_xcd, j = b >> 3;
+  const int c1 = min(c0 + per_xcd, nitems);
+  const int base = (c0 / tiles_x) * tiles_x, r0 = c0 - base;
+  const int f0 = r0 == 0 ? c0 : base + tiles_x;   // first x = 0 item
+  const int nf = f0 < c1 ? (c1 - 1 - f0) / tiles_x + 1 : 0;
+  if (j < nf) return f0 + j * tiles_x;
+  // the (j - nf)-th item with x > 0: items with x > 0 counted from base
+  const int w = tiles_x - 1;
+  const int rk = (r0 == 0 ? 0 : r0 - 1) + (j - nf);
+  return base + (rk / w) * tiles_x + rk % w + 1;
+}
+
 namespace {
 
 
@@ -181,7 +201,9 @@ template <int Q, typename S, int NPT, int MODE, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs A) {
   const int b = blockIdx.x;
   if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
-  const int t = xcd_item(b, A.per_xcd, A.nitems, A.reverse);
+  const int t = A.front_first && !A.reverse
+                    ? xcd_item_front_first(b, A.per_xcd, A.nitems, A.tiles_x)
+                    : xcd_item(b, A.per_xcd, A.nitems, A.reverse);
   step_item<Q, S, NPT, MODE, NT>(A, to_global((const S *)A.src),
                                   to_global((S *)A.dst), t, A.slots + t);
 }

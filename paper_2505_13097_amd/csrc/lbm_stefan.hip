@@ -406,6 +406,8 @@ hipError_t irebm::launch_step(const lbm_stefan_t *h, const void *src,
   const Variant &v = vt[vt[h->variant].tb    ? kDefaultVariant2D
                         : vt[h->variant].res ? kDefaultVariant1D
                                              : h->variant];
+  // a Dirichlet x = 0 wall is where the workloads heat: its tiles first
+  A.front_first = h->p.bc[0] == LBM_BC_DIRICHLET;
   return step_launch(mode_of(h->p), h->p.q, h->p.storage, A, v,
                      v.rev && (h->steps & 1), stream ? stream : h->stream);
 }
