@@ -77,6 +77,7 @@ struct StepArgs3 {
   // x_off, columns from x_lim on are not updated; flags: one per work item
   int32_t x_off, x_lim;
   int32_t *flags;
+  int32_t front_first;  // each XCD takes the x = 0 tiles of its chunk first
 };
 
 template <int Q, typename S>
@@ -454,7 +455,9 @@ template <int Q, typename S, int NPT, int MODE, bool NT, int SPLIT = 0>
 __global__ __launch_bounds__(256) void step3_kernel(StepArgs3 A) {
   const int b = (int)blockIdx.x;
   if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
-  const int t = xcd_item(b, A.per_xcd, A.nitems, 0);
+  const int t = A.front_first
+                    ? xcd_item_front_first(b, A.per_xcd, A.nitems, A.tiles_x)
+                    : xcd_item(b, A.per_xcd, A.nitems, 0);
   if (SPLIT > 0 &&
       __builtin_amdgcn_readfirstlane(A.flags[t]) != (SPLIT == 1 ? 0 : 2))
     return;

@@ -343,6 +343,8 @@ hipError_t irebm::advance(lbm_stefan_t *h, int64_t nsteps) {
       }
       return hipSuccess;
     }
+    // a Dirichlet x = 0 face is where the workloads heat: its tiles first
+    A.front_first = h->p.bc[0] == LBM_BC_DIRICHLET;
     for (int64_t s = 0; s < nsteps; ++s) {
       A.src = h->buf[h->cur];
       A.dst = h->buf[h->cur ^ 1];
