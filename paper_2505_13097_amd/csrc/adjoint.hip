@@ -650,6 +650,9 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
   auto states_of = [&](int64_t k) -> const void * {
     return (const void *)(t + k * slot);
   };
+  // (a tape of every state, interval 1, has nothing to recompute: no
+  // second stream then)
+  const bool overlap = I > 1;
   auto recompute = [&](int64_t k) -> hipError_t {
     const int64_t n = std::min(I, N - k * I);
     char *sg = seg[k & 1];
@@ -660,8 +663,10 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
     if (e == hipSuccess) e = hipEventRecord(h->join, h->side);
     return e;
   };
-  HIPCHK(h, hipEventRecord(h->fork, h->stream));
-  HIPCHK(h, recompute(K - 1));
+  if (overlap) {
+    HIPCHK(h, hipEventRecord(h->fork, h->stream));
+    HIPCHK(h, recompute(K - 1));
+  }
   // reverse steps N-1 .. 0: the last one node-local only (its Omega'bar is
   // the front seed), then gather-of-(n+1) fused with local-of-n, then the
   // final gather; qbar/Tbar alternate between two buffers
@@ -672,8 +677,10 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
     auto state = [&](int64_t j) -> const void * {
       return j == 0 ? states_of(k) : (const void *)(seg[k & 1] + j * slot);
     };
-    HIPCHK(h, hipStreamWaitEvent(h->stream, h->join, 0));
-    if (k >= 1) HIPCHK(h, recompute(k - 1));
+    if (overlap) {
+      HIPCHK(h, hipStreamWaitEvent(h->stream, h->join, 0));
+      if (k >= 1) HIPCHK(h, recompute(k - 1));
+    }
     for (int64_t j = n - 1; j >= 0; --j) {
       if (c < 0) {
         HIPCHK(h, local_async(h, state(j), ab[0], 0));
@@ -683,7 +690,7 @@ int lbm_stefan_backward_tape(lbm_stefan_t *h, const double *dL_dfront,
         c ^= 1;
       }
     }
-    HIPCHK(h, hipEventRecord(h->fork, h->stream));
+    if (overlap) HIPCHK(h, hipEventRecord(h->fork, h->stream));
   }
   HIPCHK(h, pull_async(h, c, ab[1]));
   HIPCHK(h, init_term_async(h, ab[1]));
