@@ -205,7 +205,7 @@ def test_batch_two_step_variants_equal_single_steps(name):
 
 
 
-def _split_mix(storage):
+def _split_mix(storage, q=5):
     """Instances for the split two-step schedule: heated at x = 0 (front
     strip), heated at x = 1 only (its front in the last strip: the quiet
     pass flags those items), heated at both walls, a field just below
@@ -213,7 +213,7 @@ def _split_mix(storage):
     lattice, and sizes from one strip (64) to three (300)."""
     probs = synth.batch_table(count=6, seed=23, sizes=[64, 192, 300],
                               storage=storage, nsteps=40)
-    p = probs
+    p = [x.with_(q=q) for x in probs]
     p[1] = p[1].with_(wall_T=(-0.5, 1.0, 0.0, 0.0))
     p[2] = p[2].with_(wall_T=(1.0, 1.0, 0.0, 0.0))
     p[3] = p[3].with_(T0=np.full((p[3].ny, p[3].nx), -2.0 * p[3].delta))
@@ -222,6 +222,30 @@ def _split_mix(storage):
     ny5 = p[5].nx // 2 + 9
     p[5] = p[5].with_(ny=ny5, T0=p[5].T0[:ny5])
     return p
+
+
+def test_split_two_step_schedule_d2q9():
+    """The split schedule on D2Q9 instances (diagonal pulls in the front
+    kernel's LDS rows and in the quiet pass), FP64 and FP32: states equal
+    one-step launches bit for bit."""
+    from paper_2505_13097_amd import StefanBatch, variant_names
+    for storage in ("f64", "f32"):
+        probs = _split_mix(storage, q=9)
+        v = variant_names(9, storage).index("128x2/t2s/r96/nt")
+        a = StefanBatch(probs)
+        ref = StefanBatch(probs)
+        a.set_schedule(v, 0, 4)
+        for n in (4, 5, 2):
+            a.step(n)
+            ref.step(n)
+            for k in range(len(probs)):
+                assert np.array_equal(a.temperature(k), ref.temperature(k)), \
+                    (storage, n, k)
+        for sa, sr in zip(a.stats(), ref.stats()):
+            assert sa["max_newton_it"] == sr["max_newton_it"]
+            assert sa["nonconverged"] == sr["nonconverged"]
+        a.close()
+        ref.close()
 
 
 @pytest.mark.parametrize("name", ["128x2/t2s/r16/nt", "128x4/t2s/r32/nt",
