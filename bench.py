@@ -120,8 +120,8 @@ def measured_traffic3(workload, variant_name):
 DEFAULT_VARIANTS = {
     "cavity": "128x4/t2/r32/nt",
     "cavity_eebm": "256x2/t2/r32/nt",
-    "planar": "256x4/npt4",
-    "planar_eebm": "256x4/npt4",
+    "planar": "128x2/npt2",
+    "planar_eebm": "128x2/npt2",
     "stefan1d": "resident2048",
     "batched": "128x2/t2s/r96/nt",
     "adjoint": "256x1/npt1",
