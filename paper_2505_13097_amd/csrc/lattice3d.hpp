@@ -78,6 +78,9 @@ struct StepArgs3 {
   int32_t x_off, x_lim;
   int32_t *flags;
   int32_t front_first;  // each XCD takes the x = 0 tiles of its chunk first
+  // rows off the y and z faces take the in-register x-face closure
+  // (close_xface3): both x faces Dirichlet or bounce-back, nx >= 3
+  int32_t xrow;
 };
 
 template <int Q, typename S>
@@ -215,6 +218,38 @@ __device__ __forceinline__ void load3(const StepArgs3 &A,
   }
 }
 
+// Loads of a node of a row off the y and z faces (the xrow path): as
+// load3<FAST>, with the x sources clamped into the row so that an x-face
+// node's unknown directions read a lattice node (their values are replaced
+// by close_xface3).  OWN false (EEBM, whose update reads the own
+// populations only for the face fluxes): own populations past the rest one
+// loaded on face nodes only.
+template <int Q, typename S, bool OWN>
+__device__ __forceinline__ void load_row3(const StepArgs3 &A,
+                                          const S *__restrict__ src, int x,
+                                          int y, int z, bool face,
+                                          NodeLoad3<Q, S> &L) {
+  const int64_t P = A.plane;
+  auto row = [&](int ey, int ez) {
+    return src + ((int64_t)(z - ez) * A.ny + (y - ey)) * A.nx;
+  };
+  const S *r0 = row(0, 0);
+  L.own[0] = r0[(uint32_t)x];
+#pragma unroll
+  for (int j = 1; j < Q; ++j)
+    L.own[j] = (OWN || face) ? (r0 + j * P)[(uint32_t)x] : (S)0;
+  L.pull[0] = L.own[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int ex = e3(i, 0), ey = e3(i, 1), ez = e3(i, 2);
+    const int sx = ex == 0 ? x : min(max(x - ex, 0), A.nx - 1);
+    L.pull[i] = (row(ey, ez) + i * P)[(uint32_t)sx];
+  }
+  L.known = (1u << Q) - 1u;
+  L.out = 0u;
+  L.mirror = 0.0;
+}
+
 // does the source of unknown direction i of node (x, y, z) lie beyond
 // bounce-back faces only?  (a periodic axis wraps and is never left)
 __device__ __forceinline__ bool leaves_by_bounceback3(const StepArgs3 &A,
@@ -245,6 +280,28 @@ __device__ __forceinline__ int dirichlet_face3(const StepArgs3 &A, int x,
   return -1;
 }
 
+// The zeroth moment a Dirichlet closure gives a node at wall temperature
+// TD: IREBM eq. Dir_on_q (TD plus the latent term's jump between the wall
+// and the node's temperature th), EEBM the wall enthalpy.  PLATEAU (the
+// quiet pass): phi only where it is exactly 0 or 1, *near set when the
+// wall or the node lies nearer the band (see close_node)
+template <bool EEBM, bool PLATEAU>
+__device__ __forceinline__ double dirichlet_deficit3(const StepArgs3 &A,
+                                                     double TD, double th,
+                                                     int *near) {
+  if constexpr (PLATEAU && !EEBM) {
+    const double ud = (TD - A.tm) * A.inv_delta;
+    const double ut = (th - A.tm) * A.inv_delta;
+    if (!(fabs(ud) > 20.0 && fabs(ut) > 20.0)) *near = 1;
+    return TD + ((ud > 20.0 ? 1.0 : 0.0) - (ut > 20.0 ? 1.0 : 0.0)) *
+                    A.inv_ste;
+  } else {
+    return EEBM ? TD + (TD > A.tm ? A.inv_ste : 0.0)
+                : TD + (phi_only(TD, A.tm, A.inv_delta) -
+                        phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
+  }
+}
+
 // Closure of the unknown pulled populations (Section 4.2), as close_node:
 // bounce-back from a known opposite; Dirichlet deficit (IREBM eq.
 // Dir_on_q, EEBM the wall enthalpy) shared by weight; Neumann deficit to
@@ -252,9 +309,9 @@ __device__ __forceinline__ int dirichlet_face3(const StepArgs3 &A, int x,
 // Omega_opp for anything left.  Returns the sum of the closed values.
 // PLATEAU (the quiet pass): phi only where it is exactly 0 or 1, *near set
 // when the wall or the node lies nearer the band (see close_node)
-template <int Q, bool EEBM, bool NEU, bool PLATEAU = false>
+template <int Q, bool EEBM, bool NEU, bool PLATEAU = false, typename S>
 __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
-                                         int z, double th, const double *om,
+                                         int z, double th, const S *om,
                                          double *q, uint32_t known,
                                          double mirror, int *near = nullptr) {
   // the bounce-back set first, then its values: compiled from the
@@ -279,18 +336,7 @@ __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
   bool share = false;
   double D = 0.0;
   if (face >= 0) {
-    const double TD = A.wall_T[face];
-    if constexpr (PLATEAU && !EEBM) {
-      const double ud = (TD - A.tm) * A.inv_delta;
-      const double ut = (th - A.tm) * A.inv_delta;
-      if (!(fabs(ud) > 20.0 && fabs(ut) > 20.0)) *near = 1;
-      D = TD + ((ud > 20.0 ? 1.0 : 0.0) - (ut > 20.0 ? 1.0 : 0.0)) *
-                   A.inv_ste;
-    } else {
-      D = EEBM ? TD + (TD > A.tm ? A.inv_ste : 0.0)
-               : TD + (phi_only(TD, A.tm, A.inv_delta) -
-                       phi_only(th, A.tm, A.inv_delta)) * A.inv_ste;
-    }
+    D = dirichlet_deficit3<EEBM, PLATEAU>(A, A.wall_T[face], th, near);
     share = true;
   } else if (NEU) {
     int m[3];
@@ -317,7 +363,44 @@ __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
 #pragma unroll
   for (int i = 1; i < Q; ++i)
     if (!(set >> i & 1u)) {
-      q[i] = om[opp3(i)];
+      q[i] = (double)om[opp3(i)];
+      fill += q[i];
+    }
+  return fill;
+}
+
+// close3 for a node on an x face (side 0: x = 0, whose unknown directions
+// have e_x = +1; side 1: x = nx - 1, e_x = -1) of a row off the y and z
+// faces, the x faces being Dirichlet or bounce-back (xrow): there close3
+// copies every unknown direction from its known opposite (bounce-back) or
+// shares the Dirichlet deficit by weight, and this does the same
+// operations in the same order, from the direction masks of the face.
+template <int Q, bool EEBM, bool PLATEAU>
+__device__ __forceinline__ double close_xface3(const StepArgs3 &A, int side,
+                                               double th, double *q,
+                                               int *near) {
+  const int eu = side == 0 ? 1 : -1;
+  double fill = 0.0;
+  if (A.bc[side] == BC_BOUNCEBACK) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      if (e3(i, 0) == eu) {
+        q[i] = q[opp3(i)];
+        fill += q[i];
+      }
+    return fill;
+  }
+  double D = dirichlet_deficit3<EEBM, PLATEAU>(A, A.wall_T[side], th, near);
+  double wu = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (e3(i, 0) != eu) D -= q[i];
+    else wu += wt3<Q>(i);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    if (e3(i, 0) == eu) {
+      q[i] = D * (wt3<Q>(i) / wu);
       fill += q[i];
     }
   return fill;
@@ -327,31 +410,43 @@ __device__ __forceinline__ double close3(const StepArgs3 &A, int x, int y,
 // arithmetic as update_values (irebm_node.hpp) on the 3D lattice.  QUIET:
 // the quiet pass's form (no Newton code): a node that is not quiet is
 // counted in st.solves and v is left meaningless.
-template <int Q, typename S, int MODE, bool FAST, bool QUIET = false>
+template <int Q, typename S, int MODE, bool FAST, bool QUIET = false,
+          bool XROW = false>
 __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
                                         int z, const NodeLoad3<Q, S> &L,
-                                        NodeStats &st, S v[Q]) {
+                                        NodeStats &st, S v[Q],
+                                        int side = -1) {
   constexpr bool PLAIN = base_mode(MODE) == kPlain;
   constexpr bool EEBM = base_mode(MODE) == kEebm;
   constexpr bool NEU = neumann_mode(MODE);
-  double om[Q], q[Q];
+  // own populations stay in storage precision until used (fewer
+  // registers than an FP64 copy held across the closure)
+  double q[Q];
   double th = 0.0;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    om[j] = (double)L.own[j];
-    th += om[j];
-  }
+  for (int j = 0; j < Q; ++j) th += (double)L.own[j];
 #pragma unroll
   for (int i = 0; i < Q; ++i) q[i] = (double)L.pull[i];
   int near = 0;
   if (!FAST) {
     if (L.known != (1u << Q) - 1u)
-      st.flux_in += close3<Q, EEBM, NEU, QUIET>(A, x, y, z, th, om, q,
+      st.flux_in += close3<Q, EEBM, NEU, QUIET>(A, x, y, z, th, L.own, q,
                                                 L.known, L.mirror, &near);
     if (L.out) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
-        if (L.out >> i & 1u) st.flux_out += om[i];
+        if (L.out >> i & 1u) st.flux_out += (double)L.own[i];
+    }
+  }
+  if constexpr (XROW) {
+    // an x-face node of an interior row (side >= 0): its closure, and the
+    // populations leaving through the face
+    if (side >= 0) {
+      st.flux_in += close_xface3<Q, EEBM, QUIET>(A, side, th, q, &near);
+      const int eo = side == 0 ? -1 : 1;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (e3(i, 0) == eo) st.flux_out += (double)L.own[i];
     }
   }
   double m0 = 0.0;
@@ -415,14 +510,15 @@ __device__ __forceinline__ void update3(const StepArgs3 &A, int x, int y,
   st.max_res = res > st.max_res ? res : st.max_res;
 }
 
-template <int Q, typename S, int MODE, bool FAST, bool NT, bool QUIET = false>
+template <int Q, typename S, int MODE, bool FAST, bool NT, bool QUIET = false,
+          bool XROW = false>
 __device__ __forceinline__ void update_store3(const StepArgs3 &A,
                                               S *__restrict__ dst, int x,
                                               int y, int z,
                                               const NodeLoad3<Q, S> &L,
-                                              NodeStats &st) {
+                                              NodeStats &st, int side = -1) {
   S v[Q];
-  update3<Q, S, MODE, FAST, QUIET>(A, x, y, z, L, st, v);
+  update3<Q, S, MODE, FAST, QUIET, XROW>(A, x, y, z, L, st, v, side);
   S *row = dst + ((int64_t)z * A.ny + y) * A.nx;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -432,11 +528,21 @@ __device__ __forceinline__ void update_store3(const StepArgs3 &A,
   }
 }
 
+// waves per SIMD the 3D step asks of the compiler: the occupancy its
+// register count gives without the interior-row path, which would
+// otherwise cost D3Q19 a wave
+constexpr int step3_waves(int q, int bytes, int npt) {
+  return q == 19 ? (bytes == 4 || npt == 1 ? 3 : 2) : (npt == 1 ? 5 : 4);
+}
+
 namespace {
 
 // One step of a 3D lattice: one block per work item (a column chunk of
 // cz slices), XCD-contiguous item order; interior slices of interior
-// columns take the path with no bounds checks.  Per-item statistics slots
+// columns take the path with no bounds checks, and so do the rows off the
+// y and z faces of the other columns when both x faces are Dirichlet or
+// bounce-back (xrow), an x-face node closed in registers; the rest take
+// the bounds-checked path, a node at a time.  Per-item statistics slots
 // as in step_kernel.
 //
 // Split step (variants ".../s", IREBM, a lattice heated through the x = 0
@@ -452,7 +558,9 @@ namespace {
 // no solve left (the quiet pass skips items flagged 2).  Same per-node
 // arithmetic either way.
 template <int Q, typename S, int NPT, int MODE, bool NT, int SPLIT = 0>
-__global__ __launch_bounds__(256) void step3_kernel(StepArgs3 A) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(step3_waves(Q, sizeof(S), NPT))))
+void step3_kernel(StepArgs3 A) {
   const int b = (int)blockIdx.x;
   if ((b & 7) * A.per_xcd + (b >> 3) >= A.nitems) return;
   const int t = A.front_first
@@ -493,6 +601,27 @@ __global__ __launch_bounds__(256) void step3_kernel(StepArgs3 A) {
       for (int k = 0; k < NPT; ++k)
         update_store3<Q, S, MODE, true, NT, SPLIT == 1>(
             B, dst, x0 + (int)threadIdx.x + k * bx, y, z, L[k], st);
+    } else if (B.xrow && z >= 1 && z <= B.nz - 2 && y >= 1 &&
+               y <= B.ny - 2) {
+      // a row off the y and z faces in a tile holding an x face or a
+      // ragged end: both nodes' loads in flight as above, an x-face node
+      // closed in registers (close_xface3), lanes past the row idle
+      constexpr bool OWN = base_mode(MODE) != kEebm;
+      NodeLoad3<Q, S> L[NPT];
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int x = x0 + (int)threadIdx.x + k * bx;
+        load_row3<Q, S, OWN>(B, src, min(x, B.nx - 1), y, z,
+                             x == 0 || x == B.nx - 1, L[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        const int x = x0 + (int)threadIdx.x + k * bx;
+        if (x < B.nx && x < B.x_lim)
+          update_store3<Q, S, MODE, true, NT, SPLIT == 1, true>(
+              B, dst, x, y, z, L[k], st,
+              x == 0 ? 0 : (x == B.nx - 1 ? 1 : -1));
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {

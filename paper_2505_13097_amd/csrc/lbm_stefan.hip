@@ -236,6 +236,10 @@ void irebm::fill_args3(const lbm_stefan_params &p, StepArgs3 *A) {
   A->max_it = p.newton_max_it;
   A->x_off = 0;
   A->x_lim = (int32_t)p.nx;
+  auto closes_in_rows = [](int32_t b) {
+    return b == BC_DIRICHLET || b == BC_BOUNCEBACK;
+  };
+  A->xrow = p.nx >= 3 && closes_in_rows(bc[0]) && closes_in_rows(bc[1]);
 }
 
 void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {

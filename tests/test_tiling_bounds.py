@@ -63,12 +63,16 @@ def _parse3(name):
 
 def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
             neu=(0, 0, 0, 0, 0, 0), bad_fast=False, x_off=0, x_lim=None,
-            out=None):
+            out=None, bad_row=False):
     """Every offset step3_kernel touches; returns the number checked.
     bad_fast: widen the fast path's x guard by one (a planted mistake).
     x_off, x_lim: the split step's column range (tiles from x_off, no
     update from x_lim on); out, if given, receives the stores per node
-    ([z][y][x])."""
+    ([z][y][x]).  The interior-row path (xrow: both x faces Dirichlet or
+    bounce-back, so neither periodic nor Neumann here) is replayed for the
+    rows off the y and z faces of tiles off the fast path; bad_row: its x
+    sources left unclamped (a planted mistake)."""
+    xrow = nx >= 3 and not periodic[0] and not neu[0] and not neu[1]
     P = nx * ny * nz
     n = (nx, ny, nz)
     tw = bx * npt
@@ -110,6 +114,26 @@ def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
             for k in range(npt):
                 x = (x0 + txx + k * bx).ravel()
                 y = (y0 + tyy).ravel()
+                if not fast and xrow and 1 <= z <= nz - 2:
+                    # rows off the y and z faces (a wave is one row): every
+                    # lane loads, at its column clamped into the row, the x
+                    # sources clamped too; lanes inside the row and before
+                    # x_lim store
+                    row = (y >= 1) & (y <= ny - 2)
+                    xc = np.minimum(x[row], nx - 1)
+                    yr = y[row]
+                    if xc.size:
+                        st = x[row] < min(nx, x_lim)
+                        if out is not None:
+                            np.add.at(out, (np.full(st.sum(), z), yr[st],
+                                            x[row][st]), 1)
+                        for i, e in enumerate(dirs):
+                            check(i, xc, yr, np.full_like(xc, z))
+                            sx = xc - e[0]
+                            if e[0] != 0 and not bad_row:
+                                sx = np.clip(sx, 0, nx - 1)
+                            check(i, sx, yr - e[1], np.full_like(xc, z - e[2]))
+                    x, y = x[~row], y[~row]
                 if not fast:
                     keep = (x < x_lim) & (y < ny)
                     x, y = x[keep], y[keep]
@@ -203,6 +227,35 @@ def test_3d_split_step_stores_every_node_once(names, q):
                 replay3(q, *shape, bx, by, npt, cz, per,
                         x_off=FRONT3_COLUMNS, out=out)
                 assert np.all(out == 1), (name, shape)
+
+
+@pytest.mark.parametrize("q", [7, 19])
+def test_3d_step_stores_every_node_once(names, q):
+    """The plain 3D step of every variant: the fast path, the interior-row
+    path (rows off the y and z faces of tiles holding an x face or a ragged
+    end) and the bounds-checked path together store every node once, with
+    the interior-row path on (Dirichlet or bounce-back x faces) and off
+    (a periodic x axis, a Neumann x face)."""
+    for name in names[q]:
+        if name.endswith("/s"):
+            continue
+        bx, by, npt, cz = _parse3(name)
+        for shape in SHAPES3 + [(300, 7, 6)]:
+            for per, neu in (((0, 0, 0), (0,) * 6), ((0, 1, 1), (0,) * 6),
+                             ((1, 0, 0), (0,) * 6),
+                             ((0, 0, 0), (0, 1, 0, 0, 1, 0))):
+                out = np.zeros(shape[::-1], dtype=int)
+                replay3(q, *shape, bx, by, npt, cz, per, neu, out=out)
+                assert np.all(out == 1), (name, shape, per, neu)
+
+
+def test_3d_replay_detects_an_unclamped_row_source():
+    """The replay itself: with the interior-row path's x sources left
+    unclamped, the x = 0 node's +x pull reads column -1, and the replay
+    says so."""
+    replay3(7, 130, 6, 6, 128, 1, 2, 4)
+    with pytest.raises(AssertionError):
+        replay3(7, 130, 6, 6, 128, 1, 2, 4, bad_row=True)
 
 
 def test_3d_replay_detects_an_overrun():
