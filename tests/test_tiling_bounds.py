@@ -205,7 +205,7 @@ def test_3d_kernel_offsets_inside_planes(names, q):
 # the 3D split step: front strip of FRONT3_COLUMNS columns with the tiling
 # of FRONT3 (kFront3Columns, kFront3Variant of lattice3d.hpp)
 FRONT3_COLUMNS = 64
-FRONT3 = (64, 4, 1, 8)
+FRONT3 = (64, 4, 1, 32)
 
 
 @pytest.mark.parametrize("q", [7, 19])
