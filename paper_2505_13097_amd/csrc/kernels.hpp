@@ -446,7 +446,7 @@ __device__ __forceinline__ void merge_stats(NodeStats &st,
 // rows of a front segment: R + 2 rows of step n + 1 fill 256 threads
 // evenly (4 rows of 64 columns per pass)
 template <typename S>
-constexpr int front_rows() { return sizeof(S) == 4 ? 14 : 6; }
+constexpr int front_rows() { return sizeof(S) == 4 ? 10 : 6; }
 
 // Two steps of segment `seg` (front_rows<S>() rows) of an instance's front
 // strip, one block of 256 threads: step n + 1 of the segment's rows and of

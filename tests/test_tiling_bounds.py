@@ -417,7 +417,7 @@ def replay_t2(q, nx, ny, win, by, rows, px, py, two=True, ring_rows=None,
 # FRONT_ROWS[storage bytes] rows (kFrontColumns of host_util.hpp,
 # front_rows of kernels.hpp)
 FRONT_COLUMNS = 60
-FRONT_ROWS = {4: 14, 8: 6}
+FRONT_ROWS = {4: 10, 8: 6}
 
 
 def front_cols(nx):
