@@ -170,6 +170,11 @@ typedef struct lbm_stefan_params {
 } lbm_stefan_params;
 
 #define LBM_FLAG_ADJOINT 1 /* reserve workspace for the reverse mode */
+/* 3D lattices: every node of a tile that holds an x face takes the
+ * bounds-checked path, a node at a time, instead of the interior loads
+ * with the x-face closure in registers (both give the same states bit for
+ * bit; the flag exists to check that, and costs speed) */
+#define LBM_FLAG_CHECKED_FACES 2
 
 typedef struct lbm_stefan_stats {
   int64_t steps;         /* steps taken since init */

@@ -18,7 +18,7 @@ STORE_F64, STORE_F32 = 0, 1
 NEWTON_SAFEGUARDED, NEWTON_PLAIN = 0, 1
 FRONT_LIQUID_INTEGRAL, FRONT_ZERO_CROSSING = 0, 1
 FIELD_T, FIELD_STATE, FIELD_LIQUID = 0, 1, 2
-FLAG_ADJOINT = 1
+FLAG_ADJOINT, FLAG_CHECKED_FACES = 1, 2
 SCHEME_IREBM, SCHEME_EEBM, SCHEME_ILFBM = 0, 1, 2
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)

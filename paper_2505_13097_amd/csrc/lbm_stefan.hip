@@ -239,7 +239,8 @@ void irebm::fill_args3(const lbm_stefan_params &p, StepArgs3 *A) {
   auto closes_in_rows = [](int32_t b) {
     return b == BC_DIRICHLET || b == BC_BOUNCEBACK;
   };
-  A->xrow = p.nx >= 3 && closes_in_rows(bc[0]) && closes_in_rows(bc[1]);
+  A->xrow = p.nx >= 3 && closes_in_rows(bc[0]) && closes_in_rows(bc[1]) &&
+            !(p.flags & LBM_FLAG_CHECKED_FACES);
 }
 
 void irebm::fill_step_args(const lbm_stefan_t *h, StepArgs *A) {
