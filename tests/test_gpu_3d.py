@@ -456,11 +456,15 @@ def test_row_closure_equals_checked_path(storage):
     tile down the bounds-checked path instead.  Both give the same states
     bit for bit and the same Newton counters, fluxes to rounding
     (summation order), on every variant of every lattice above, IREBM and
-    EEBM.  The lattices with a periodic or Neumann x face never take the
-    row path: for them the check is that the flag changes nothing."""
+    EEBM, and on the split step's lattices (wider than two front strips:
+    its front strip, quiet and full passes take the row path too).  The
+    lattices with a periodic or Neumann x face never take the row path:
+    for them the check is that the flag changes nothing."""
     from paper_2505_13097_amd import Stefan, variant_names
     from paper_2505_13097_amd import _lib as C
-    for name, make, steps in CASES:
+    wide = [(p.name, (lambda s, sc, p=p: p.with_(scheme=sc)), 12)
+            for q in (7, 19) for p in _split_cases(q, storage)]
+    for name, make, steps in CASES + wide:
         for scheme in ("irebm", "eebm"):
             prob = make(storage, scheme)
             names = variant_names(prob.q, storage)
