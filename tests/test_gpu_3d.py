@@ -265,19 +265,28 @@ def _window3(prob, o, w):
                       bc_z=tuple(bc[4:]), T0=T0, dx=prob.dx)
 
 
+@pytest.mark.parametrize("variant", ["bench", "autotune"])
 @pytest.mark.parametrize("q,storage,tol", [(19, "f32", TOL32),
                                            (19, "f64", TOL64),
                                            (7, "f32", TOL32)])
-def test_full_size_cube_sampled_windows(q, storage, tol):
-    """The 512^3 cube of the bench in the variant its autotuner picks,
-    from a field in the melting band: after 6 steps, 14 windows of 18^3
-    nodes (corners, edges, faces, interior) rerun by the oracle; nodes at
-    least 6 cells from a window's artificial faces must match."""
+def test_full_size_cube_sampled_windows(q, storage, tol, variant):
+    """The 512^3 cube of the bench in the variant the bench times (D3Q19
+    256x1/npt2/z4/nt, D3Q7 the split step 64x4/npt1/z8/nt/s) and in the
+    variant its autotuner picks, from a field in the melting band: after 6
+    steps, 14 windows of 18^3 nodes (corners, edges, faces, interior) rerun
+    by the oracle; nodes at least 6 cells from a window's artificial faces
+    must match."""
+    import bench
     from paper_2505_13097_amd import Stefan, variant_names
     steps, w, n = 6, 18, 512
     prob = _mushy3(synth.cavity_3d(n=n, q=q, storage=storage))
     g = Stefan(prob)
-    v, _ = g.autotune(steps=3)
+    if variant == "bench":
+        v = variant_names(q, storage).index(
+            bench.DEFAULT_VARIANTS[f"cube3d_{q}"])
+        g.set_variant(v)
+    else:
+        v, _ = g.autotune(steps=3)
     st = g.step(steps, stats=True)
     T = g.temperature()
     g.close()

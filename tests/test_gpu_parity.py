@@ -280,13 +280,19 @@ def _windows(nx, ny, w, h, seed, count, avoid_y_edges=False):
 
 
 def _full_size_variants(q):
-    """the default one-step variant, every two-step variant (the bench
-    times one of them: 128x4/t2/r32/nt unless asked to autotune) and the
-    autotuner's pick"""
+    """the default one-step variant, every two-step variant, the variant
+    the bench times on this lattice (unless asked to autotune: the cavity's
+    128x4/t2/r32/nt, the planar step's 128x2/npt2) and the autotuner's
+    pick"""
+    import bench
     from paper_2505_13097_amd import variant_names
     names = variant_names(q, "f32")
-    return [-1] + [i for i, n in enumerate(names) if "/t2/" in n] + \
-        ["autotune"]
+    out = [-1] + [i for i, n in enumerate(names) if "/t2/" in n]
+    timed = names.index(bench.DEFAULT_VARIANTS["cavity" if q == 9
+                                               else "planar"])
+    if timed not in out:
+        out.append(timed)
+    return out + ["autotune"]
 
 
 @pytest.mark.parametrize("variant", _full_size_variants(9))
