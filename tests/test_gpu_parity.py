@@ -325,6 +325,26 @@ def test_full_size_planar_sampled_windows(storage, tol, variant):
                                       avoid_y_edges=True), tol, variant)
 
 
+@pytest.mark.parametrize("storage,tol", [("f32", TOL32), ("f64", TOL64)])
+def test_cavity_as_benched_hundred_step_windows(storage, tol):
+    """The roofline-graded cavity exactly as the bench runs it (8192 x 8192
+    D2Q9, its initial state and walls, the bench's two-step variant) for a
+    100-step window, then 8 windows rerun by the oracle: the hot wall where
+    the front forms (both corners and two stretches of the wall), the cold
+    corner and wall, the top wall and the interior.  Each window keeps the
+    nodes more than 100 cells from its artificial sides."""
+    import bench
+    from paper_2505_13097_amd import variant_names
+    prob = synth.cavity_2d(storage=storage).with_(
+        name=f"cavity8192_as_benched_{storage}")
+    v = variant_names(9, storage).index(bench.DEFAULT_VARIANTS["cavity"])
+    n, e, s_ = prob.nx, 164, 232
+    wins = [(0, 0, e, e), (0, n - e, e, e), (0, n // 2 - s_ // 2, e, s_),
+            (0, n // 3, e, s_), (n - e, 0, e, e), (n - e, n // 2, e, s_),
+            (n // 2, n - e, s_, e), (n // 2 - s_ // 2, n // 2 - s_ // 2, s_, s_)]
+    _check_windows(prob, 100, wins, tol, v)
+
+
 def test_full_size_planar_properties():
     """The 2048 x 2048 D2Q5 planar workload at full length (10k steps):
     energy balance through the walls, bounded temperatures, Newton within
