@@ -61,6 +61,10 @@ def _parse3(name):
     return tw // npt, by, npt, cz
 
 
+# the 3D item order's bands of rows (kBand3Rows of lattice3d.hpp)
+BAND3_ROWS = 128
+
+
 def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
             neu=(0, 0, 0, 0, 0, 0), bad_fast=False, x_off=0, x_lim=None,
             out=None, bad_row=False):
@@ -104,7 +108,12 @@ def replay3(q, nx, ny, nz, bx, by, npt, cz, periodic=(0, 0, 0),
         seen[t] += 1                      # the block's statistics slot
         tx = t % tiles[0]
         r = t // tiles[0]
-        ty, tz = r % tiles[1], r // tiles[1]
+        # bands of tile rows, each through all its z chunks (set_tiling3)
+        band = max(1, BAND3_ROWS // by)
+        per = band * tiles[2]
+        bi, rr = r // per, r % per
+        bw = min(band, tiles[1] - bi * band)
+        ty, tz = bi * band + rr % bw, rr // bw
         x0, y0 = x_off + tx * tw, ty * by
         z0, z1 = tz * cz, min(tz * cz + cz, nz)
         fxy = (x0 >= 1 and x0 + tw <= nx - (0 if bad_fast else 1) and
@@ -240,7 +249,8 @@ def test_3d_step_stores_every_node_once(names, q):
         if name.endswith("/s"):
             continue
         bx, by, npt, cz = _parse3(name)
-        for shape in SHAPES3 + [(300, 7, 6)]:
+        # (70, 300, 6): several bands of rows and a ragged last band
+        for shape in SHAPES3 + [(300, 7, 6), (70, 300, 6)]:
             for per, neu in (((0, 0, 0), (0,) * 6), ((0, 1, 1), (0,) * 6),
                              ((1, 0, 0), (0,) * 6),
                              ((0, 0, 0), (0, 1, 0, 0, 1, 0))):
